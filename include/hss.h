@@ -1,0 +1,249 @@
+/*
+ * hss.h -- C ABI of the MI355X (gfx950) randomized HSS library.
+ *
+ * Randomized compression of a dense n x n matrix into Hierarchically
+ * Semi-Separable form, HSS matrix-vector products and the ULV-like
+ * factorization and solve, following Rouet, Li, Ghysels, Napov,
+ * "A distributed-memory package for dense Hierarchically Semi-Separable
+ * matrix computations using randomization" (arXiv 1503.05464).
+ *
+ * Conventions shared by every entry point
+ *  - Matrices are row-major: element (i, j) of a matrix with leading
+ *    dimension ld is at p[i*ld + j].
+ *  - Pointers named A, x, b, R, S, Y, ... are DEVICE pointers unless the
+ *    comment says "host".  Caller-owned buffers are only read or written
+ *    during the call (stream-ordered calls: until the work on `stream`
+ *    completes) and never retained.
+ *  - `stream` is a hipStream_t passed as void*; NULL is the default stream.
+ *  - No C++ exception crosses the ABI.  Every call returns an hss_status;
+ *    on an error, hss_last_error() returns a thread-local message.
+ *  - A handle owns all of its device memory until hss_destroy().  Calls on
+ *    one handle must not overlap; different handles are independent.
+ */
+#ifndef HSS_H
+#define HSS_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct hss_handle_s* hss_handle;
+
+typedef enum {
+  HSS_OK = 0,
+  HSS_NOT_CONVERGED = 1,  /* d reached d_max: the handle is complete and usable,
+                             but some ID was accepted above the fail rule */
+  HSS_ERR_ARG = -1,       /* invalid argument (sizes, pointers, tree) */
+  HSS_ERR_ALLOC = -2,     /* device allocation failed */
+  HSS_ERR_HIP = -3,       /* a HIP runtime call or kernel launch failed */
+  HSS_ERR_STATE = -4,     /* call out of order (e.g. solve before factor) */
+  HSS_ERR_SINGULAR = -5   /* a zero pivot in the ULV factors or the root LU */
+} hss_status;
+
+typedef enum { HSS_F64 = 0, HSS_F32 = 1 } hss_dtype; /* storage type of A */
+
+/* Precision of the sampling products S^r = A R^r, S^c = A^T R^c. */
+typedef enum {
+  HSS_SAMPLE_F64 = 0  /* FP64 MFMA; an FP32 A is widened exactly */
+} hss_sample_prec;
+
+/* Node states of the adaptive sampling (Sec. 3.3). */
+enum { HSS_UNTOUCHED = 0, HSS_PARTIALLY_COMPRESSED = 1, HSS_COMPRESSED = 2 };
+
+/*
+ * Compression parameters (Sec. 2.2, Sec. 3.3).
+ *  rtol      relative ID threshold eps: the pivoted QR of a node stops at
+ *            the first pivot with |R_ii| <= rtol * |R_11|.
+ *  d0, dd    initial number of random vectors and the growth step.
+ *  d_max     cap on d; if a pass still fails at d_max, one more pass accepts
+ *            every ID and hss_compress returns HSS_NOT_CONVERGED.
+ *  p_margin  an ID of rank k fails when k > d - p_margin and k < m (m = rows
+ *            of the node's local sample); default 10, the oversampling of
+ *            Alg. 1 (d = r + 10).
+ *  seed      Philox4x64-10 key; R^r and R^c entry (i, j) is a function of
+ *            (seed, stream, i, j) only, so appended columns never depend on
+ *            the growth history.
+ *  leaf_size tree built by bisection when no tree is given.
+ *  R_user_r, R_user_c  optional DEVICE n x d_max row-major random matrices
+ *            (leading dimension ld_R_user) used instead of Philox; for tests.
+ */
+typedef struct {
+  double rtol;
+  int d0;
+  int dd;
+  int d_max;
+  int p_margin;
+  unsigned long long seed;
+  int leaf_size;
+  int sample_prec;            /* hss_sample_prec */
+  const double* R_user_r;
+  const double* R_user_c;
+  long long ld_R_user;
+} hss_opts;
+
+/* Fills *o with rtol 1e-6, d0 64, dd 32, d_max 4096, p_margin 10, seed 0,
+ * leaf_size 64, FP64 sampling, no user R. */
+void hss_default_opts(hss_opts* o);
+
+/*
+ * Binary cluster tree (Sec. 2.1): host arrays of n_nodes entries; node 0 is
+ * the root with interval [0, n); node t owns [lo[t], hi[t]); left/right are
+ * child numbers or -1 for a leaf; the children split the parent interval
+ * into two adjacent parts (left first).  Copied by the callee.
+ */
+typedef struct {
+  int n_nodes;
+  const int* lo;
+  const int* hi;
+  const int* left;
+  const int* right;
+} hss_tree;
+
+/*
+ * Randomized compression of the dense matrix A (Alg. 1) with adaptive
+ * sampling (Alg. 5, late notification, run level by level over heights).
+ *  A       DEVICE, n x n row-major, leading dimension lda >= n, storage type
+ *          dtype (hss_dtype).  Read only; may be freed when the call returns
+ *          (D and B are copied into the handle).
+ *  tree    NULL: bisection tree of [0, n) with opts->leaf_size (intervals of
+ *          m > leaf_size split into floor(m/2), ceil(m/2)).
+ *  opts    NULL: hss_default_opts.
+ *  *out    receives a new handle (also on HSS_NOT_CONVERGED).
+ * Host-synchronous: returns when the handle is complete.  All device work is
+ * issued on `stream`.
+ */
+hss_status hss_compress(const void* A, int dtype, long long n, long long lda,
+                        const hss_tree* tree, const hss_opts* opts, void* stream,
+                        hss_handle* out);
+
+/*
+ * b = A_HSS x (Alg. 2) for nrhs columns.  x: DEVICE n x nrhs (ldx >= nrhs),
+ * b: DEVICE n x nrhs (ldb >= nrhs), must not overlap x.  Stream-ordered.
+ */
+hss_status hss_matvec(hss_handle h, int nrhs, const double* x, long long ldx,
+                      double* b, long long ldb, void* stream);
+
+/* ULV-like factorization of the HSS form (Alg. 3); root LU with partial
+ * pivoting.  Host-synchronous. */
+hss_status hss_factor(hss_handle h, void* stream);
+
+/* Solve A_HSS x = b after hss_factor (Alg. 4).  b, x: DEVICE n x nrhs;
+ * HSS_ERR_STATE before hss_factor.  Stream-ordered. */
+hss_status hss_solve(hss_handle h, int nrhs, const double* b, long long ldb,
+                     double* x, long long ldx, void* stream);
+
+/* Summary of a compression.  Times are wall-clock milliseconds measured
+ * with HIP events on the compression stream. */
+typedef struct {
+  long long n;
+  int n_nodes;
+  int height;
+  int d_final;
+  int passes;
+  int converged;
+  int max_rank;
+  long long generator_bytes;   /* D + B + E + index arrays */
+  double sample_flops;         /* 4 n^2 d_final */
+  double t_total_ms;
+  double t_sample_ms;          /* random matrices + sampling products */
+  double t_levels_ms;          /* local samples, IDs, updates */
+  double t_id_ms;              /* pivoted QR + triangular solves */
+} hss_stats_t;
+
+hss_status hss_stats(hss_handle h, hss_stats_t* st);
+
+/* Per-node ranks and local-sample row counts (host arrays of n_nodes
+ * entries; any may be NULL).  Root entries are 0. */
+hss_status hss_ranks(hss_handle h, int* kr, int* kc, int* mr, int* mc);
+
+/*
+ * Generators of one node, host memory (hss_export fills caller buffers of
+ * the sizes hss_ranks reports; hss_import reads them).  m = mr (U side) or
+ * mc (V side) rows, k = kr or kc.
+ *  Jr, Jc    k entries, pivot order, local row numbers in [0, m).
+ *  Er, Ec    (m-k) x k row-major; row i belongs to the i-th smallest local
+ *            row number not in J (U = Pi [I; E], Sec. 2.2).
+ *  Ir, Ic    k global indices of the row / column skeleton (Alg. 1).
+ *  D         leaves: |I| x |I| row-major diagonal block.
+ *  B12, B21  inner nodes with children a, b: kr_a x kc_b and kr_b x kc_a.
+ * Pointers that are NULL are skipped.
+ */
+typedef struct {
+  int* Jr;
+  int* Jc;
+  double* Er;
+  double* Ec;
+  int* Ir;
+  int* Ic;
+  double* D;
+  double* B12;
+  double* B21;
+} hss_node_generators;
+
+hss_status hss_export_node(hss_handle h, int node, hss_node_generators* g);
+
+/*
+ * Builds a handle from host generators (for example from another
+ * implementation): n, the tree (as in hss_compress), per-node ranks
+ * kr[], kc[] (host, n_nodes entries, 0 at the root) and one
+ * hss_node_generators per node (Ir, Ic unused).  Validates the index sets.
+ */
+hss_status hss_import(long long n, const hss_tree* tree, const int* kr, const int* kc,
+                      const hss_node_generators* nodes, hss_handle* out);
+
+void hss_destroy(hss_handle h);
+
+/* Thread-local message of the last error (empty string if none). */
+const char* hss_last_error(void);
+
+/* ---------------------------------------------------------------------
+ * Building blocks of hss_compress, exported for parity tests.
+ * ------------------------------------------------------------------- */
+
+/*
+ * Columns col0..col1-1 of the Gaussian random matrix of `which` (0 = R^r,
+ * 1 = R^c) for rows 0..n-1 into R (DEVICE, ld >= col1 - col0, column col0
+ * at R[0]).  Entry (i, j): Philox4x64-10 with key (seed, 0) and counter
+ * (i/4, j, which, 0) gives four words; word w maps to
+ * u = ((w >> 12) + 1/2) 2^-52; rows 4q, 4q+1 are the Box-Muller pair of
+ * (u0, u1), rows 4q+2, 4q+3 that of (u2, u3): sqrt(-2 ln ua) cos(2 pi ub),
+ * sqrt(-2 ln ua) sin(2 pi ub).  Stream-ordered.
+ */
+hss_status hss_random_normal(unsigned long long seed, int which, long long n, int col0,
+                             int col1, double* R, long long ld, void* stream);
+
+/*
+ * Sampling products (Sec. 2.2): Sr = (A - M) Rr and Sc = (A - M)^T Rc for
+ * ncols columns, where M is zero (leaf_of == NULL) or the block-diagonal part
+ * of A made of the leaf diagonal blocks (leaf_of: DEVICE int array of n
+ * entries, the leaf number of each index; indices of one leaf are
+ * contiguous), which yields the leaves' local samples directly:
+ * S^(l) = (A - D^(l)) R (Sec. 2.2).  A: DEVICE n x n (dtype), Rr, Rc: DEVICE
+ * n x ncols (ldr); Sr, Sc: DEVICE n x ncols (lds).  Either of Sr/Rr or
+ * Sc/Rc may be NULL.  Stream-ordered.
+ */
+hss_status hss_sample(const void* A, int dtype, long long n, long long lda,
+                      const int* leaf_of, int ncols, const double* Rr, const double* Rc,
+                      long long ldr, double* Sr, double* Sc, long long lds, void* stream);
+
+/*
+ * Batched interpolative decompositions (Sec. 2.2, Sec. 3.2).  Problem p
+ * takes the rows of a DEVICE matrix Y_p^T (m[p] rows, d[p] columns, leading
+ * dimension ldy[p], pointer ys[p]) -- i.e. Y_p is d x m and its columns are
+ * the rows given -- and returns its eps-rank k[p] (host), the selected
+ * columns J (pivot order) followed by the rest in increasing order in
+ * perm[p] (DEVICE, m entries), and E (DEVICE, (m-k) x k row-major) in
+ * es[p] (capacity m*m/4+m doubles).  Host arrays ys, m, d, ldy, perms, es
+ * of nprob entries.  Host-synchronous.
+ */
+hss_status hss_id_batched(int nprob, const double* const* ys, const int* m, const int* d,
+                          const long long* ldy, double rtol, int* const* perms,
+                          double* const* es, int* k, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HSS_H */

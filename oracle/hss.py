@@ -344,3 +344,23 @@ def sampling_flops(n: int, d: int) -> float:
     """Flops of the two sampling products S^r = A R^r, S^c = A^T R^c with d
     columns each: 2 * (2 n^2 d) (Sec. 2.2 states they dominate)."""
     return 4.0 * n * n * d
+
+
+def sample(A, R_r, R_c):
+    """S^r = A R^r and S^c = A^T R^c (Alg. 1, step 2), FP64."""
+    A = np.asarray(A, dtype=np.float64)
+    return A @ np.asarray(R_r, dtype=np.float64), A.T @ np.asarray(R_c, dtype=np.float64)
+
+
+def leaf_local_samples(A, tree: ClusterTree, S_r, S_c, R_r, R_c):
+    """Leaf local samples of Alg. 1 stacked in index order:
+    S^r_loc = S^r(I,:) - D R^r(I,:), S^c_loc = S^c(I,:) - D^T R^c(I,:)."""
+    A = np.asarray(A, dtype=np.float64)
+    out_r = np.array(S_r, dtype=np.float64, copy=True)
+    out_c = np.array(S_c, dtype=np.float64, copy=True)
+    for t in tree.leaves():
+        lo, hi = tree.lo[t], tree.hi[t]
+        D = A[lo:hi, lo:hi]
+        out_r[lo:hi] -= D @ R_r[lo:hi]
+        out_c[lo:hi] -= D.T @ R_c[lo:hi]
+    return out_r, out_c

@@ -1,0 +1,354 @@
+"""Python binding of the MI355X randomized HSS library (``include/hss.h``).
+
+Argument marshalling only: every step runs in the HIP kernels of
+``lib/libhss.so``.  PyTorch tensors provide device memory and streams.  The
+functions keep the C names:
+
+    hss_compress, hss_matvec, hss_factor, hss_solve, hss_stats, hss_ranks,
+    hss_export_node, hss_import, hss_destroy, hss_random_normal, hss_sample,
+    hss_id_batched, hss_default_opts
+
+The library is loaded on first use; if it has not been built (see
+``build.py``) every call raises ``RuntimeError`` -- there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "lib", "libhss.so")
+
+HSS_OK, HSS_NOT_CONVERGED = 0, 1
+HSS_ERR_ARG, HSS_ERR_ALLOC, HSS_ERR_HIP, HSS_ERR_STATE, HSS_ERR_SINGULAR = -1, -2, -3, -4, -5
+HSS_F64, HSS_F32 = 0, 1
+HSS_SAMPLE_F64 = 0
+
+EXPORTED = [
+    "hss_default_opts", "hss_compress", "hss_matvec", "hss_factor", "hss_solve", "hss_stats",
+    "hss_ranks", "hss_export_node", "hss_import", "hss_destroy", "hss_last_error",
+    "hss_random_normal", "hss_sample", "hss_id_batched",
+]
+
+
+class HSSError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"hss status {status}: {msg}")
+        self.status = status
+
+
+class hss_opts(C.Structure):
+    _fields_ = [
+        ("rtol", C.c_double), ("d0", C.c_int), ("dd", C.c_int), ("d_max", C.c_int),
+        ("p_margin", C.c_int), ("seed", C.c_ulonglong), ("leaf_size", C.c_int),
+        ("sample_prec", C.c_int), ("R_user_r", C.c_void_p), ("R_user_c", C.c_void_p),
+        ("ld_R_user", C.c_longlong),
+    ]
+
+
+class hss_tree(C.Structure):
+    _fields_ = [("n_nodes", C.c_int), ("lo", C.POINTER(C.c_int)), ("hi", C.POINTER(C.c_int)),
+                ("left", C.POINTER(C.c_int)), ("right", C.POINTER(C.c_int))]
+
+
+class hss_stats_t(C.Structure):
+    _fields_ = [
+        ("n", C.c_longlong), ("n_nodes", C.c_int), ("height", C.c_int), ("d_final", C.c_int),
+        ("passes", C.c_int), ("converged", C.c_int), ("max_rank", C.c_int),
+        ("generator_bytes", C.c_longlong), ("sample_flops", C.c_double),
+        ("t_total_ms", C.c_double), ("t_sample_ms", C.c_double), ("t_levels_ms", C.c_double),
+        ("t_id_ms", C.c_double),
+    ]
+
+
+class hss_node_generators(C.Structure):
+    _fields_ = [(f, C.c_void_p) for f in ("Jr", "Jc", "Er", "Ec", "Ir", "Ic", "D", "B12", "B21")]
+
+
+_lib = None
+
+
+def lib() -> C.CDLL:
+    """The loaded shared library (raises if it was not built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_1503_05464_amd/build.py "
+                               "(there is no fallback implementation)")
+        L = C.CDLL(LIB_PATH)
+        vp, ll, i, d = C.c_void_p, C.c_longlong, C.c_int, C.c_double
+        L.hss_last_error.restype = C.c_char_p
+        L.hss_default_opts.argtypes = [C.POINTER(hss_opts)]
+        L.hss_default_opts.restype = None
+        L.hss_compress.argtypes = [vp, i, ll, ll, C.POINTER(hss_tree), C.POINTER(hss_opts), vp,
+                                   C.POINTER(vp)]
+        L.hss_matvec.argtypes = [vp, i, vp, ll, vp, ll, vp]
+        L.hss_factor.argtypes = [vp, vp]
+        L.hss_solve.argtypes = [vp, i, vp, ll, vp, ll, vp]
+        L.hss_stats.argtypes = [vp, C.POINTER(hss_stats_t)]
+        L.hss_ranks.argtypes = [vp, vp, vp, vp, vp]
+        L.hss_export_node.argtypes = [vp, i, C.POINTER(hss_node_generators)]
+        L.hss_import.argtypes = [ll, C.POINTER(hss_tree), vp, vp, vp, C.POINTER(vp)]
+        L.hss_destroy.argtypes = [vp]
+        L.hss_destroy.restype = None
+        L.hss_random_normal.argtypes = [C.c_ulonglong, i, ll, i, i, vp, ll, vp]
+        L.hss_sample.argtypes = [vp, i, ll, ll, vp, i, vp, vp, ll, vp, vp, ll, vp]
+        L.hss_id_batched.argtypes = [i, vp, vp, vp, vp, d, vp, vp, vp, vp]
+        for f in EXPORTED:
+            if f not in ("hss_default_opts", "hss_destroy", "hss_last_error"):
+                getattr(L, f).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _check(st: int, allow=(HSS_OK,)) -> int:
+    if st not in allow:
+        raise HSSError(st, lib().hss_last_error().decode(errors="replace"))
+    return st
+
+
+def _stream(stream):
+    import torch
+
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+def _ptr(t) -> C.c_void_p:
+    return C.c_void_p(t.data_ptr())
+
+
+def _np_ptr(a: np.ndarray) -> C.c_void_p:
+    return C.c_void_p(a.ctypes.data)
+
+
+def _tree_struct(tree):
+    """tree: None or (lo, hi, left, right) integer sequences."""
+    if tree is None:
+        return None, None
+    arrs = [np.ascontiguousarray(np.asarray(a, dtype=np.int32)) for a in tree]
+    t = hss_tree(len(arrs[0]), *[a.ctypes.data_as(C.POINTER(C.c_int)) for a in arrs])
+    return t, arrs
+
+
+def hss_default_opts() -> hss_opts:
+    o = hss_opts()
+    lib().hss_default_opts(C.byref(o))
+    return o
+
+
+class HSSHandle:
+    """Owns an hss_handle; destroyed with the object (or hss_destroy)."""
+
+    def __init__(self, ptr: C.c_void_p, n: int, status: int, keep=None):
+        self.ptr = ptr
+        self.n = n
+        self.status = status
+        self._keep = keep
+
+    @property
+    def converged(self) -> bool:
+        return self.status == HSS_OK
+
+    def __del__(self):
+        try:
+            hss_destroy(self)
+        except Exception:
+            pass
+
+
+def hss_compress(A, tree=None, *, rtol=1e-6, d0=64, dd=32, d_max=4096, p_margin=10, seed=0,
+                 leaf_size=64, R_user=None, stream=None) -> HSSHandle:
+    """Compress the square CUDA tensor A (float32 or float64, row-major
+    with unit column stride).  R_user: optional (R^r, R^c) CUDA float64
+    tensors n x >= d_max (row-major) used instead of the Philox columns."""
+    import torch
+
+    if A.dim() != 2 or A.shape[0] != A.shape[1] or A.stride(1) != 1 or not A.is_cuda:
+        raise ValueError("A must be a square CUDA matrix with unit column stride")
+    dt = {torch.float64: HSS_F64, torch.float32: HSS_F32}.get(A.dtype)
+    if dt is None:
+        raise ValueError("A must be float32 or float64")
+    o = hss_default_opts()
+    o.rtol, o.d0, o.dd, o.d_max, o.p_margin = float(rtol), int(d0), int(dd), int(d_max), int(p_margin)
+    o.seed, o.leaf_size = int(seed), int(leaf_size)
+    keep = [A]
+    if R_user is not None:
+        rr, rc = R_user
+        for r in (rr, rc):
+            if r.dtype != torch.float64 or not r.is_cuda or r.stride(1) != 1 or r.shape[0] != A.shape[0] \
+                    or r.shape[1] < d_max or r.stride(0) != rr.stride(0):
+                raise ValueError("R_user tensors must be CUDA float64 n x >= d_max, same layout")
+        o.R_user_r, o.R_user_c, o.ld_R_user = rr.data_ptr(), rc.data_ptr(), rr.stride(0)
+        keep += [rr, rc]
+    t, arrs = _tree_struct(tree)
+    out = C.c_void_p()
+    st = lib().hss_compress(_ptr(A), dt, A.shape[0], A.stride(0), C.byref(t) if t else None,
+                            C.byref(o), _stream(stream), C.byref(out))
+    _check(st, (HSS_OK, HSS_NOT_CONVERGED))
+    return HSSHandle(out, A.shape[0], st)
+
+
+def hss_matvec(h: HSSHandle, x, b=None, stream=None):
+    """b = A_HSS x for a CUDA float64 tensor x (n or n x nrhs)."""
+    import torch
+
+    vec = x.dim() == 1
+    x2 = x.reshape(-1, 1) if vec else x
+    if x2.dtype != torch.float64 or x2.stride(1) != 1 or x2.shape[0] != h.n:
+        raise ValueError("x must be float64, n x nrhs with unit column stride")
+    if b is None:
+        b = torch.empty_like(x2, memory_format=torch.contiguous_format)
+    b2 = b.reshape(-1, 1) if b.dim() == 1 else b
+    _check(lib().hss_matvec(h.ptr, x2.shape[1], _ptr(x2), x2.stride(0), _ptr(b2), b2.stride(0),
+                            _stream(stream)))
+    return b2.reshape(-1) if vec else b2
+
+
+def hss_factor(h: HSSHandle, stream=None) -> None:
+    _check(lib().hss_factor(h.ptr, _stream(stream)))
+
+
+def hss_solve(h: HSSHandle, b, x=None, stream=None):
+    import torch
+
+    vec = b.dim() == 1
+    b2 = b.reshape(-1, 1) if vec else b
+    if b2.dtype != torch.float64 or b2.stride(1) != 1 or b2.shape[0] != h.n:
+        raise ValueError("b must be float64, n x nrhs with unit column stride")
+    if x is None:
+        x = torch.empty_like(b2, memory_format=torch.contiguous_format)
+    x2 = x.reshape(-1, 1) if x.dim() == 1 else x
+    _check(lib().hss_solve(h.ptr, b2.shape[1], _ptr(b2), b2.stride(0), _ptr(x2), x2.stride(0),
+                           _stream(stream)))
+    return x2.reshape(-1) if vec else x2
+
+
+def hss_stats(h: HSSHandle) -> dict:
+    s = hss_stats_t()
+    _check(lib().hss_stats(h.ptr, C.byref(s)))
+    return {f: getattr(s, f) for f, _ in hss_stats_t._fields_}
+
+
+def _n_nodes(h: HSSHandle) -> int:
+    return hss_stats(h)["n_nodes"]
+
+
+def hss_ranks(h: HSSHandle):
+    nn = _n_nodes(h)
+    out = [np.zeros(nn, dtype=np.int32) for _ in range(4)]
+    _check(lib().hss_ranks(h.ptr, *[_np_ptr(a) for a in out]))
+    return tuple(out)
+
+
+def hss_export_node(h: HSSHandle, node: int, tree_children=None) -> dict:
+    """Host copies of one node's generators (numpy).  tree_children: the
+    (left, right) child numbers of `node`, needed for B sizes."""
+    kr, kc, mr, mc = hss_ranks(h)
+    g = hss_node_generators()
+    res = {}
+
+    def buf(name, shape, dtype):
+        a = np.zeros(shape, dtype=dtype)
+        res[name] = a
+        setattr(g, name, a.ctypes.data if a.size else None)
+
+    if node != 0:
+        buf("Jr", (kr[node],), np.int32)
+        buf("Jc", (kc[node],), np.int32)
+        buf("Er", (mr[node] - kr[node], kr[node]), np.float64)
+        buf("Ec", (mc[node] - kc[node], kc[node]), np.float64)
+        buf("Ir", (kr[node],), np.int32)
+        buf("Ic", (kc[node],), np.int32)
+    if tree_children is None or tree_children[0] < 0:
+        buf("D", (mr[node], mr[node]), np.float64)
+    else:
+        a, b = tree_children
+        buf("B12", (kr[a], kc[b]), np.float64)
+        buf("B21", (kr[b], kc[a]), np.float64)
+    _check(lib().hss_export_node(h.ptr, node, C.byref(g)))
+    return res
+
+
+def hss_import(n: int, tree, kr, kc, nodes) -> HSSHandle:
+    """Handle from host generators: tree = (lo, hi, left, right); nodes[t] a
+    dict with keys among Jr, Jc, Er, Ec, D, B12, B21 (numpy arrays)."""
+    t, arrs = _tree_struct(tree)
+    keep = [arrs]
+    gens = (hss_node_generators * len(nodes))()
+    for q, nd in enumerate(nodes):
+        for f in ("Jr", "Jc", "Er", "Ec", "D", "B12", "B21"):
+            if f in nd and nd[f] is not None:
+                a = np.ascontiguousarray(nd[f], dtype=np.int32 if f in ("Jr", "Jc") else np.float64)
+                keep.append(a)
+                setattr(gens[q], f, a.ctypes.data if a.size else None)
+    kr = np.ascontiguousarray(kr, dtype=np.int32)
+    kc = np.ascontiguousarray(kc, dtype=np.int32)
+    out = C.c_void_p()
+    _check(lib().hss_import(int(n), C.byref(t), _np_ptr(kr), _np_ptr(kc), gens, C.byref(out)))
+    return HSSHandle(out, n, HSS_OK)
+
+
+def hss_destroy(h: HSSHandle) -> None:
+    if h is not None and h.ptr:
+        lib().hss_destroy(h.ptr)
+        h.ptr = C.c_void_p()
+
+
+def hss_random_normal(seed: int, which: int, n: int, col0: int, col1: int, out=None, stream=None):
+    import torch
+
+    if out is None:
+        out = torch.empty((n, col1 - col0), dtype=torch.float64, device="cuda")
+    _check(lib().hss_random_normal(int(seed), int(which), int(n), int(col0), int(col1), _ptr(out),
+                                   out.stride(0), _stream(stream)))
+    return out
+
+
+def hss_sample(A, Rr=None, Rc=None, leaf_of=None, stream=None):
+    """(Sr, Sc) = ((A - M) Rr, (A - M)^T Rc); M = leaf diagonal blocks
+    when leaf_of (CUDA int32, leaf ordinal of each index) is given."""
+    import torch
+
+    dt = {torch.float64: HSS_F64, torch.float32: HSS_F32}[A.dtype]
+    R = Rr if Rr is not None else Rc
+    ncols = R.shape[1]
+    Sr = torch.empty((A.shape[0], ncols), dtype=torch.float64, device=A.device) if Rr is not None else None
+    Sc = torch.empty((A.shape[0], ncols), dtype=torch.float64, device=A.device) if Rc is not None else None
+    if Rr is not None and Rc is not None and Rr.stride(0) != Rc.stride(0):
+        raise ValueError("Rr and Rc must share a leading dimension")
+    S = Sr if Sr is not None else Sc
+    _check(lib().hss_sample(_ptr(A), dt, A.shape[0], A.stride(0),
+                            _ptr(leaf_of) if leaf_of is not None else None, ncols,
+                            _ptr(Rr) if Rr is not None else None, _ptr(Rc) if Rc is not None else None,
+                            R.stride(0), _ptr(Sr) if Sr is not None else None,
+                            _ptr(Sc) if Sc is not None else None, S.stride(0), _stream(stream)))
+    return Sr, Sc
+
+
+def hss_id_batched(Ys, rtol: float, stream=None):
+    """Interpolative decompositions of the d x m matrices whose columns are
+    the rows of the CUDA float64 tensors in Ys (each m x d, unit column
+    stride).  Returns a list of (k, perm, E) with perm = J then the rest."""
+    import torch
+
+    np_ = len(Ys)
+    m = np.array([y.shape[0] for y in Ys], dtype=np.int32)
+    d = np.array([y.shape[1] for y in Ys], dtype=np.int32)
+    ldy = np.array([max(y.stride(0), y.shape[1]) for y in Ys], dtype=np.int64)
+    perms = [torch.empty(int(mm), dtype=torch.int32, device="cuda") for mm in m]
+    es = [torch.empty(int(mm) * int(mm) // 4 + 1, dtype=torch.float64, device="cuda") for mm in m]
+    ys_p = np.array([y.data_ptr() for y in Ys], dtype=np.uint64)
+    pp = np.array([p.data_ptr() for p in perms], dtype=np.uint64)
+    ep = np.array([e.data_ptr() for e in es], dtype=np.uint64)
+    k = np.zeros(np_, dtype=np.int32)
+    _check(lib().hss_id_batched(np_, _np_ptr(ys_p), _np_ptr(m), _np_ptr(d), _np_ptr(ldy), float(rtol),
+                                _np_ptr(pp), _np_ptr(ep), _np_ptr(k), _stream(stream)))
+    out = []
+    for q in range(np_):
+        kk, mm = int(k[q]), int(m[q])
+        out.append((kk, perms[q].cpu().numpy(), es[q][: (mm - kk) * kk].reshape(mm - kk, kk).cpu().numpy()))
+    return out

@@ -1,0 +1,1206 @@
+// C ABI of the randomized HSS library: compression (Alg. 1 with the
+// late-notification adaptive sampling of Alg. 5, run level-synchronously over
+// node heights), HSS matvec (Alg. 2), export / import of generators and the
+// exported building blocks.  The ULV factorization and solve are in
+// hss_ulv.cpp.  All arithmetic runs in the HIP kernels; this file sizes
+// buffers, builds descriptor tables and orders the launches.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <climits>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "hss_handle.h"
+
+using namespace hss;
+
+namespace {
+
+thread_local std::string g_err;
+
+hss_status fail(hss_status st, const std::string& msg) {
+  g_err = msg;
+  return st;
+}
+
+#define HIPCHK(x)                                                                      \
+  do {                                                                                 \
+    hipError_t e_ = (x);                                                               \
+    if (e_ != hipSuccess)                                                              \
+      return fail(HSS_ERR_HIP, std::string(#x) + ": " + hipGetErrorString(e_));       \
+  } while (0)
+
+#define CHK(x)                              \
+  do {                                      \
+    hss_status st_ = (x);                   \
+    if (st_ != HSS_OK) return st_;          \
+  } while (0)
+
+size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+double now_ms() {
+  return std::chrono::duration<double, std::milli>(
+             std::chrono::steady_clock::now().time_since_epoch())
+      .count();
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// memory helpers
+// ---------------------------------------------------------------------------
+namespace hss {
+
+void* Arena::alloc(size_t bytes) {
+  bytes = round_up(bytes ? bytes : 1, 256);
+  if (bytes > left) {
+    const size_t chunk = std::max(bytes, (size_t)64 << 20);
+    void* p = nullptr;
+    if (hipMalloc(&p, chunk) != hipSuccess) return nullptr;
+    chunks.push_back(p);
+    cur = static_cast<char*>(p);
+    left = chunk;
+  }
+  void* r = cur;
+  cur += bytes;
+  left -= bytes;
+  total += bytes;
+  return r;
+}
+
+void Arena::release() {
+  for (void* p : chunks) hipFree(p);
+  chunks.clear();
+  cur = nullptr;
+  left = 0;
+  total = 0;
+}
+
+void* Scratch::ensure(size_t bytes) {
+  bytes = round_up(bytes ? bytes : 1, 256);
+  if (bytes <= cap) return p;
+  if (p) hipFree(p);
+  p = nullptr;
+  cap = 0;
+  const size_t want = std::max(bytes, cap * 3 / 2);
+  if (hipMalloc(&p, want) != hipSuccess) return nullptr;
+  cap = want;
+  return p;
+}
+
+void Scratch::release() {
+  if (p) hipFree(p);
+  p = nullptr;
+  cap = 0;
+}
+
+hipError_t Staging::init(size_t bytes, hipStream_t s) {
+  stream = s;
+  cap = bytes;
+  used = 0;
+  hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&host), bytes, hipHostMallocDefault);
+  if (e != hipSuccess) return e;
+  return hipMalloc(reinterpret_cast<void**>(&dev), bytes);
+}
+
+void Staging::release() {
+  if (host) hipHostFree(host);
+  if (dev) hipFree(dev);
+  host = dev = nullptr;
+  cap = used = 0;
+}
+
+void* Staging::push(const void* src, size_t bytes) {
+  const size_t need = round_up(bytes ? bytes : 1, 256);
+  if (used + need > cap) {
+    // every queued copy must have read its region before it is rewritten
+    if (hipStreamSynchronize(stream) != hipSuccess) return nullptr;
+    used = 0;
+    if (need > cap) {
+      release();
+      if (init(need * 2, stream) != hipSuccess) return nullptr;
+    }
+  }
+  std::memcpy(host + used, src, bytes);
+  if (hipMemcpyAsync(dev + used, host + used, bytes, hipMemcpyHostToDevice, stream) != hipSuccess)
+    return nullptr;
+  void* r = dev + used;
+  used += need;
+  return r;
+}
+
+long long Handle::generator_bytes() const {
+  long long b = 0;
+  for (size_t t = 0; t < nodes.size(); ++t) {
+    const Node& v = nodes[t];
+    if (v.leaf()) b += (long long)v.size() * v.size() * 8;
+    if (t != 0) {
+      b += (long long)(v.mr - v.kr) * v.kr * 8 + (long long)(v.mc - v.kc) * v.kc * 8;
+      b += (long long)(v.mr + v.mc + v.kr + v.kc) * 4;
+    }
+    if (!v.leaf()) {
+      const Node& a = nodes[v.left];
+      const Node& c = nodes[v.right];
+      b += (long long)(a.kr * c.kc + c.kr * a.kc) * 8;
+    }
+  }
+  return b;
+}
+
+}  // namespace hss
+
+// ---------------------------------------------------------------------------
+// tree
+// ---------------------------------------------------------------------------
+namespace {
+
+hss_status build_tree(Handle& H, long long n, const hss_tree* tree, int leaf_size) {
+  std::vector<Node>& nd = H.nodes;
+  nd.clear();
+  if (!tree) {
+    if (leaf_size < 1) return fail(HSS_ERR_ARG, "leaf_size must be >= 1");
+    Node r;
+    r.lo = 0;
+    r.hi = (int)n;
+    nd.push_back(r);
+    for (size_t head = 0; head < nd.size(); ++head) {  // breadth-first
+      const int lo = nd[head].lo, hi = nd[head].hi, m = hi - lo;
+      if (m > leaf_size) {
+        const int mid = lo + m / 2;
+        Node a, b;
+        a.lo = lo;
+        a.hi = mid;
+        a.parent = (int)head;
+        b.lo = mid;
+        b.hi = hi;
+        b.parent = (int)head;
+        nd.push_back(a);
+        nd.push_back(b);
+        nd[head].left = (int)nd.size() - 2;
+        nd[head].right = (int)nd.size() - 1;
+      }
+    }
+  } else {
+    const int nn = tree->n_nodes;
+    if (nn < 1 || !tree->lo || !tree->hi || !tree->left || !tree->right)
+      return fail(HSS_ERR_ARG, "tree arrays missing");
+    nd.resize(nn);
+    for (int t = 0; t < nn; ++t) {
+      nd[t].lo = tree->lo[t];
+      nd[t].hi = tree->hi[t];
+      nd[t].left = tree->left[t];
+      nd[t].right = tree->right[t];
+    }
+    if (nd[0].lo != 0 || nd[0].hi != n) return fail(HSS_ERR_ARG, "root interval must be [0, n)");
+    std::vector<int> seen(nn, 0);
+    seen[0] = 1;
+    for (int t = 0; t < nn; ++t) {
+      Node& v = nd[t];
+      if (v.hi <= v.lo) return fail(HSS_ERR_ARG, "empty tree interval");
+      if ((v.left < 0) != (v.right < 0)) return fail(HSS_ERR_ARG, "node with one child");
+      if (v.left >= 0) {
+        if (v.left >= nn || v.right >= nn || v.left == 0 || v.right == 0)
+          return fail(HSS_ERR_ARG, "bad child index");
+        Node &a = nd[v.left], &b = nd[v.right];
+        if (a.lo != v.lo || a.hi != b.lo || b.hi != v.hi)
+          return fail(HSS_ERR_ARG, "children do not split the parent interval");
+        if (seen[v.left]++ || seen[v.right]++) return fail(HSS_ERR_ARG, "node reached twice");
+        a.parent = t;
+        b.parent = t;
+      }
+    }
+    for (int t = 0; t < nn; ++t)
+      if (!seen[t]) return fail(HSS_ERR_ARG, "node not reachable from the root");
+  }
+  // heights (children before parents: iterate until stable; depth-first order)
+  std::vector<int> order;
+  order.reserve(nd.size());
+  std::vector<int> st{0};
+  while (!st.empty()) {
+    int t = st.back();
+    st.pop_back();
+    order.push_back(t);
+    if (nd[t].left >= 0) {
+      st.push_back(nd[t].left);
+      st.push_back(nd[t].right);
+    }
+  }
+  for (auto it = order.rbegin(); it != order.rend(); ++it) {
+    Node& v = nd[*it];
+    v.height = v.leaf() ? 0 : 1 + std::max(nd[v.left].height, nd[v.right].height);
+  }
+  H.height = nd[0].height;
+  H.levels.assign(H.height, {});
+  for (size_t t = 1; t < nd.size(); ++t) H.levels[nd[t].height].push_back((int)t);
+  H.leaves.clear();
+  for (size_t t = 0; t < nd.size(); ++t)
+    if (nd[t].leaf()) H.leaves.push_back((int)t);
+  std::sort(H.leaves.begin(), H.leaves.end(),
+            [&](int a, int b) { return nd[a].lo < nd[b].lo; });
+  return HSS_OK;
+}
+
+template <typename T>
+T* arena_alloc(Handle& H, size_t count) {
+  return static_cast<T*>(H.arena.alloc(count * sizeof(T)));
+}
+
+// ---------------------------------------------------------------------------
+// compression
+// ---------------------------------------------------------------------------
+struct EventTimer {  // HIP events on the compression stream, summed at the end
+  std::vector<hipEvent_t> ev;
+  std::vector<int> b, e, cat;  // begin index, end index, category (0 sample, 1 levels, 2 id)
+  hipStream_t s = nullptr;
+  int begin() {
+    hipEvent_t x;
+    hipEventCreate(&x);
+    hipEventRecord(x, s);
+    ev.push_back(x);
+    return (int)ev.size() - 1;
+  }
+  void end(int bi, int c) {
+    const int ei = begin();
+    b.push_back(bi);
+    e.push_back(ei);
+    cat.push_back(c);
+  }
+  void finish(double* acc) {
+    hipStreamSynchronize(s);
+    for (size_t i = 0; i < b.size(); ++i) {
+      float ms = 0;
+      hipEventElapsedTime(&ms, ev[b[i]], ev[e[i]]);
+      acc[cat[i]] += ms;
+    }
+    for (auto x : ev) hipEventDestroy(x);
+    ev.clear();
+    b.clear();
+    e.clear();
+    cat.clear();
+  }
+};
+
+hss_status sample_columns(Handle& H, const void* A, long long lda, int c0, int c1, EventTimer& tm) {
+  const int nc = c1 - c0;
+  if (nc <= 0) return HSS_OK;
+  const int ev0 = tm.begin();
+  if (H.opts.R_user_r) {
+    HIPCHK(hipMemcpy2DAsync(H.Rr + c0, H.ldg * 8, H.opts.R_user_r + c0, H.opts.ld_R_user * 8,
+                            (size_t)nc * 8, H.n, hipMemcpyDeviceToDevice, H.stream));
+    HIPCHK(hipMemcpy2DAsync(H.Rc + c0, H.ldg * 8, H.opts.R_user_c + c0, H.opts.ld_R_user * 8,
+                            (size_t)nc * 8, H.n, hipMemcpyDeviceToDevice, H.stream));
+  } else {
+    launch_random_normal(H.opts.seed, 0, H.n, c0, c1, H.Rr + c0, H.ldg, H.stream);
+    launch_random_normal(H.opts.seed, 1, H.n, c0, c1, H.Rc + c0, H.ldg, H.stream);
+  }
+  const long long wd = sample_workspace_doubles(H.n, nc);
+  double* work = nullptr;
+  if (wd > 0) {
+    work = static_cast<double*>(H.work_sample.ensure((size_t)wd * 8));
+    if (!work) return fail(HSS_ERR_ALLOC, "sampling workspace");
+  }
+  launch_sample(A, H.dtype, H.n, lda, H.leaf_of, nc, H.Rr + c0, H.Rc + c0, H.ldg, H.Sr + c0,
+                H.Sc + c0, H.ldg, work, H.stream);
+  HIPCHK(hipGetLastError());
+  tm.end(ev0, 0);
+  return HSS_OK;
+}
+
+// Source rows of the "R_in" stack of node t: R(I_t) at a leaf, [R_a; R_b] above.
+Seg r_in(const Handle& H, int t, bool row_side, int c0) {
+  const Node& v = H.nodes[t];
+  Seg s{};
+  s.ld = H.ldg;
+  s.split = INT_MAX;
+  if (v.leaf()) {
+    s.p0 = (row_side ? H.Rr : H.Rc) + (long long)v.lo * H.ldg + c0;
+  } else {
+    const Node& a = H.nodes[v.left];
+    const Node& b = H.nodes[v.right];
+    s.p0 = (row_side ? a.Rr : a.Rc) + c0;
+    s.p1 = (row_side ? b.Rr : b.Rc) + c0;
+    s.split = row_side ? a.kc : a.kr;
+  }
+  return s;
+}
+
+hss_status process_level(Handle& H, const void* A, long long lda, const std::vector<int>& lvl,
+                         const std::vector<char>& ext, int d, bool forced, bool& any_fail,
+                         EventTimer& tm) {
+  std::vector<Node>& nd = H.nodes;
+  std::vector<int> todo;
+  for (int t : lvl) {
+    const Node& v = nd[t];
+    if (!v.leaf() && !(nd[v.left].state == HSS_COMPRESSED && nd[v.right].state == HSS_COMPRESSED))
+      continue;
+    if (v.state == HSS_COMPRESSED && !ext[t]) continue;
+    if (v.state == HSS_COMPRESSED && v.cdone >= d) continue;
+    todo.push_back(t);
+  }
+  if (todo.empty()) return HSS_OK;
+  const int ev_level = tm.begin();
+
+  // (1) first visit: sizes, buffers, D or B
+  std::vector<GatherDesc> gath;
+  for (int t : todo) {
+    Node& v = nd[t];
+    if (v.set_up) continue;
+    if (v.leaf()) {
+      const int m = v.size();
+      v.mr = v.mc = m;
+      v.Sr = H.Sr + (long long)v.lo * H.ldg;
+      v.Sc = H.Sc + (long long)v.lo * H.ldg;
+      v.D = arena_alloc<double>(H, (size_t)m * m);
+      if (!v.D) return fail(HSS_ERR_ALLOC, "leaf D");
+      GatherDesc g{};
+      g.nr = g.nc = m;
+      g.out = v.D;
+      g.ldo = m;
+      g.row_off = g.col_off = v.lo;
+      gath.push_back(g);
+    } else {
+      const Node& a = nd[v.left];
+      const Node& b = nd[v.right];
+      v.mr = a.kr + b.kr;
+      v.mc = a.kc + b.kc;
+      v.B12 = arena_alloc<double>(H, (size_t)a.kr * b.kc);
+      v.B21 = arena_alloc<double>(H, (size_t)b.kr * a.kc);
+      v.Sr = arena_alloc<double>(H, (size_t)v.mr * H.ldg);
+      v.Sc = arena_alloc<double>(H, (size_t)v.mc * H.ldg);
+      if (!v.B12 || !v.B21 || !v.Sr || !v.Sc) return fail(HSS_ERR_ALLOC, "inner node buffers");
+      GatherDesc g{};
+      g.rows = a.Ir;
+      g.cols = b.Ic;
+      g.nr = a.kr;
+      g.nc = b.kc;
+      g.out = v.B12;
+      g.ldo = b.kc;
+      gath.push_back(g);
+      g.rows = b.Ir;
+      g.cols = a.Ic;
+      g.nr = b.kr;
+      g.nc = a.kc;
+      g.out = v.B21;
+      g.ldo = a.kc;
+      gath.push_back(g);
+    }
+    v.perm_r = arena_alloc<int>(H, (size_t)v.mr);
+    v.perm_c = arena_alloc<int>(H, (size_t)v.mc);
+    v.Er = arena_alloc<double>(H, (size_t)v.mr * v.mr / 4 + 1);
+    v.Ec = arena_alloc<double>(H, (size_t)v.mc * v.mc / 4 + 1);
+    if (!v.perm_r || !v.perm_c || !v.Er || !v.Ec) return fail(HSS_ERR_ALLOC, "ID buffers");
+    v.cdone = 0;
+    v.set_up = true;
+  }
+  HIPCHK(launch_gather(A, H.dtype, lda, gath.data(), (int)gath.size(), H.staging, H.stream));
+
+  // (2) local samples of inner nodes, columns [cdone, d) (Alg. 1 / Alg. 5)
+  std::vector<GemmDesc> gd;
+  for (int t : todo) {
+    Node& v = nd[t];
+    if (v.leaf() || v.cdone >= d) continue;
+    const Node& a = nd[v.left];
+    const Node& b = nd[v.right];
+    const int c0 = v.cdone, N = d - c0;
+    auto mk = [&](int M, int K, const double* Am, long long lda_, int tr, const double* Bp,
+                  const double* Cp, const int* cmap, double* Dp) {
+      GemmDesc g{};
+      g.M = M;
+      g.N = N;
+      g.K = K;
+      g.A = Am;
+      g.lda = lda_;
+      g.transA = tr;
+      g.B = Seg{Bp, nullptr, H.ldg, INT_MAX, nullptr};
+      g.C = Seg{Cp, nullptr, H.ldg, INT_MAX, cmap};
+      g.D = SegOut{Dp, nullptr, H.ldg, INT_MAX, nullptr};
+      g.alpha = -1.0;
+      g.beta = 1.0;
+      gd.push_back(g);
+    };
+    // S^r_loc = [S^r_a - B_ab R^r_b ; S^r_b - B_ba R^r_a]
+    mk(a.kr, b.kc, v.B12, b.kc, 0, b.Rr + c0, a.Sr + c0, a.perm_r, v.Sr + c0);
+    mk(b.kr, a.kc, v.B21, a.kc, 0, a.Rr + c0, b.Sr + c0, b.perm_r, v.Sr + (long long)a.kr * H.ldg + c0);
+    // S^c_loc = [S^c_a - B_ba^T R^c_b ; S^c_b - B_ab^T R^c_a]
+    mk(a.kc, b.kr, v.B21, a.kc, 1, b.Rc + c0, a.Sc + c0, a.perm_c, v.Sc + c0);
+    mk(b.kc, a.kr, v.B12, b.kc, 1, a.Rc + c0, b.Sc + c0, b.perm_c, v.Sc + (long long)a.kc * H.ldg + c0);
+  }
+  HIPCHK(launch_gemm_batched(gd.data(), (int)gd.size(), H.staging, H.stream));
+
+  // (3) interpolative decompositions of the nodes not yet compressed
+  std::vector<int> idn;
+  for (int t : todo)
+    if (nd[t].state != HSS_COMPRESSED) idn.push_back(t);
+  std::vector<int> passed;
+  if (!idn.empty()) {
+    const int np = 2 * (int)idn.size();
+    std::vector<IdProblem> pr(np);
+    std::vector<long long> offs(np);
+    long long wtot = 0, mtot = 0;
+    for (int q = 0; q < np; ++q) {
+      const Node& v = nd[idn[q / 2]];
+      const bool rs = (q % 2) == 0;
+      IdProblem& p = pr[q];
+      p.Y = rs ? v.Sr : v.Sc;
+      p.ldy = H.ldg;
+      p.m = rs ? v.mr : v.mc;
+      p.d = d;
+      p.ldw = d;
+      p.perm = rs ? v.perm_r : v.perm_c;
+      p.E = rs ? v.Er : v.Ec;
+      p.kfail = forced ? -1 : std::max(d - H.opts.p_margin, -1);
+      if (!forced && d - H.opts.p_margin < 0) p.kfail = -1;
+      offs[q] = mtot;
+      mtot += p.m;
+      wtot += (long long)p.m * d;
+    }
+    const size_t wbytes = round_up((size_t)wtot * 8, 256);
+    const size_t sbytes = round_up((size_t)mtot * 4, 256);
+    const size_t nbytes = round_up((size_t)mtot * 8, 256);
+    const size_t kbytes = round_up((size_t)np * 4, 256);
+    char* base = static_cast<char*>(H.work_id.ensure(wbytes + sbytes + nbytes + kbytes));
+    if (!base) return fail(HSS_ERR_ALLOC, "ID workspace");
+    double* W = reinterpret_cast<double*>(base);
+    int* step = reinterpret_cast<int*>(base + wbytes);
+    double* nrm = reinterpret_cast<double*>(base + wbytes + sbytes);
+    int* kdev = reinterpret_cast<int*>(base + wbytes + sbytes + nbytes);
+    long long wo = 0;
+    for (int q = 0; q < np; ++q) {
+      pr[q].W = W + wo;
+      wo += (long long)pr[q].m * d;
+    }
+    if (H.k_host_cap < np) {
+      if (H.k_host) hipHostFree(H.k_host);
+      H.k_host = nullptr;
+      HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&H.k_host), (size_t)np * 2 * 4, hipHostMallocDefault));
+      H.k_host_cap = np * 2;
+    }
+    const int ev_id = tm.begin();
+    HIPCHK(launch_id_batched(pr.data(), np, H.opts.rtol, kdev, step, nrm, offs.data(), H.staging,
+                             H.stream));
+    tm.end(ev_id, 2);
+    HIPCHK(hipMemcpyAsync(H.k_host, kdev, (size_t)np * 4, hipMemcpyDeviceToHost, H.stream));
+    HIPCHK(hipStreamSynchronize(H.stream));
+    H.staging.reset();
+    const int kf = d - H.opts.p_margin;
+    for (size_t q = 0; q < idn.size(); ++q) {
+      Node& v = nd[idn[q]];
+      const int kr = H.k_host[2 * q], kc = H.k_host[2 * q + 1];
+      const bool fr = (kr > kf && kr < v.mr), fc = (kc > kf && kc < v.mc);
+      if (!forced && (fr || fc)) {
+        v.state = HSS_PARTIALLY_COMPRESSED;
+        any_fail = true;
+        continue;
+      }
+      v.kr = kr;
+      v.kc = kc;
+      v.Rr = arena_alloc<double>(H, (size_t)kc * H.ldg);
+      v.Rc = arena_alloc<double>(H, (size_t)kr * H.ldg);
+      v.Ir = arena_alloc<int>(H, (size_t)kr);
+      v.Ic = arena_alloc<int>(H, (size_t)kc);
+      if (!v.Rr || !v.Rc || !v.Ir || !v.Ic) return fail(HSS_ERR_ALLOC, "node R / index buffers");
+      v.state = HSS_COMPRESSED;
+      passed.push_back(idn[q]);
+    }
+  }
+
+  // (4) skeleton index sets of the nodes compressed now: I_tau = I_in(J)
+  std::vector<IndexDesc> ix;
+  for (int t : passed) {
+    const Node& v = nd[t];
+    IndexDesc a{}, c{};
+    a.perm = v.perm_r;
+    a.k = v.kr;
+    c.perm = v.perm_c;
+    c.k = v.kc;
+    if (v.leaf()) {
+      a.split = c.split = INT_MAX;
+      a.off0 = c.off0 = v.lo;
+    } else {
+      const Node& l = nd[v.left];
+      const Node& r = nd[v.right];
+      a.b0 = l.Ir;
+      a.b1 = r.Ir;
+      a.split = l.kr;
+      c.b0 = l.Ic;
+      c.b1 = r.Ic;
+      c.split = l.kc;
+    }
+    a.out = v.Ir;
+    c.out = v.Ic;
+    if (a.k > 0) ix.push_back(a);
+    if (c.k > 0) ix.push_back(c);
+  }
+  HIPCHK(launch_index_compose(ix.data(), (int)ix.size(), H.staging, H.stream));
+
+  // (5) R^r_tau = V^T R^r_in and R^c_tau = U^T R^c_in on the new columns
+  gd.clear();
+  for (int t : todo) {
+    Node& v = nd[t];
+    if (v.state != HSS_COMPRESSED) continue;
+    const bool fresh = std::find(passed.begin(), passed.end(), t) != passed.end();
+    const int c0 = fresh ? 0 : v.cdone;
+    if (c0 >= d) continue;
+    for (int side = 0; side < 2; ++side) {
+      // side 0: R^r_tau uses V (perm_c, Ec, kc, mc); side 1: R^c_tau uses U
+      const int k = side == 0 ? v.kc : v.kr;
+      const int m = side == 0 ? v.mc : v.mr;
+      const int* perm = side == 0 ? v.perm_c : v.perm_r;
+      Seg src = r_in(H, t, side == 0, c0);
+      GemmDesc g{};
+      g.M = k;
+      g.N = d - c0;
+      g.K = m - k;
+      g.A = side == 0 ? v.Ec : v.Er;
+      g.lda = k;
+      g.transA = 1;
+      g.B = src;
+      g.B.map = perm + k;
+      g.C = src;
+      g.C.map = perm;
+      g.D = SegOut{(side == 0 ? v.Rr : v.Rc) + c0, nullptr, H.ldg, INT_MAX, nullptr};
+      g.alpha = 1.0;
+      g.beta = 1.0;
+      gd.push_back(g);
+    }
+  }
+  HIPCHK(launch_gemm_batched(gd.data(), (int)gd.size(), H.staging, H.stream));
+  for (int t : todo) nd[t].cdone = d;
+  tm.end(ev_level, 1);
+  HIPCHK(hipStreamSynchronize(H.stream));
+  H.staging.reset();
+  return HSS_OK;
+}
+
+hss_status compress_impl(Handle& H, const void* A, long long lda) {
+  const double t0 = now_ms();
+  EventTimer tm;
+  tm.s = H.stream;
+  std::vector<Node>& nd = H.nodes;
+  const long long n = H.n;
+  if (nd[0].leaf()) {  // a single leaf: D = A
+    Node& r = nd[0];
+    r.D = arena_alloc<double>(H, (size_t)n * n);
+    if (!r.D) return fail(HSS_ERR_ALLOC, "D");
+    GatherDesc g{};
+    g.nr = g.nc = (int)n;
+    g.out = r.D;
+    g.ldo = n;
+    HIPCHK(launch_gather(A, H.dtype, lda, &g, 1, H.staging, H.stream));
+    HIPCHK(hipStreamSynchronize(H.stream));
+    H.compressed = true;
+    H.t_total = now_ms() - t0;
+    return HSS_OK;
+  }
+  const int dmax = H.opts.d_max;
+  H.ldg = (long long)round_up((size_t)dmax, 8);
+  H.Rr = arena_alloc<double>(H, (size_t)n * H.ldg);
+  H.Rc = arena_alloc<double>(H, (size_t)n * H.ldg);
+  H.Sr = arena_alloc<double>(H, (size_t)n * H.ldg);
+  H.Sc = arena_alloc<double>(H, (size_t)n * H.ldg);
+  H.leaf_of = arena_alloc<int>(H, (size_t)n);
+  if (!H.Rr || !H.Rc || !H.Sr || !H.Sc || !H.leaf_of)
+    return fail(HSS_ERR_ALLOC, "random matrices / samples (n x d_max doubles each)");
+  {
+    const int nl = (int)H.leaves.size();
+    std::vector<int> lo(nl), hi(nl);
+    for (int q = 0; q < nl; ++q) {
+      lo[q] = nd[H.leaves[q]].lo;
+      hi[q] = nd[H.leaves[q]].hi;
+    }
+    int* dlo = static_cast<int*>(H.staging.push(lo.data(), lo.size() * 4));
+    int* dhi = static_cast<int*>(H.staging.push(hi.data(), hi.size() * 4));
+    if (!dlo || !dhi) return fail(HSS_ERR_HIP, "staging");
+    launch_leaf_of(nl, dlo, dhi, H.leaf_of, H.stream);
+    HIPCHK(hipGetLastError());
+  }
+  int d = std::min(H.opts.d0, dmax);
+  CHK(sample_columns(H, A, lda, 0, d, tm));
+  bool forced = false;
+  H.passes = 0;
+  H.converged = true;
+  std::vector<char> ext(nd.size(), 0);
+  while (true) {
+    ++H.passes;
+    // a compressed node extends its samples iff a non-root ancestor is
+    // unfinished (only then does anyone read the new columns)
+    for (size_t t = 1; t < nd.size(); ++t) ext[t] = 0;
+    for (int h = H.height - 1; h >= 0; --h)
+      for (int t : H.levels[h]) {
+        const int p = nd[t].parent;
+        ext[t] = (p != 0) && (nd[p].state != HSS_COMPRESSED || ext[p]);
+      }
+    bool any_fail = false;
+    for (int h = 0; h < H.height; ++h)
+      CHK(process_level(H, A, lda, H.levels[h], ext, d, forced, any_fail, tm));
+    bool done = true;
+    for (size_t t = 1; t < nd.size(); ++t)
+      if (nd[t].state != HSS_COMPRESSED) done = false;
+    if (done) break;
+    if (d >= dmax) {
+      forced = true;
+      H.converged = false;
+      continue;
+    }
+    const int dn = std::min(d + H.opts.dd, dmax);
+    CHK(sample_columns(H, A, lda, d, dn, tm));
+    d = dn;
+  }
+  // root: B_ab = A(I^r_a, I^c_b), B_ba = A(I^r_b, I^c_a)
+  {
+    Node& r = nd[0];
+    const Node& a = nd[r.left];
+    const Node& b = nd[r.right];
+    r.mr = a.kr + b.kr;
+    r.mc = a.kc + b.kc;
+    r.B12 = arena_alloc<double>(H, (size_t)a.kr * b.kc);
+    r.B21 = arena_alloc<double>(H, (size_t)b.kr * a.kc);
+    if (!r.B12 || !r.B21) return fail(HSS_ERR_ALLOC, "root B");
+    GatherDesc g[2] = {};
+    g[0].rows = a.Ir;
+    g[0].cols = b.Ic;
+    g[0].nr = a.kr;
+    g[0].nc = b.kc;
+    g[0].out = r.B12;
+    g[0].ldo = b.kc;
+    g[1].rows = b.Ir;
+    g[1].cols = a.Ic;
+    g[1].nr = b.kr;
+    g[1].nc = a.kc;
+    g[1].out = r.B21;
+    g[1].ldo = a.kc;
+    HIPCHK(launch_gather(A, H.dtype, lda, g, 2, H.staging, H.stream));
+  }
+  double acc[3] = {0, 0, 0};
+  tm.finish(acc);
+  HIPCHK(hipStreamSynchronize(H.stream));
+  H.staging.reset();
+  H.d = d;
+  H.t_sample = acc[0];
+  H.t_levels = acc[1];
+  H.t_id = acc[2];
+  H.compressed = true;
+  H.t_total = now_ms() - t0;
+  return H.converged ? HSS_OK : HSS_NOT_CONVERGED;
+}
+
+hss_status new_handle(hss_handle* out, long long n, hipStream_t s, hss_handle_s** hp) {
+  hss_handle_s* p = new (std::nothrow) hss_handle_s();
+  if (!p) return fail(HSS_ERR_ALLOC, "handle");
+  p->h.n = n;
+  p->h.stream = s;
+  if (p->h.staging.init((size_t)4 << 20, s) != hipSuccess) {
+    delete p;
+    return fail(HSS_ERR_ALLOC, "staging buffers");
+  }
+  *hp = p;
+  (void)out;
+  return HSS_OK;
+}
+
+void free_handle(hss_handle_s* p) {
+  if (!p) return;
+  Handle& H = p->h;
+  if (H.stream) hipStreamSynchronize(H.stream);
+  H.arena.release();
+  H.work_id.release();
+  H.work_sample.release();
+  H.work_mv.release();
+  H.work_misc.release();
+  H.staging.release();
+  if (H.k_host) hipHostFree(H.k_host);
+  delete p;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// matvec (Alg. 2)
+// ---------------------------------------------------------------------------
+namespace hss {
+
+hss_status matvec_impl(Handle& H, int nrhs, const double* x, long long ldx, double* b,
+                       long long ldb, hipStream_t s) {
+  std::vector<Node>& nd = H.nodes;
+  H.staging.stream = s;
+  if (nd[0].leaf()) {
+    GemmDesc g{};
+    g.M = g.K = (int)H.n;
+    g.N = nrhs;
+    g.A = nd[0].D;
+    g.lda = H.n;
+    g.B = Seg{x, nullptr, ldx, INT_MAX, nullptr};
+    g.D = SegOut{b, nullptr, ldb, INT_MAX, nullptr};
+    g.alpha = 1.0;
+    HIPCHK(launch_gemm_batched(&g, 1, H.staging, s));
+    HIPCHK(hipStreamSynchronize(s));
+    H.staging.reset();
+    return HSS_OK;
+  }
+  // workspace: y (kc), z (kr), w (mr) per node, nrhs columns each
+  std::vector<long long> oy(nd.size()), oz(nd.size()), ow(nd.size());
+  long long tot = 0;
+  for (size_t t = 0; t < nd.size(); ++t) {
+    oy[t] = tot;
+    tot += (long long)nd[t].kc * nrhs;
+    oz[t] = tot;
+    tot += (long long)nd[t].kr * nrhs;
+    ow[t] = tot;
+    tot += (long long)nd[t].mr * nrhs;
+  }
+  double* ws = static_cast<double*>(H.work_mv.ensure((size_t)tot * 8 + 8));
+  if (!ws) return fail(HSS_ERR_ALLOC, "matvec workspace");
+  auto Y = [&](int t) { return ws + oy[t]; };
+  auto Z = [&](int t) { return ws + oz[t]; };
+  auto Wv = [&](int t) { return ws + ow[t]; };
+  std::vector<GemmDesc> gd;
+  // upward: y_tau = V^T x_in
+  for (int h = 0; h < H.height; ++h) {
+    gd.clear();
+    for (int t : H.levels[h]) {
+      const Node& v = nd[t];
+      Seg src{};
+      if (v.leaf()) {
+        src = Seg{x + (long long)v.lo * ldx, nullptr, ldx, INT_MAX, nullptr};
+      } else {
+        src = Seg{Y(v.left), Y(v.right), nrhs, nd[v.left].kc, nullptr};
+      }
+      GemmDesc g{};
+      g.M = v.kc;
+      g.N = nrhs;
+      g.K = v.mc - v.kc;
+      g.A = v.Ec;
+      g.lda = v.kc;
+      g.transA = 1;
+      g.B = src;
+      g.B.map = v.perm_c + v.kc;
+      g.C = src;
+      g.C.map = v.perm_c;
+      g.D = SegOut{Y(t), nullptr, nrhs, INT_MAX, nullptr};
+      g.alpha = g.beta = 1.0;
+      gd.push_back(g);
+    }
+    HIPCHK(launch_gemm_batched(gd.data(), (int)gd.size(), H.staging, s));
+  }
+  // downward: w_tau = U_tau z_tau, then z_a = B_ab y_b + w_tau(top), z_b = B_ba y_a + w_tau(bottom)
+  for (int h = H.height; h >= 1; --h) {
+    std::vector<int> inner;
+    if (h == H.height) inner.push_back(0);
+    else
+      for (int t : H.levels[h]) inner.push_back(t);
+    gd.clear();
+    for (int t : inner) {
+      if (t == 0) continue;
+      const Node& v = nd[t];
+      GemmDesc g{};  // rows J: w[J[a]] = z[a]
+      g.M = v.kr;
+      g.N = nrhs;
+      g.K = 0;
+      g.C = Seg{Z(t), nullptr, nrhs, INT_MAX, nullptr};
+      g.D = SegOut{Wv(t), nullptr, nrhs, INT_MAX, v.perm_r};
+      g.alpha = 1.0;
+      g.beta = 1.0;
+      gd.push_back(g);
+      GemmDesc e{};  // other rows: w[rest[i]] = (E z)[i]
+      e.M = v.mr - v.kr;
+      e.N = nrhs;
+      e.K = v.kr;
+      e.A = v.Er;
+      e.lda = v.kr;
+      e.B = Seg{Z(t), nullptr, nrhs, INT_MAX, nullptr};
+      e.D = SegOut{Wv(t), nullptr, nrhs, INT_MAX, v.perm_r + v.kr};
+      e.alpha = 1.0;
+      gd.push_back(e);
+    }
+    HIPCHK(launch_gemm_batched(gd.data(), (int)gd.size(), H.staging, s));
+    gd.clear();
+    for (int t : inner) {
+      const Node& v = nd[t];
+      const Node& a = nd[v.left];
+      const Node& c = nd[v.right];
+      GemmDesc g{};
+      g.N = nrhs;
+      g.alpha = 1.0;
+      g.beta = (t == 0) ? 0.0 : 1.0;
+      // z_a = B_ab y_b (+ w top)
+      g.M = a.kr;
+      g.K = c.kc;
+      g.A = v.B12;
+      g.lda = c.kc;
+      g.B = Seg{Y(v.right), nullptr, nrhs, INT_MAX, nullptr};
+      g.C = Seg{Wv(t), nullptr, nrhs, INT_MAX, nullptr};
+      g.D = SegOut{Z(v.left), nullptr, nrhs, INT_MAX, nullptr};
+      gd.push_back(g);
+      // z_b = B_ba y_a (+ w bottom)
+      g.M = c.kr;
+      g.K = a.kc;
+      g.A = v.B21;
+      g.lda = a.kc;
+      g.B = Seg{Y(v.left), nullptr, nrhs, INT_MAX, nullptr};
+      g.C = Seg{Wv(t) + (long long)a.kr * nrhs, nullptr, nrhs, INT_MAX, nullptr};
+      g.D = SegOut{Z(v.right), nullptr, nrhs, INT_MAX, nullptr};
+      gd.push_back(g);
+    }
+    HIPCHK(launch_gemm_batched(gd.data(), (int)gd.size(), H.staging, s));
+  }
+  // leaves: b(I) = U z + D x(I)
+  gd.clear();
+  for (int t : H.leaves) {
+    const Node& v = nd[t];
+    GemmDesc g{};
+    g.M = v.kr;
+    g.N = nrhs;
+    g.K = 0;
+    g.C = Seg{Z(t), nullptr, nrhs, INT_MAX, nullptr};
+    g.D = SegOut{Wv(t), nullptr, nrhs, INT_MAX, v.perm_r};
+    g.alpha = g.beta = 1.0;
+    gd.push_back(g);
+    GemmDesc e{};
+    e.M = v.mr - v.kr;
+    e.N = nrhs;
+    e.K = v.kr;
+    e.A = v.Er;
+    e.lda = v.kr;
+    e.B = Seg{Z(t), nullptr, nrhs, INT_MAX, nullptr};
+    e.D = SegOut{Wv(t), nullptr, nrhs, INT_MAX, v.perm_r + v.kr};
+    e.alpha = 1.0;
+    gd.push_back(e);
+  }
+  HIPCHK(launch_gemm_batched(gd.data(), (int)gd.size(), H.staging, s));
+  gd.clear();
+  for (int t : H.leaves) {
+    const Node& v = nd[t];
+    GemmDesc g{};
+    g.M = g.K = v.size();
+    g.N = nrhs;
+    g.A = v.D;
+    g.lda = v.size();
+    g.B = Seg{x + (long long)v.lo * ldx, nullptr, ldx, INT_MAX, nullptr};
+    g.C = Seg{Wv(t), nullptr, nrhs, INT_MAX, nullptr};
+    g.D = SegOut{b + (long long)v.lo * ldb, nullptr, ldb, INT_MAX, nullptr};
+    g.alpha = g.beta = 1.0;
+    gd.push_back(g);
+  }
+  HIPCHK(launch_gemm_batched(gd.data(), (int)gd.size(), H.staging, s));
+  // the descriptor tables live in the staging area until the copies ran
+  HIPCHK(hipStreamSynchronize(s));
+  H.staging.reset();
+  return HSS_OK;
+}
+
+}  // namespace hss
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+const char* hss_last_error(void) { return g_err.c_str(); }
+
+void hss_default_opts(hss_opts* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->rtol = 1e-6;
+  o->d0 = 64;
+  o->dd = 32;
+  o->d_max = 4096;
+  o->p_margin = 10;
+  o->seed = 0;
+  o->leaf_size = 64;
+  o->sample_prec = HSS_SAMPLE_F64;
+}
+
+hss_status hss_compress(const void* A, int dtype, long long n, long long lda,
+                        const hss_tree* tree, const hss_opts* opts, void* stream,
+                        hss_handle* out) {
+  g_err.clear();
+  if (!out) return fail(HSS_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  if (!A || n < 1 || lda < n) return fail(HSS_ERR_ARG, "A, n or lda invalid");
+  if (dtype != HSS_F64 && dtype != HSS_F32) return fail(HSS_ERR_ARG, "dtype");
+  if (n > INT_MAX / 2) return fail(HSS_ERR_ARG, "n too large");
+  hss_opts o;
+  if (opts) o = *opts;
+  else hss_default_opts(&o);
+  if (!(o.rtol >= 0.0) || o.d0 < 1 || o.dd < 1 || o.d_max < o.d0 || o.p_margin < 0)
+    return fail(HSS_ERR_ARG, "rtol / d0 / dd / d_max / p_margin invalid");
+  if (o.sample_prec != HSS_SAMPLE_F64) return fail(HSS_ERR_ARG, "unsupported sample precision");
+  if ((o.R_user_r == nullptr) != (o.R_user_c == nullptr))
+    return fail(HSS_ERR_ARG, "R_user_r and R_user_c must both be given or both NULL");
+  if (o.R_user_r && o.ld_R_user < o.d_max) return fail(HSS_ERR_ARG, "ld_R_user < d_max");
+  hss_handle_s* p = nullptr;
+  CHK(new_handle(out, n, static_cast<hipStream_t>(stream), &p));
+  Handle& H = p->h;
+  H.dtype = dtype;
+  H.opts = o;
+  hss_status st = build_tree(H, n, tree, o.leaf_size);
+  if (st == HSS_OK) st = compress_impl(H, A, lda);
+  if (st != HSS_OK && st != HSS_NOT_CONVERGED) {
+    const std::string msg = g_err;
+    free_handle(p);
+    g_err = msg;
+    return st;
+  }
+  *out = p;
+  return st;
+}
+
+hss_status hss_matvec(hss_handle h, int nrhs, const double* x, long long ldx, double* b,
+                      long long ldb, void* stream) {
+  g_err.clear();
+  if (!h || !h->h.compressed) return fail(HSS_ERR_STATE, "handle not compressed");
+  if (nrhs < 0 || ldx < nrhs || ldb < nrhs) return fail(HSS_ERR_ARG, "nrhs / ldx / ldb");
+  if (nrhs == 0) return HSS_OK;
+  if (!x || !b) return fail(HSS_ERR_ARG, "x or b is NULL");
+  const Handle& H = h->h;
+  const char* xb = reinterpret_cast<const char*>(x);
+  const char* bb = reinterpret_cast<const char*>(b);
+  const long long xe = ((H.n - 1) * ldx + nrhs) * 8, be = ((H.n - 1) * ldb + nrhs) * 8;
+  if (xb < bb + be && bb < xb + xe) return fail(HSS_ERR_ARG, "x and b overlap");
+  return matvec_impl(h->h, nrhs, x, ldx, b, ldb, static_cast<hipStream_t>(stream));
+}
+
+hss_status hss_stats(hss_handle h, hss_stats_t* st) {
+  if (!h || !st) return fail(HSS_ERR_ARG, "NULL argument");
+  const Handle& H = h->h;
+  std::memset(st, 0, sizeof(*st));
+  st->n = H.n;
+  st->n_nodes = (int)H.nodes.size();
+  st->height = H.height;
+  st->d_final = H.d;
+  st->passes = H.passes;
+  st->converged = H.converged ? 1 : 0;
+  int mx = 0;
+  for (size_t t = 1; t < H.nodes.size(); ++t) mx = std::max(mx, std::max(H.nodes[t].kr, H.nodes[t].kc));
+  st->max_rank = mx;
+  st->generator_bytes = H.generator_bytes();
+  st->sample_flops = 4.0 * (double)H.n * (double)H.n * (double)H.d;
+  st->t_total_ms = H.t_total;
+  st->t_sample_ms = H.t_sample;
+  st->t_levels_ms = H.t_levels;
+  st->t_id_ms = H.t_id;
+  return HSS_OK;
+}
+
+hss_status hss_ranks(hss_handle h, int* kr, int* kc, int* mr, int* mc) {
+  if (!h) return fail(HSS_ERR_ARG, "NULL handle");
+  const Handle& H = h->h;
+  for (size_t t = 0; t < H.nodes.size(); ++t) {
+    const Node& v = H.nodes[t];
+    if (kr) kr[t] = t ? v.kr : 0;
+    if (kc) kc[t] = t ? v.kc : 0;
+    if (mr) mr[t] = v.leaf() ? v.size() : v.mr;
+    if (mc) mc[t] = v.leaf() ? v.size() : v.mc;
+  }
+  return HSS_OK;
+}
+
+hss_status hss_export_node(hss_handle h, int node, hss_node_generators* g) {
+  if (!h || !g) return fail(HSS_ERR_ARG, "NULL argument");
+  Handle& H = h->h;
+  if (node < 0 || node >= (int)H.nodes.size()) return fail(HSS_ERR_ARG, "node out of range");
+  const Node& v = H.nodes[node];
+  HIPCHK(hipStreamSynchronize(H.stream));
+  if (node != 0) {
+    if (g->Jr && v.kr) HIPCHK(hipMemcpy(g->Jr, v.perm_r, (size_t)v.kr * 4, hipMemcpyDeviceToHost));
+    if (g->Jc && v.kc) HIPCHK(hipMemcpy(g->Jc, v.perm_c, (size_t)v.kc * 4, hipMemcpyDeviceToHost));
+    if (g->Er && v.kr && v.mr > v.kr)
+      HIPCHK(hipMemcpy(g->Er, v.Er, (size_t)(v.mr - v.kr) * v.kr * 8, hipMemcpyDeviceToHost));
+    if (g->Ec && v.kc && v.mc > v.kc)
+      HIPCHK(hipMemcpy(g->Ec, v.Ec, (size_t)(v.mc - v.kc) * v.kc * 8, hipMemcpyDeviceToHost));
+    if (g->Ir && v.kr && v.Ir) HIPCHK(hipMemcpy(g->Ir, v.Ir, (size_t)v.kr * 4, hipMemcpyDeviceToHost));
+    if (g->Ic && v.kc && v.Ic) HIPCHK(hipMemcpy(g->Ic, v.Ic, (size_t)v.kc * 4, hipMemcpyDeviceToHost));
+  }
+  if (v.leaf() && g->D)
+    HIPCHK(hipMemcpy(g->D, v.D, (size_t)v.size() * v.size() * 8, hipMemcpyDeviceToHost));
+  if (!v.leaf()) {
+    const Node& a = H.nodes[v.left];
+    const Node& c = H.nodes[v.right];
+    if (g->B12 && a.kr && c.kc)
+      HIPCHK(hipMemcpy(g->B12, v.B12, (size_t)a.kr * c.kc * 8, hipMemcpyDeviceToHost));
+    if (g->B21 && c.kr && a.kc)
+      HIPCHK(hipMemcpy(g->B21, v.B21, (size_t)c.kr * a.kc * 8, hipMemcpyDeviceToHost));
+  }
+  return HSS_OK;
+}
+
+hss_status hss_import(long long n, const hss_tree* tree, const int* kr, const int* kc,
+                      const hss_node_generators* nodes, hss_handle* out) {
+  g_err.clear();
+  if (!out || !tree || !kr || !kc || !nodes || n < 1) return fail(HSS_ERR_ARG, "NULL argument");
+  *out = nullptr;
+  hss_handle_s* p = nullptr;
+  CHK(new_handle(out, n, nullptr, &p));
+  Handle& H = p->h;
+  hss_status st = build_tree(H, n, tree, 1);
+  if (st != HSS_OK) {
+    free_handle(p);
+    return st;
+  }
+  std::vector<Node>& nd = H.nodes;
+  auto bad = [&](const char* m) {
+    free_handle(p);
+    return fail(HSS_ERR_ARG, m);
+  };
+  // sizes bottom-up
+  std::vector<int> order;
+  for (int h = 0; h < H.height; ++h)
+    for (int t : H.levels[h]) order.push_back(t);
+  order.push_back(0);
+  for (int t : order) {
+    Node& v = nd[t];
+    if (v.leaf()) v.mr = v.mc = v.size();
+    else {
+      v.mr = nd[v.left].kr + nd[v.right].kr;
+      v.mc = nd[v.left].kc + nd[v.right].kc;
+    }
+    if (t != 0) {
+      v.kr = kr[t];
+      v.kc = kc[t];
+      if (v.kr < 0 || v.kc < 0 || v.kr > v.mr || v.kc > v.mc) return bad("rank out of range");
+    }
+  }
+  for (int t : order) {
+    Node& v = nd[t];
+    const hss_node_generators& g = nodes[t];
+    if (v.leaf()) {
+      v.D = arena_alloc<double>(H, (size_t)v.size() * v.size());
+      if (!v.D || !g.D) return bad("leaf D missing");
+      if (hipMemcpy(v.D, g.D, (size_t)v.size() * v.size() * 8, hipMemcpyHostToDevice) != hipSuccess)
+        return bad("copy D");
+    } else {
+      const Node& a = nd[v.left];
+      const Node& c = nd[v.right];
+      v.B12 = arena_alloc<double>(H, (size_t)a.kr * c.kc);
+      v.B21 = arena_alloc<double>(H, (size_t)c.kr * a.kc);
+      if ((a.kr * c.kc && !g.B12) || (c.kr * a.kc && !g.B21)) return bad("B missing");
+      if (a.kr * c.kc) hipMemcpy(v.B12, g.B12, (size_t)a.kr * c.kc * 8, hipMemcpyHostToDevice);
+      if (c.kr * a.kc) hipMemcpy(v.B21, g.B21, (size_t)c.kr * a.kc * 8, hipMemcpyHostToDevice);
+    }
+    if (t == 0) continue;
+    for (int side = 0; side < 2; ++side) {
+      const int m = side ? v.mc : v.mr, k = side ? v.kc : v.kr;
+      const int* J = side ? g.Jc : g.Jr;
+      const double* E = side ? g.Ec : g.Er;
+      if (k && !J) return bad("J missing");
+      if (k && m > k && !E) return bad("E missing");
+      std::vector<int> perm;
+      std::vector<char> sel(m, 0);
+      for (int q = 0; q < k; ++q) {
+        if (J[q] < 0 || J[q] >= m || sel[J[q]]) return bad("J is not a set of distinct rows");
+        sel[J[q]] = 1;
+        perm.push_back(J[q]);
+      }
+      for (int q = 0; q < m; ++q)
+        if (!sel[q]) perm.push_back(q);
+      int* dp = arena_alloc<int>(H, (size_t)m);
+      double* de = arena_alloc<double>(H, (size_t)(m - k) * k + 1);
+      if (!dp || !de) return bad("alloc");
+      if (m) hipMemcpy(dp, perm.data(), (size_t)m * 4, hipMemcpyHostToDevice);
+      if ((m - k) * k) hipMemcpy(de, E, (size_t)(m - k) * k * 8, hipMemcpyHostToDevice);
+      if (side) {
+        v.perm_c = dp;
+        v.Ec = de;
+      } else {
+        v.perm_r = dp;
+        v.Er = de;
+      }
+    }
+    v.state = HSS_COMPRESSED;
+  }
+  H.compressed = true;
+  H.d = 0;
+  *out = p;
+  return HSS_OK;
+}
+
+void hss_destroy(hss_handle h) { free_handle(h); }
+
+hss_status hss_random_normal(unsigned long long seed, int which, long long n, int col0, int col1,
+                             double* R, long long ld, void* stream) {
+  g_err.clear();
+  if (n < 0 || col0 < 0 || col1 < col0 || (n > 0 && !R) || ld < col1 - col0 || (which != 0 && which != 1))
+    return fail(HSS_ERR_ARG, "random_normal arguments");
+  launch_random_normal(seed, which, n, col0, col1, R, ld, static_cast<hipStream_t>(stream));
+  HIPCHK(hipGetLastError());
+  return HSS_OK;
+}
+
+hss_status hss_sample(const void* A, int dtype, long long n, long long lda, const int* leaf_of,
+                      int ncols, const double* Rr, const double* Rc, long long ldr, double* Sr,
+                      double* Sc, long long lds, void* stream) {
+  g_err.clear();
+  if (!A || n < 1 || lda < n || ncols < 0 || ldr < ncols || lds < ncols)
+    return fail(HSS_ERR_ARG, "sample arguments");
+  if ((Sr == nullptr) != (Rr == nullptr) || (Sc == nullptr) != (Rc == nullptr))
+    return fail(HSS_ERR_ARG, "S and R must be given together");
+  if (dtype != HSS_F64 && dtype != HSS_F32) return fail(HSS_ERR_ARG, "dtype");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const long long wd = sample_workspace_doubles(n, ncols);
+  double* work = nullptr;
+  if (wd > 0) HIPCHK(hipMallocAsync(reinterpret_cast<void**>(&work), (size_t)wd * 8, s));
+  launch_sample(A, dtype, n, lda, leaf_of, ncols, Rr, Rc, ldr, Sr, Sc, lds, work, s);
+  hipError_t e = hipGetLastError();
+  if (work) hipFreeAsync(work, s);
+  HIPCHK(e);
+  return HSS_OK;
+}
+
+hss_status hss_id_batched(int nprob, const double* const* ys, const int* m, const int* d,
+                          const long long* ldy, double rtol, int* const* perms,
+                          double* const* es, int* k, void* stream) {
+  g_err.clear();
+  if (nprob < 0 || (nprob > 0 && (!ys || !m || !d || !ldy || !perms || !es || !k)))
+    return fail(HSS_ERR_ARG, "id arguments");
+  if (nprob == 0) return HSS_OK;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  std::vector<IdProblem> pr(nprob);
+  std::vector<long long> offs(nprob);
+  long long wtot = 0, mtot = 0;
+  for (int q = 0; q < nprob; ++q) {
+    if (m[q] < 0 || d[q] < 0 || (m[q] > 0 && d[q] > 0 && ldy[q] < d[q]))
+      return fail(HSS_ERR_ARG, "problem sizes");
+    pr[q].Y = ys[q];
+    pr[q].ldy = ldy[q];
+    pr[q].m = m[q];
+    pr[q].d = d[q];
+    pr[q].ldw = std::max(d[q], 1);
+    pr[q].perm = perms[q];
+    pr[q].E = es[q];
+    pr[q].kfail = -1;
+    offs[q] = mtot;
+    mtot += m[q];
+    wtot += (long long)m[q] * pr[q].ldw;
+  }
+  Staging st;
+  HIPCHK(st.init((size_t)1 << 20, s));
+  char* base = nullptr;
+  const size_t wbytes = round_up((size_t)wtot * 8 + 8, 256), sbytes = round_up((size_t)mtot * 4 + 4, 256);
+  const size_t nbytes = round_up((size_t)mtot * 8 + 8, 256), kbytes = round_up((size_t)nprob * 4, 256);
+  hipError_t e = hipMalloc(reinterpret_cast<void**>(&base), wbytes + sbytes + nbytes + kbytes);
+  if (e != hipSuccess) {
+    st.release();
+    return fail(HSS_ERR_ALLOC, "id workspace");
+  }
+  long long wo = 0;
+  for (int q = 0; q < nprob; ++q) {
+    pr[q].W = reinterpret_cast<double*>(base) + wo;
+    wo += (long long)pr[q].m * pr[q].ldw;
+  }
+  int* kdev = reinterpret_cast<int*>(base + wbytes + sbytes + nbytes);
+  e = launch_id_batched(pr.data(), nprob, rtol, kdev, reinterpret_cast<int*>(base + wbytes),
+                        reinterpret_cast<double*>(base + wbytes + sbytes), offs.data(), st, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(k, kdev, (size_t)nprob * 4, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  hipFree(base);
+  st.release();
+  HIPCHK(e);
+  return HSS_OK;
+}
+
+}  // extern "C"

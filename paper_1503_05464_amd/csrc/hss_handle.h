@@ -1,0 +1,104 @@
+// Host-side state of an HSS handle: tree, per-node generators (device
+// pointers into the handle's arena), compression bookkeeping and workspaces.
+#pragma once
+
+#include <string>
+#include <vector>
+
+#include "../../include/hss.h"
+#include "hss_internal.h"
+
+namespace hss {
+
+// Device memory owned by a handle: large chunks, bump-allocated, 256-byte
+// aligned, released together.
+struct Arena {
+  std::vector<void*> chunks;
+  char* cur = nullptr;
+  size_t left = 0;
+  size_t total = 0;
+  void* alloc(size_t bytes);
+  void release();
+};
+
+// A growable device buffer reused between launches (freed and reallocated
+// larger when needed; hipFree synchronises the device).
+struct Scratch {
+  void* p = nullptr;
+  size_t cap = 0;
+  void* ensure(size_t bytes);
+  void release();
+};
+
+struct Node {
+  int lo = 0, hi = 0, left = -1, right = -1, parent = -1, height = 0;
+  bool leaf() const { return left < 0; }
+  int size() const { return hi - lo; }
+  // compression state
+  int state = HSS_UNTOUCHED;
+  int cdone = 0;        // columns of the local samples / R_tau computed
+  bool set_up = false;  // sizes fixed, D or B gathered, buffers allocated
+  int mr = 0, mc = 0;   // rows of S^r_loc, S^c_loc (and of U, V)
+  int kr = 0, kc = 0;   // ranks of U, V
+  double* Sr = nullptr;  // local samples, mr x ldg (leaf: rows of the global S)
+  double* Sc = nullptr;
+  double* Rr = nullptr;  // R^r_tau = V^T R^r_in, kc x ldg
+  double* Rc = nullptr;  // R^c_tau = U^T R^c_in, kr x ldg
+  int* perm_r = nullptr;  // mr: J^r (pivot order) then the rest (increasing)
+  int* perm_c = nullptr;
+  double* Er = nullptr;   // (mr-kr) x kr
+  double* Ec = nullptr;   // (mc-kc) x kc
+  int* Ir = nullptr;      // global row skeleton (kr)
+  int* Ic = nullptr;      // global column skeleton (kc)
+  double* D = nullptr;    // leaf: size x size
+  double* B12 = nullptr;  // inner: kr_a x kc_b
+  double* B21 = nullptr;  // inner: kr_b x kc_a
+  // ULV factors (Alg. 3); all row-major FP64
+  double* Wt = nullptr;   // W_t = D_tau(rest) - E D_tau(J): (m-k) x m, then LQ data
+  double* Wb = nullptr;   // W_b = D_tau(J): k x m
+  double* tauq = nullptr; // Householder scalars of the LQ (m-k)
+  double* Vt = nullptr;   // Vt = Q Vh: m x kc
+  double* Dt = nullptr;   // Dt = W_b Q_b^T: k x k
+  double* Dm = nullptr;   // D_tau of an inner node (merged), m x m
+};
+
+struct Handle {
+  long long n = 0;
+  int dtype = HSS_F64;
+  hss_opts opts{};
+  std::vector<Node> nodes;
+  int height = 0;                        // height of the root
+  std::vector<std::vector<int>> levels;  // non-root nodes by height
+  std::vector<int> leaves;               // leaves in index order
+  Arena arena;
+  Scratch work_id, work_sample, work_mv, work_misc;
+  Staging staging;
+  hipStream_t stream = nullptr;
+  // global random matrices and samples, n x ldg
+  double* Rr = nullptr;
+  double* Rc = nullptr;
+  double* Sr = nullptr;
+  double* Sc = nullptr;
+  long long ldg = 0;
+  int* leaf_of = nullptr;
+  int* k_host = nullptr;  // pinned readback of ranks
+  int k_host_cap = 0;
+  // results
+  int d = 0;
+  int passes = 0;
+  bool converged = true;
+  bool compressed = false;
+  bool factored = false;
+  double t_total = 0, t_sample = 0, t_levels = 0, t_id = 0;
+  // ULV root LU (host-driven, device data)
+  double* root_lu = nullptr;
+  int* root_piv = nullptr;
+  int root_m = 0;
+  long long generator_bytes() const;
+};
+
+}  // namespace hss
+
+struct hss_handle_s {
+  hss::Handle h;
+};

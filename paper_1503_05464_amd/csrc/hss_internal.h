@@ -1,0 +1,128 @@
+// Internal declarations shared by the host orchestration and the HIP
+// kernels of the randomized HSS library (gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace hss {
+
+// ---------------------------------------------------------------------------
+// Staging of per-launch descriptor tables: a pinned host buffer and its
+// device mirror, bump-allocated.  push() writes into the pinned buffer and
+// queues the copy on the stream; regions are only reused after a stream
+// synchronisation (reset), so no queued copy ever reads a rewritten region.
+// ---------------------------------------------------------------------------
+struct Staging {
+  char* host = nullptr;
+  char* dev = nullptr;
+  size_t cap = 0;
+  size_t used = 0;
+  hipStream_t stream = nullptr;
+  hipError_t init(size_t bytes, hipStream_t s);
+  void release();
+  // returns the device address of the copied table, or nullptr on failure
+  void* push(const void* src, size_t bytes);
+  void reset() { used = 0; }
+};
+
+// ---------------------------------------------------------------------------
+// Random matrices: Philox4x64-10 + Box-Muller (kernels_rng.hip)
+// ---------------------------------------------------------------------------
+void launch_random_normal(unsigned long long seed, int which, long long n, int col0, int col1,
+                          double* R, long long ld, hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// Sampling products on FP64 MFMA (kernels_sample.hip)
+//   Sr = (A - M) Rr, Sc = (A - M)^T Rc, M = leaf diagonal blocks if leaf_of
+// `work` must hold sample_workspace_doubles(n, ncols) doubles (split-K
+// partial sums); it may be null when that size is 0.
+// ---------------------------------------------------------------------------
+long long sample_workspace_doubles(long long n, int ncols);
+void launch_sample(const void* A, int dtype, long long n, long long lda, const int* leaf_of,
+                   int ncols, const double* Rr, const double* Rc, long long ldr, double* Sr,
+                   double* Sc, long long lds, double* work, hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// Batched FP64 GEMM with row gathers / scatters (kernels_gemm.hip)
+//   D[rowD(r), c] = beta * C[rowC(r), c] + alpha * sum_k Aop(r, k) B[rowB(k), c]
+// for r < M, c < N.  Aop(r, k) = A[r*lda + k] or, if transA, A[k*lda + r].
+// A "segmented" source X with rows split at `split`: row q < split lives at
+// X0 + q*ld, row q >= split at X1 + (q - split)*ld.  Maps are optional.
+// ---------------------------------------------------------------------------
+struct Seg {
+  const double* p0;
+  const double* p1;
+  long long ld;
+  int split;   // rows >= split come from p1 (split = INT_MAX: single segment)
+  const int* map;  // optional logical-row -> segmented-row map
+};
+struct SegOut {
+  double* p0;
+  double* p1;
+  long long ld;
+  int split;
+  const int* map;
+};
+struct GemmDesc {
+  int M, N, K;
+  const double* A;
+  long long lda;
+  int transA;
+  Seg B;
+  Seg C;
+  SegOut D;
+  double alpha, beta;
+};
+// Runs all problems of `descs` (host array) in one launch.
+hipError_t launch_gemm_batched(const GemmDesc* descs, int nprob, Staging& st, hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// Batched interpolative decomposition (kernels_qrcp.hip)
+// ---------------------------------------------------------------------------
+struct IdProblem {
+  const double* Y;   // rows of Y^T: m rows, d columns, leading dimension ldy
+  long long ldy;
+  int m, d;
+  double* W;         // workspace m x d (ld = ldw), overwritten with R data
+  long long ldw;
+  int* perm;         // m entries out: J (pivot order) then rest (increasing)
+  double* E;         // (m-k) x k out (row-major, ld = k)
+  int kfail;         // early exit once k > kfail and k < m is certain (-1: never)
+};
+// k_dev: device int array of nprob ranks (out).  step_dev / nrm_dev: device
+// int / double arrays of sum(m) entries (pivot step of every column, and the
+// column norms), problem p using the entries from offs[p] (host prefix sums).
+hipError_t launch_id_batched(const IdProblem* probs, int nprob, double rtol, int* k_dev,
+                             int* step_dev, double* nrm_dev, const long long* offs, Staging& st,
+                             hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// Small helpers (kernels_misc.hip)
+// ---------------------------------------------------------------------------
+struct GatherDesc {   // out[r*ldo + c] = A[rows[r]*lda + cols[c]] (widened)
+  const int* rows;
+  const int* cols;
+  int nr, nc;
+  double* out;
+  long long ldo;
+  int row_off, col_off;  // added to rows/cols (for contiguous ranges: rows = null)
+};
+hipError_t launch_gather(const void* A, int dtype, long long lda, const GatherDesc* descs,
+                         int nprob, Staging& st, hipStream_t s);
+
+struct IndexDesc {    // out[a] = base(perm[a]) for a < k; base(q) = q < split ? b0[q] (or q+off0) : b1[q-split]
+  const int* perm;
+  int k;
+  const int* b0;
+  const int* b1;
+  int split;
+  int off0;           // used when b0 == null: base(q) = off0 + q
+  int* out;
+};
+hipError_t launch_index_compose(const IndexDesc* descs, int nprob, Staging& st, hipStream_t s);
+
+void launch_leaf_of(int n_leaves, const int* lo_dev, const int* hi_dev, int* leaf_of, hipStream_t s);
+
+}  // namespace hss

@@ -1,0 +1,59 @@
+"""CPU checks of the C ABI boundary: the shared library loads (no GPU
+needed to load it) and exports every function include/hss.h declares; the
+Python binding keeps the C names; argument errors are rejected on the host
+before any device work."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_1503_05464_amd as P
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "hss.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = set(re.findall(r"\b(hss_[a-z_]+)\s*\(", src))
+    return sorted(names)
+
+
+def test_library_exports_every_declared_symbol():
+    if not os.path.exists(P.LIB_PATH):
+        pytest.fail("libhss.so not built: run __graft_entry__.build()")
+    lib = ctypes.CDLL(P.LIB_PATH)
+    declared = _declared()
+    assert "hss_compress" in declared and "hss_solve" in declared
+    for name in declared:
+        assert hasattr(lib, name), name
+    assert sorted(P.EXPORTED) == declared
+    for name in declared:
+        assert callable(getattr(P, name, None)) or name == "hss_last_error", name
+
+
+def test_host_side_argument_errors():
+    L = P.lib()
+    out = ctypes.c_void_p()
+    # NULL A / bad sizes: rejected before touching the device
+    st = L.hss_compress(None, 0, 10, 10, None, None, None, ctypes.byref(out))
+    assert st == P.HSS_ERR_ARG and out.value is None
+    assert b"invalid" in L.hss_last_error()
+    st = L.hss_compress(ctypes.c_void_p(16), 7, 10, 10, None, None, None, ctypes.byref(out))
+    assert st == P.HSS_ERR_ARG
+    o = P.hss_default_opts()
+    assert (o.rtol, o.d0, o.dd, o.d_max, o.p_margin, o.leaf_size) == (1e-6, 64, 32, 4096, 10, 64)
+    o.d0 = 0
+    st = L.hss_compress(ctypes.c_void_p(16), 0, 10, 10, None, ctypes.byref(o), None, ctypes.byref(out))
+    assert st == P.HSS_ERR_ARG
+    assert L.hss_matvec(None, 1, None, 1, None, 1, None) == P.HSS_ERR_STATE
+    assert L.hss_random_normal(0, 3, 10, 0, 1, ctypes.c_void_p(16), 1, None) == P.HSS_ERR_ARG
+    assert L.hss_id_batched(-1, None, None, None, None, 0.1, None, None, None, None) == P.HSS_ERR_ARG
+
+
+def test_missing_library_fails_loudly(monkeypatch):
+    monkeypatch.setattr(P, "_lib", None)
+    monkeypatch.setattr(P, "LIB_PATH", "/nonexistent/libhss.so")
+    with pytest.raises(RuntimeError, match="no fallback"):
+        P.lib()

@@ -1,0 +1,107 @@
+"""GPU parity of the building blocks against the oracle, through the C ABI.
+
+Tolerances (FP64, u = 2^-53):
+* random matrices: the same Philox words on both sides; the Box-Muller
+  log/sqrt/cos/sin may differ by a few ulps -> |diff| <= 1e-14 max(1, |z|);
+* sampling: a dot product of length K has error <= gamma_K |A||R| with
+  gamma_K = K u / (1 - K u) in any summation order, so two correct
+  implementations differ by at most 2 gamma_K (|A||R|) entrywise;
+* ID: inputs with well separated column norms have unique pivots -> J and k
+  equal exactly; E = (R1^{-1} R2)^T agrees to 1e-10 relative (the QR
+  factors differ by rounding, amplified by cond(R1)).
+"""
+import numpy as np
+import pytest
+import torch
+
+import paper_1503_05464_amd as P
+import workloads as W
+from oracle import hss as ohss
+from oracle import interp, philox
+from oracle.tree import bisection_tree
+
+pytestmark = pytest.mark.gpu
+U = 2.0 ** -53
+
+
+def _gamma(k):
+    return k * U / (1 - k * U)
+
+
+@pytest.mark.parametrize("n,c0,c1", [(1, 0, 1), (1001, 3, 70), (4096, 0, 128), (777, 64, 96)])
+def test_random_normal_matches_oracle(n, c0, c1):
+    print(f"random_normal n={n} cols=[{c0},{c1})", flush=True)
+    for which in (0, 1):
+        g = P.hss_random_normal(7, which, n, c0, c1).cpu().numpy()
+        ref = philox.gaussian_columns(7, which, n, c0, c1)
+        assert np.all(np.abs(g - ref) <= 1e-14 * np.maximum(1.0, np.abs(ref)))
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("n,ncols,masked", [(1000, 64, False), (1000, 100, True), (2048, 128, True),
+                                            (300, 7, True), (4500, 64, False)])
+def test_sample_matches_oracle(dtype, n, ncols, masked):
+    print(f"sample n={n} ncols={ncols} masked={masked} dtype={dtype}", flush=True)
+    g = np.random.default_rng(n + ncols)
+    A = W.toeplitz_inverse_distance(n) + 0.3 * g.standard_normal((n, n)) / np.sqrt(n)
+    A = A.astype(np.float32 if dtype == torch.float32 else np.float64)
+    A64 = A.astype(np.float64)
+    Rr = g.standard_normal((n, ncols))
+    Rc = g.standard_normal((n, ncols))
+    Ad = torch.from_numpy(A).cuda()
+    tree = bisection_tree(n, 64)
+    leaf_of = None
+    if masked:
+        lo = np.zeros(n, dtype=np.int32)
+        for q, t in enumerate(sorted(tree.leaves(), key=lambda t: tree.lo[t])):
+            lo[tree.lo[t]:tree.hi[t]] = q
+        leaf_of = torch.from_numpy(lo).cuda()
+    Sr, Sc = P.hss_sample(Ad, torch.from_numpy(Rr).cuda(), torch.from_numpy(Rc).cuda(), leaf_of)
+    torch.cuda.synchronize()
+    ref_r, ref_c = ohss.sample(A64, Rr, Rc)
+    absA = np.abs(A64)
+    if masked:
+        ref_r, ref_c = ohss.leaf_local_samples(A64, tree, ref_r, ref_c, Rr, Rc)
+    bound_r = 2 * _gamma(n) * (absA @ np.abs(Rr)) + 1e-300
+    bound_c = 2 * _gamma(n) * (absA.T @ np.abs(Rc)) + 1e-300
+    # the masked oracle subtracts D R afterwards: add that product's error too
+    if masked:
+        bound_r *= 2
+        bound_c *= 2
+    assert np.all(np.abs(Sr.cpu().numpy() - ref_r) <= bound_r)
+    assert np.all(np.abs(Sc.cpu().numpy() - ref_c) <= bound_c)
+
+
+def _separated(d, m, seed, rank=None):
+    g = np.random.default_rng(seed)
+    y = g.standard_normal((d, m))
+    if rank is not None:
+        y = g.standard_normal((d, rank)) @ g.standard_normal((rank, m))
+    scale = 2.0 ** (-np.arange(m) * 0.37)
+    return y * scale[g.permutation(m)]
+
+
+@pytest.mark.parametrize("rtol", [1e-2, 1e-6, 1e-12])
+def test_id_batched_matches_oracle(rtol):
+    cases = [(12, 8, None), (8, 12, None), (64, 300, None), (130, 257, None), (1, 5, None),
+             (5, 1, None), (40, 25, 6), (200, 64, None), (3, 3, 0)]
+    Ys, refs = [], []
+    for q, (d, m, rank) in enumerate(cases):
+        y = _separated(d, m, 100 + q, rank) if rank != 0 else np.zeros((d, m))
+        refs.append(interp.interpolative_decomposition(y, rtol))
+        Ys.append(torch.from_numpy(np.ascontiguousarray(y.T)).cuda())  # rows = columns of Y
+    print(f"id_batched rtol={rtol} problems={len(cases)}", flush=True)
+    got = P.hss_id_batched(Ys, rtol)
+    for (k, perm, E), ref, (d, m, rank) in zip(got, refs, cases):
+        assert k == ref.k, (d, m, rank)
+        assert list(perm[:k]) == list(ref.J)
+        assert list(perm[k:]) == list(ref.rest)
+        if E.size:
+            assert np.allclose(E, ref.E, rtol=1e-10, atol=1e-10 * max(1.0, np.abs(ref.E).max()))
+
+
+def test_id_ties_take_lowest_index():
+    y = np.eye(6)[:, [3, 1, 5, 0, 2, 4]] * 2.0
+    got = P.hss_id_batched([torch.from_numpy(np.ascontiguousarray(y.T)).cuda()], 1e-8)[0]
+    ref = interp.interpolative_decomposition(y, 1e-8)
+    assert got[0] == ref.k == 6 and list(got[1]) == list(ref.J) == [0, 1, 2, 3, 4, 5]
