@@ -150,6 +150,10 @@ typedef struct {
   double t_sample_ms;          /* random matrices + sampling products */
   double t_levels_ms;          /* local samples, IDs, updates */
   double t_id_ms;              /* pivoted QR + triangular solves */
+  int n_sample_launches;       /* launches of the sampling GEMM kernel */
+  double t_sample_gemm_ms;     /* their summed duration (HIP events on the stream) */
+  double sample_gemm_flops;    /* their algorithmic flops, 2 n^2 per column per side */
+  double sample_gemm_bytes;    /* their algorithmic bytes: A once per launch + R in + S out */
 } hss_stats_t;
 
 hss_status hss_stats(hss_handle h, hss_stats_t* st);

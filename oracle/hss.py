@@ -116,13 +116,20 @@ class _Sampler:
         sc = np.zeros((self.n, c1 - c0))
         for r0 in range(0, self.n, self.panel):
             r1 = min(self.n, r0 + self.panel)
-            blk = np.asarray(self.A[r0:r1], dtype=np.float64)
-            sr[r0:r1] = blk @ rr
-            sc += blk.T @ rc[r0:r1]
+            sr[r0:r1], part = sample_panel(self.A[r0:r1], rr, rc[r0:r1])
+            sc += part
         self.Rr = np.hstack([self.Rr, rr])
         self.Rc = np.hstack([self.Rc, rc])
         self.Sr = np.hstack([self.Sr, sr])
         self.Sc = np.hstack([self.Sc, sc])
+
+
+def sample_panel(A_rows, R_r, R_c_rows):
+    """One row panel P of the sampling products: S^r(P, :) = A(P, :) R^r and
+    the panel's share A(P, :)^T R^c(P, :) of S^c = A^T R^c.  A(P, :) may be
+    float32; it is widened exactly to float64."""
+    blk = np.asarray(A_rows, dtype=np.float64)
+    return blk @ R_r, blk.T @ R_c_rows
 
 
 def _fails(idr: IDResult, d: int, p_margin: int) -> bool:

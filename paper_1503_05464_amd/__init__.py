@@ -59,7 +59,8 @@ class hss_stats_t(C.Structure):
         ("passes", C.c_int), ("converged", C.c_int), ("max_rank", C.c_int),
         ("generator_bytes", C.c_longlong), ("sample_flops", C.c_double),
         ("t_total_ms", C.c_double), ("t_sample_ms", C.c_double), ("t_levels_ms", C.c_double),
-        ("t_id_ms", C.c_double),
+        ("t_id_ms", C.c_double), ("n_sample_launches", C.c_int), ("t_sample_gemm_ms", C.c_double),
+        ("sample_gemm_flops", C.c_double), ("sample_gemm_bytes", C.c_double),
     ]
 
 

@@ -11,6 +11,7 @@
 #include <climits>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -255,7 +256,7 @@ T* arena_alloc(Handle& H, size_t count) {
 // ---------------------------------------------------------------------------
 struct EventTimer {  // HIP events on the compression stream, summed at the end
   std::vector<hipEvent_t> ev;
-  std::vector<int> b, e, cat;  // begin index, end index, category (0 sample, 1 levels, 2 id)
+  std::vector<int> b, e, cat;  // begin, end, category (0 sample, 1 levels, 2 id, 3 sample GEMM)
   hipStream_t s = nullptr;
   int begin() {
     hipEvent_t x;
@@ -304,10 +305,17 @@ hss_status sample_columns(Handle& H, const void* A, long long lda, int c0, int c
     work = static_cast<double*>(H.work_sample.ensure((size_t)wd * 8));
     if (!work) return fail(HSS_ERR_ALLOC, "sampling workspace");
   }
+  const int evg = tm.begin();
   launch_sample(A, H.dtype, H.n, lda, H.leaf_of, nc, H.Rr + c0, H.Rc + c0, H.ldg, H.Sr + c0,
                 H.Sc + c0, H.ldg, work, H.stream);
   HIPCHK(hipGetLastError());
+  tm.end(evg, 3);
   tm.end(ev0, 0);
+  // two launches (S^r and S^c), each 2 n^2 nc flops; bytes: A once, R read, S written
+  H.n_sgemm += 2;
+  H.sgemm_flops += 4.0 * (double)H.n * (double)H.n * nc;
+  H.sgemm_bytes += 2.0 * ((double)H.n * (double)H.n * (H.dtype == HSS_F32 ? 4 : 8) +
+                          2.0 * (double)H.n * nc * 8);
   return HSS_OK;
 }
 
@@ -440,8 +448,6 @@ hss_status process_level(Handle& H, const void* A, long long lda, const std::vec
   if (!idn.empty()) {
     const int np = 2 * (int)idn.size();
     std::vector<IdProblem> pr(np);
-    std::vector<long long> offs(np);
-    long long wtot = 0, mtot = 0;
     for (int q = 0; q < np; ++q) {
       const Node& v = nd[idn[q / 2]];
       const bool rs = (q % 2) == 0;
@@ -450,30 +456,13 @@ hss_status process_level(Handle& H, const void* A, long long lda, const std::vec
       p.ldy = H.ldg;
       p.m = rs ? v.mr : v.mc;
       p.d = d;
-      p.ldw = d;
       p.perm = rs ? v.perm_r : v.perm_c;
       p.E = rs ? v.Er : v.Ec;
-      p.kfail = forced ? -1 : std::max(d - H.opts.p_margin, -1);
-      if (!forced && d - H.opts.p_margin < 0) p.kfail = -1;
-      offs[q] = mtot;
-      mtot += p.m;
-      wtot += (long long)p.m * d;
+      p.kfail = (forced || d - H.opts.p_margin < 0) ? -1 : d - H.opts.p_margin;
     }
-    const size_t wbytes = round_up((size_t)wtot * 8, 256);
-    const size_t sbytes = round_up((size_t)mtot * 4, 256);
-    const size_t nbytes = round_up((size_t)mtot * 8, 256);
-    const size_t kbytes = round_up((size_t)np * 4, 256);
-    char* base = static_cast<char*>(H.work_id.ensure(wbytes + sbytes + nbytes + kbytes));
-    if (!base) return fail(HSS_ERR_ALLOC, "ID workspace");
-    double* W = reinterpret_cast<double*>(base);
-    int* step = reinterpret_cast<int*>(base + wbytes);
-    double* nrm = reinterpret_cast<double*>(base + wbytes + sbytes);
-    int* kdev = reinterpret_cast<int*>(base + wbytes + sbytes + nbytes);
-    long long wo = 0;
-    for (int q = 0; q < np; ++q) {
-      pr[q].W = W + wo;
-      wo += (long long)pr[q].m * d;
-    }
+    const size_t wb = id_workspace_bytes(pr.data(), np);
+    void* wk = H.work_id.ensure(wb);
+    if (!wk) return fail(HSS_ERR_ALLOC, "ID workspace");
     if (H.k_host_cap < np) {
       if (H.k_host) hipHostFree(H.k_host);
       H.k_host = nullptr;
@@ -481,13 +470,11 @@ hss_status process_level(Handle& H, const void* A, long long lda, const std::vec
       H.k_host_cap = np * 2;
     }
     const int ev_id = tm.begin();
-    HIPCHK(launch_id_batched(pr.data(), np, H.opts.rtol, kdev, step, nrm, offs.data(), H.staging,
-                             H.stream));
-    tm.end(ev_id, 2);
-    HIPCHK(hipMemcpyAsync(H.k_host, kdev, (size_t)np * 4, hipMemcpyDeviceToHost, H.stream));
-    HIPCHK(hipStreamSynchronize(H.stream));
+    HIPCHK(launch_id_factor(pr.data(), np, H.opts.rtol, wk, H.work_id.cap, H.k_host, H.staging,
+                            H.stream));
     H.staging.reset();
     const int kf = d - H.opts.p_margin;
+    std::vector<int> sel;
     for (size_t q = 0; q < idn.size(); ++q) {
       Node& v = nd[idn[q]];
       const int kr = H.k_host[2 * q], kc = H.k_host[2 * q + 1];
@@ -506,7 +493,12 @@ hss_status process_level(Handle& H, const void* A, long long lda, const std::vec
       if (!v.Rr || !v.Rc || !v.Ir || !v.Ic) return fail(HSS_ERR_ALLOC, "node R / index buffers");
       v.state = HSS_COMPRESSED;
       passed.push_back(idn[q]);
+      sel.push_back(2 * (int)q);
+      sel.push_back(2 * (int)q + 1);
     }
+    HIPCHK(launch_id_finish(pr.data(), np, H.k_host, sel.data(), (int)sel.size(), wk, H.staging,
+                            H.stream));
+    tm.end(ev_id, 2);
   }
 
   // (4) skeleton index sets of the nodes compressed now: I_tau = I_in(J)
@@ -639,8 +631,17 @@ hss_status compress_impl(Handle& H, const void* A, long long lda) {
     for (int h = 0; h < H.height; ++h)
       CHK(process_level(H, A, lda, H.levels[h], ext, d, forced, any_fail, tm));
     bool done = true;
-    for (size_t t = 1; t < nd.size(); ++t)
+    int ncomp = 0, nmax = 0;
+    for (size_t t = 1; t < nd.size(); ++t) {
       if (nd[t].state != HSS_COMPRESSED) done = false;
+      else ++ncomp;
+      nmax = std::max(nmax, std::max(nd[t].kr, nd[t].kc));
+    }
+    if (H.verbose) {
+      std::fprintf(stderr, "[hss] pass %d d=%d compressed %d/%d max rank %d (%.1f ms)\n", H.passes, d,
+                   ncomp, (int)nd.size() - 1, nmax, now_ms() - t0);
+      std::fflush(stderr);
+    }
     if (done) break;
     if (d >= dmax) {
       forced = true;
@@ -676,8 +677,9 @@ hss_status compress_impl(Handle& H, const void* A, long long lda) {
     g[1].ldo = a.kc;
     HIPCHK(launch_gather(A, H.dtype, lda, g, 2, H.staging, H.stream));
   }
-  double acc[3] = {0, 0, 0};
+  double acc[4] = {0, 0, 0, 0};
   tm.finish(acc);
+  H.t_sgemm = acc[3];
   HIPCHK(hipStreamSynchronize(H.stream));
   H.staging.reset();
   H.d = d;
@@ -938,6 +940,10 @@ hss_status hss_compress(const void* A, int dtype, long long n, long long lda,
   Handle& H = p->h;
   H.dtype = dtype;
   H.opts = o;
+  {
+    const char* v = std::getenv("HSS_VERBOSE");
+    H.verbose = v && v[0] && v[0] != '0';
+  }
   hss_status st = build_tree(H, n, tree, o.leaf_size);
   if (st == HSS_OK) st = compress_impl(H, A, lda);
   if (st != HSS_OK && st != HSS_NOT_CONVERGED) {
@@ -984,6 +990,10 @@ hss_status hss_stats(hss_handle h, hss_stats_t* st) {
   st->t_sample_ms = H.t_sample;
   st->t_levels_ms = H.t_levels;
   st->t_id_ms = H.t_id;
+  st->n_sample_launches = H.n_sgemm;
+  st->t_sample_gemm_ms = H.t_sgemm;
+  st->sample_gemm_flops = H.sgemm_flops;
+  st->sample_gemm_bytes = H.sgemm_bytes;
   return HSS_OK;
 }
 
@@ -1160,8 +1170,6 @@ hss_status hss_id_batched(int nprob, const double* const* ys, const int* m, cons
   if (nprob == 0) return HSS_OK;
   hipStream_t s = static_cast<hipStream_t>(stream);
   std::vector<IdProblem> pr(nprob);
-  std::vector<long long> offs(nprob);
-  long long wtot = 0, mtot = 0;
   for (int q = 0; q < nprob; ++q) {
     if (m[q] < 0 || d[q] < 0 || (m[q] > 0 && d[q] > 0 && ldy[q] < d[q]))
       return fail(HSS_ERR_ARG, "problem sizes");
@@ -1169,33 +1177,23 @@ hss_status hss_id_batched(int nprob, const double* const* ys, const int* m, cons
     pr[q].ldy = ldy[q];
     pr[q].m = m[q];
     pr[q].d = d[q];
-    pr[q].ldw = std::max(d[q], 1);
     pr[q].perm = perms[q];
     pr[q].E = es[q];
     pr[q].kfail = -1;
-    offs[q] = mtot;
-    mtot += m[q];
-    wtot += (long long)m[q] * pr[q].ldw;
   }
   Staging st;
   HIPCHK(st.init((size_t)1 << 20, s));
-  char* base = nullptr;
-  const size_t wbytes = round_up((size_t)wtot * 8 + 8, 256), sbytes = round_up((size_t)mtot * 4 + 4, 256);
-  const size_t nbytes = round_up((size_t)mtot * 8 + 8, 256), kbytes = round_up((size_t)nprob * 4, 256);
-  hipError_t e = hipMalloc(reinterpret_cast<void**>(&base), wbytes + sbytes + nbytes + kbytes);
+  const size_t wb = id_workspace_bytes(pr.data(), nprob);
+  void* base = nullptr;
+  hipError_t e = hipMalloc(&base, wb);
   if (e != hipSuccess) {
     st.release();
     return fail(HSS_ERR_ALLOC, "id workspace");
   }
-  long long wo = 0;
-  for (int q = 0; q < nprob; ++q) {
-    pr[q].W = reinterpret_cast<double*>(base) + wo;
-    wo += (long long)pr[q].m * pr[q].ldw;
-  }
-  int* kdev = reinterpret_cast<int*>(base + wbytes + sbytes + nbytes);
-  e = launch_id_batched(pr.data(), nprob, rtol, kdev, reinterpret_cast<int*>(base + wbytes),
-                        reinterpret_cast<double*>(base + wbytes + sbytes), offs.data(), st, s);
-  if (e == hipSuccess) e = hipMemcpyAsync(k, kdev, (size_t)nprob * 4, hipMemcpyDeviceToHost, s);
+  e = launch_id_factor(pr.data(), nprob, rtol, base, wb, k, st, s);
+  std::vector<int> sel(nprob);
+  for (int q = 0; q < nprob; ++q) sel[q] = q;
+  if (e == hipSuccess) e = launch_id_finish(pr.data(), nprob, k, sel.data(), nprob, base, st, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   hipFree(base);
   st.release();

@@ -89,7 +89,10 @@ struct Handle {
   bool converged = true;
   bool compressed = false;
   bool factored = false;
-  double t_total = 0, t_sample = 0, t_levels = 0, t_id = 0;
+  bool verbose = false;  // HSS_VERBOSE: one line per pass on stderr
+  double t_total = 0, t_sample = 0, t_levels = 0, t_id = 0, t_sgemm = 0;
+  int n_sgemm = 0;
+  double sgemm_flops = 0, sgemm_bytes = 0;
   // ULV root LU (host-driven, device data)
   double* root_lu = nullptr;
   int* root_piv = nullptr;

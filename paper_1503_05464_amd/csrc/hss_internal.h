@@ -85,18 +85,22 @@ struct IdProblem {
   const double* Y;   // rows of Y^T: m rows, d columns, leading dimension ldy
   long long ldy;
   int m, d;
-  double* W;         // workspace m x d (ld = ldw), overwritten with R data
+  double* W;         // set by launch_id_factor: workspace copy, then R data
   long long ldw;
   int* perm;         // m entries out: J (pivot order) then rest (increasing)
   double* E;         // (m-k) x k out (row-major, ld = k)
   int kfail;         // early exit once k > kfail and k < m is certain (-1: never)
 };
-// k_dev: device int array of nprob ranks (out).  step_dev / nrm_dev: device
-// int / double arrays of sum(m) entries (pivot step of every column, and the
-// column norms), problem p using the entries from offs[p] (host prefix sums).
-hipError_t launch_id_batched(const IdProblem* probs, int nprob, double rtol, int* k_dev,
-                             int* step_dev, double* nrm_dev, const long long* offs, Staging& st,
-                             hipStream_t s);
+// Device workspace for a batch (carved by the launcher).
+size_t id_workspace_bytes(const IdProblem* probs, int nprob);
+// Column-pivoted QR to tolerance of every problem; synchronises the stream
+// and returns the ranks in k_host (pinned or pageable host array).
+hipError_t launch_id_factor(IdProblem* probs, int nprob, double rtol, void* work, size_t work_bytes,
+                            int* k_host, Staging& st, hipStream_t s);
+// J / rest permutation and E for the problems listed in `sel` (after
+// launch_id_factor on the same batch and workspace).
+hipError_t launch_id_finish(const IdProblem* probs, int nprob, const int* k_host, const int* sel,
+                            int nsel, void* work, Staging& st, hipStream_t s);
 
 // ---------------------------------------------------------------------------
 // Small helpers (kernels_misc.hip)

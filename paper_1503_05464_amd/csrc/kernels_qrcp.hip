@@ -1,41 +1,91 @@
 // Batched interpolative decomposition [X, J] = ID(Y, eps) by Householder QR
-// with column pivoting, stopped at the first pivot with
-// |R_ii| <= eps |R_11| (Sec. 2.2; the modified xGEQP3 of Sec. 3.2).
+// with column pivoting, stopped at the first pivot with |R_ii| <= eps |R_11|
+// (Sec. 2.2; the modified xGEQP3 of Sec. 3.2).
 //
-// Problem p holds Y_p (d x m) as the m rows of a row-major matrix (the rows
-// of the local sample S_loc, so "column j of Y" is a contiguous row).  The
-// kernel works on a copy W.  One workgroup per problem:
-//   * pivot = largest remaining column norm, lowest index on ties (block
-//     reduction);
-//   * the reflector of the pivot column is staged in LDS and applied to all
-//     unselected columns, one column per wavefront at a time (wavefront dot
-//     product, update, and an exact recomputation of the remaining norm --
-//     no downdating, so small tolerances stay accurate);
-//   * columns are not swapped: a per-column step number marks the pivots,
-//     so R(i, j) stays in row i of column j's storage.
-// A second kernel forms J (pivot order) and the other columns in increasing
-// order, and E = (R1^{-1} R2)^T by back substitution, one thread per
-// unselected column.
+// Problem q holds Y_q (d x m) as the m rows of a row-major matrix (the rows
+// of a node's local sample), so "column j of Y" is a contiguous vector.
+// Pivot rule: largest remaining 2-norm, lowest column index on ties; the
+// remaining norms are recomputed exactly after every reflection (no
+// downdating), so small tolerances keep their accuracy.  Columns are never
+// swapped: a per-column step number marks the pivots and R(i, j) stays in
+// row i of column j's storage.
 //
-// Early exit: when the caller's fail rule (rank above d - p_margin and
-// below m) is already certain -- more than kfail pivots accepted and m > d,
-// so the rank cannot reach m -- the factorization stops; the reported rank
-// is then a lower bound that still trips the rule.
+// Two factorization kernels, chosen per problem by size:
+//  * small problems (m <= 256, d <= 192): one workgroup of RW wavefronts holds
+//    the whole matrix in registers (wavefront w owns columns w, w+RW, ...;
+//    lane l owns rows l, l+64, ...) and runs every pivot step without
+//    touching global memory;
+//  * large problems: one launch per pivot step for the whole batch; a problem
+//    is split over ceil(m/16) workgroups, each owning 16 columns; every
+//    workgroup of a problem selects the same pivot from the same norms
+//    (double-buffered between steps so no workgroup waits on another), builds
+//    the same reflector from the pivot column, and updates its own columns.
+//    Kernel boundaries order the steps.
+// A finishing pass forms J (pivot order) and the other columns in increasing
+// order, and E = (R1^{-1} R2)^T by a blocked triangular solve whose
+// off-diagonal updates run on the batched GEMM.  It is skipped for IDs the
+// caller rejects.
+//
+// Early exit: when the caller's fail rule (rank above d - p_margin and below
+// m) is certain -- more than kfail pivots accepted and m > d, so the rank can
+// not reach m -- the factorization stops; the reported rank is then a lower
+// bound that still trips the rule.
+#include <climits>
 #include <cmath>
+#include <vector>
 
 #include "hss_internal.h"
 
 namespace hss {
 namespace {
 
-constexpr int NT = 256;
-constexpr int NW = NT / 64;
-
-struct DevIdProblem {
+struct DevProb {
   IdProblem p;
-  long long off;
-  int allow_early;
+  long long off;    // into the per-column arrays (sum of m)
+  long long aoff;   // into the per-step arrays (sum of kmax)
+  int kmax;         // min(m, d)
+  int g0;           // first workgroup of this problem (large path)
+  int cpw;          // columns per workgroup (large path)
 };
+
+struct Work {
+  double* nrm;   // 2 * sum(m): double-buffered norms
+  int* step;     // sum(m): pivot step of each column, -1 if not selected
+  double* alpha; // sum(kmax): R_ii
+  int* piv;      // sum(kmax): pivot column of step i
+  int* k;        // nprob
+  int* done;     // nprob
+  double* nu0;   // nprob
+  int* ndone;    // 1
+  double* W;     // sum(m * d)
+};
+
+size_t al(size_t b) { return (b + 255) / 256 * 256; }
+
+void carve(const IdProblem* probs, int nprob, void* base, Work& w, long long& tm, long long& tk,
+           long long& tw) {
+  tm = tk = tw = 0;
+  for (int q = 0; q < nprob; ++q) {
+    tm += probs[q].m;
+    tk += std::min(probs[q].m, probs[q].d);
+    tw += (long long)probs[q].m * probs[q].d;
+  }
+  char* c = static_cast<char*>(base);
+  auto take = [&](size_t b) {
+    char* r = c;
+    c += al(b ? b : 1);
+    return r;
+  };
+  w.nrm = reinterpret_cast<double*>(take(2 * tm * 8));
+  w.step = reinterpret_cast<int*>(take(tm * 4));
+  w.alpha = reinterpret_cast<double*>(take(tk * 8));
+  w.piv = reinterpret_cast<int*>(take(tk * 4));
+  w.k = reinterpret_cast<int*>(take((size_t)nprob * 4));
+  w.done = reinterpret_cast<int*>(take((size_t)nprob * 4));
+  w.nu0 = reinterpret_cast<double*>(take((size_t)nprob * 8));
+  w.ndone = reinterpret_cast<int*>(take(4));
+  w.W = reinterpret_cast<double*>(take(tw * 8));
+}
 
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
@@ -43,69 +93,63 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-__global__ __launch_bounds__(NT) void qrcp_kernel(const DevIdProblem* __restrict__ probs,
-                                                  double rtol, int* __restrict__ kout,
-                                                  int* __restrict__ step_all,
-                                                  double* __restrict__ nrm_all) {
-  extern __shared__ double u[];  // reflector, length d
-  __shared__ double red_v[NT / 64];
-  __shared__ int red_i[NT / 64];
+__device__ __forceinline__ void better(double& bv, int& bi, double ov, int oi) {
+  if (ov > bv || (ov == bv && oi < bi)) {
+    bv = ov;
+    bi = oi;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// small problems: one workgroup, matrix in registers
+// ---------------------------------------------------------------------------
+template <int RW, int CPW, int RPL>
+__global__ __launch_bounds__(RW * 64) void qrcp_reg_kernel(const DevProb* __restrict__ probs,
+                                                          const int* __restrict__ list, double rtol,
+                                                          Work w) {
+  __shared__ double xcol[RPL * 64];
+  __shared__ double nrm_s[RW * CPW];
+  __shared__ int step_s[RW * CPW];
+  __shared__ double red_v[RW];
+  __shared__ int red_i[RW];
   __shared__ double s_best;
   __shared__ int s_p;
 
-  const DevIdProblem dp = probs[blockIdx.x];
+  const int q = list[blockIdx.x];
+  const DevProb dp = probs[q];
   const IdProblem& P = dp.p;
   const int m = P.m, d = P.d;
-  const long long ldw = P.ldw;
-  double* __restrict__ W = P.W;
-  int* __restrict__ step = step_all + dp.off;
-  double* __restrict__ nrm = nrm_all + dp.off;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
 
-  // copy and initial norms
-  for (int j = wave; j < m; j += NW) {
-    const double* y = P.Y + (long long)j * P.ldy;
-    double* w = W + (long long)j * ldw;
+  double y[CPW][RPL];
+#pragma unroll
+  for (int c = 0; c < CPW; ++c) {
+    const int j = wave + RW * c;
     double s = 0.0;
-    for (int r = lane; r < d; r += 64) {
-      const double v = y[r];
-      w[r] = v;
+#pragma unroll
+    for (int t = 0; t < RPL; ++t) {
+      const int r = lane + 64 * t;
+      const double v = (j < m && r < d) ? P.Y[(long long)j * P.ldy + r] : 0.0;
+      y[c][t] = v;
       s = fma(v, v, s);
     }
     s = wave_sum(s);
-    if (lane == 0) {
-      nrm[j] = sqrt(s);
-      step[j] = -1;
+    if (lane == 0 && j < m) {
+      nrm_s[j] = sqrt(s);
+      step_s[j] = -1;
     }
   }
-  __threadfence_block();
   __syncthreads();
-
-  const int kmax = min(m, d);
+  const int kmax = dp.kmax;
   double nu0 = 0.0;
   int k = 0;
   for (int i = 0; i < kmax; ++i) {
-    // pivot: largest norm among unselected columns, lowest index on ties
     double bv = -1.0;
-    int bi = m;
-    for (int j = tid; j < m; j += NT) {
-      if (step[j] < 0) {
-        const double v = nrm[j];
-        if (v > bv) {  // j increases, so ties keep the lowest index
-          bv = v;
-          bi = j;
-        }
-      }
-    }
+    int bi = INT_MAX;
+    for (int j = tid; j < m; j += RW * 64)
+      if (step_s[j] < 0) better(bv, bi, nrm_s[j], j);
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-      const double ov = __shfl_xor(bv, o, 64);
-      const int oi = __shfl_xor(bi, o, 64);
-      if (ov > bv || (ov == bv && oi < bi)) {
-        bv = ov;
-        bi = oi;
-      }
-    }
+    for (int o = 32; o > 0; o >>= 1) better(bv, bi, __shfl_xor(bv, o, 64), __shfl_xor(bi, o, 64));
     if (lane == 0) {
       red_v[wave] = bv;
       red_i[wave] = bi;
@@ -114,12 +158,7 @@ __global__ __launch_bounds__(NT) void qrcp_kernel(const DevIdProblem* __restrict
     if (tid == 0) {
       double v = red_v[0];
       int ix = red_i[0];
-      for (int q = 1; q < NW; ++q) {
-        if (red_v[q] > v || (red_v[q] == v && red_i[q] < ix)) {
-          v = red_v[q];
-          ix = red_i[q];
-        }
-      }
+      for (int q2 = 1; q2 < RW; ++q2) better(v, ix, red_v[q2], red_i[q2]);
       s_best = v;
       s_p = ix;
     }
@@ -128,133 +167,494 @@ __global__ __launch_bounds__(NT) void qrcp_kernel(const DevIdProblem* __restrict
     const int p = s_p;
     if (i == 0) nu0 = best;
     if (best <= 0.0 || best <= rtol * nu0) break;
-    if (dp.allow_early && i > P.kfail && m > d) break;
-
-    // Householder reflector of column p, rows i..d-1: H = I - tau u u^T,
-    // u_0 = 1, H x = alpha e_1 with alpha = -sign(x_0) ||x||.
-    double* wp = W + (long long)p * ldw;
-    const double x0 = wp[i];
+    if (P.kfail >= 0 && i > P.kfail && m > d) break;
+    const int wp = p % RW, cp = p / RW;
+    if (wave == wp) {
+#pragma unroll
+      for (int c = 0; c < CPW; ++c)
+        if (c == cp) {
+#pragma unroll
+          for (int t = 0; t < RPL; ++t) xcol[lane + 64 * t] = y[c][t];
+        }
+    }
+    if (tid == 0) step_s[p] = i;
+    __syncthreads();
+    const double x0 = xcol[i];
     const double alpha = -copysign(best, x0);
     const double v0 = x0 - alpha;
     const double tau = -v0 / alpha;
     const double inv_v0 = 1.0 / v0;
-    for (int r = i + tid; r < d; r += NT) u[r - i] = (r == i) ? 1.0 : wp[r] * inv_v0;
-    __syncthreads();
-    if (tid == 0) {
-      wp[i] = alpha;
-      step[p] = i;
+    double uu[RPL];
+#pragma unroll
+    for (int t = 0; t < RPL; ++t) {
+      const int r = lane + 64 * t;
+      uu[t] = (r < d && r > i) ? xcol[r] * inv_v0 : (r == i ? 1.0 : 0.0);
     }
-    __threadfence_block();
-    __syncthreads();
-
-    for (int j = wave; j < m; j += NW) {
-      if (step[j] >= 0) continue;
-      double* w = W + (long long)j * ldw;
+    if (wave == wp) {
+#pragma unroll
+      for (int c = 0; c < CPW; ++c)
+        if (c == cp) {
+#pragma unroll
+          for (int t = 0; t < RPL; ++t)
+            if (lane + 64 * t == i) y[c][t] = alpha;
+        }
+    }
+    if (tid == 0) {
+      w.alpha[dp.aoff + i] = alpha;
+      w.piv[dp.aoff + i] = p;
+    }
+#pragma unroll
+    for (int c = 0; c < CPW; ++c) {
+      const int j = wave + RW * c;
+      if (j >= m || step_s[j] >= 0) continue;
       double dot = 0.0;
-      for (int r = i + lane; r < d; r += 64) dot = fma(u[r - i], w[r], dot);
-      dot = wave_sum(dot);
-      const double f = tau * dot;
+#pragma unroll
+      for (int t = 0; t < RPL; ++t) dot = fma(uu[t], y[c][t], dot);
+      const double f = tau * wave_sum(dot);
       double s = 0.0;
-      for (int r = i + lane; r < d; r += 64) {
-        const double v = fma(-f, u[r - i], w[r]);
-        w[r] = v;
-        if (r > i) s = fma(v, v, s);
+#pragma unroll
+      for (int t = 0; t < RPL; ++t) {
+        const int r = lane + 64 * t;
+        const double v = fma(-f, uu[t], y[c][t]);
+        y[c][t] = v;
+        if (r > i && r < d) s = fma(v, v, s);
       }
       s = wave_sum(s);
-      if (lane == 0) nrm[j] = sqrt(s);
+      if (lane == 0) nrm_s[j] = sqrt(s);
     }
-    __threadfence_block();
-    __syncthreads();
     k = i + 1;
+    __syncthreads();
   }
-  if (tid == 0) kout[blockIdx.x] = k;
+  // write back the R data and the pivot steps
+  int* step = w.step + dp.off;
+#pragma unroll
+  for (int c = 0; c < CPW; ++c) {
+    const int j = wave + RW * c;
+    if (j >= m) continue;
+#pragma unroll
+    for (int t = 0; t < RPL; ++t) {
+      const int r = lane + 64 * t;
+      if (r < d) P.W[(long long)j * P.ldw + r] = y[c][t];
+    }
+    if (lane == 0) step[j] = step_s[j];
+  }
+  if (tid == 0) w.k[q] = k;
 }
 
-// J / rest permutation and E = (R1^{-1} R2)^T.  grid: (problem, chunk of
-// NT unselected columns).  Chunk 0 also writes the permutation.
-__global__ __launch_bounds__(NT) void id_finish_kernel(const DevIdProblem* __restrict__ probs,
-                                                      const int* __restrict__ kin,
-                                                      const int* __restrict__ step_all) {
-  __shared__ int cnt[NT];
-  const DevIdProblem dp = probs[blockIdx.x];
-  const IdProblem& P = dp.p;
-  const int m = P.m;
-  const int k = kin[blockIdx.x];
-  const int* __restrict__ step = step_all + dp.off;
-  const int tid = threadIdx.x;
-  int* perm = P.perm;
+// ---------------------------------------------------------------------------
+// large problems: one launch per pivot step
+// ---------------------------------------------------------------------------
+constexpr int NT = 256;
+constexpr int NW = NT / 64;
 
-  // ranks of the unselected columns among themselves (block scan over
-  // contiguous chunks)
+__global__ __launch_bounds__(NT) void id_init_kernel(const DevProb* __restrict__ probs,
+                                                    const int* __restrict__ wg_prob, Work w) {
+  const int q = wg_prob[blockIdx.x];
+  const DevProb dp = probs[q];
+  const IdProblem& P = dp.p;
+  const int g = blockIdx.x - dp.g0;
+  const int c0 = g * dp.cpw, c1 = min(P.m, c0 + dp.cpw);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int j = c0 + wave; j < c1; j += NW) {
+    const double* src = P.Y + (long long)j * P.ldy;
+    double* dst = P.W + (long long)j * P.ldw;
+    double s = 0.0;
+    for (int r = lane; r < P.d; r += 64) {
+      const double v = src[r];
+      dst[r] = v;
+      s = fma(v, v, s);
+    }
+    s = wave_sum(s);
+    if (lane == 0) {
+      w.nrm[dp.off + j] = sqrt(s);
+      w.step[dp.off + j] = -1;
+    }
+  }
+  if (g == 0 && threadIdx.x == 0) {
+    w.done[q] = 0;
+    w.k[q] = 0;
+  }
+}
+
+__global__ __launch_bounds__(NT) void id_step_kernel(const DevProb* __restrict__ probs,
+                                                    const int* __restrict__ wg_prob, int i,
+                                                    double rtol, long long tm, Work w) {
+  extern __shared__ double u[];
+  __shared__ double red_v[NW];
+  __shared__ int red_i[NW];
+  __shared__ double s_best;
+  __shared__ int s_p;
+
+  const int q = wg_prob[blockIdx.x];
+  if (w.done[q]) return;
+  const DevProb dp = probs[q];
+  const IdProblem& P = dp.p;
+  const int m = P.m, d = P.d;
+  const int g = blockIdx.x - dp.g0;
+  const bool leader = (g == 0 && threadIdx.x == 0);
+  if (i >= dp.kmax) {
+    if (leader) {
+      w.done[q] = 1;
+      atomicAdd(w.ndone, 1);
+    }
+    return;
+  }
+  const double* __restrict__ nrm = w.nrm + (i & 1) * tm + dp.off;
+  double* __restrict__ nrm_next = w.nrm + ((i + 1) & 1) * tm + dp.off;
+  int* __restrict__ step = w.step + dp.off;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+
+  // pivot: every workgroup of the problem reduces the same norms the same way
+  double bv = -1.0;
+  int bi = INT_MAX;
+  for (int j = tid; j < m; j += NT) {
+    const int sj = step[j];
+    if (sj < 0 || sj >= i) better(bv, bi, nrm[j], j);
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) better(bv, bi, __shfl_xor(bv, o, 64), __shfl_xor(bi, o, 64));
+  if (lane == 0) {
+    red_v[wave] = bv;
+    red_i[wave] = bi;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double v = red_v[0];
+    int ix = red_i[0];
+    for (int q2 = 1; q2 < NW; ++q2) better(v, ix, red_v[q2], red_i[q2]);
+    s_best = v;
+    s_p = ix;
+  }
+  __syncthreads();
+  const double best = s_best;
+  const int p = s_p;
+  const double nu0 = (i == 0) ? best : w.nu0[q];
+  if (i == 0 && leader) w.nu0[q] = best;
+  const bool stop = (best <= 0.0 || best <= rtol * nu0) || (P.kfail >= 0 && i > P.kfail && m > d);
+  if (stop) {
+    if (leader) {
+      w.done[q] = 1;
+      atomicAdd(w.ndone, 1);
+    }
+    return;
+  }
+  const double* __restrict__ wp = P.W + (long long)p * P.ldw;
+  const double x0 = wp[i];
+  const double alpha = -copysign(best, x0);
+  const double v0 = x0 - alpha;
+  const double tau = -v0 / alpha;
+  const double inv_v0 = 1.0 / v0;
+  for (int r = i + tid; r < d; r += NT) u[r - i] = (r == i) ? 1.0 : wp[r] * inv_v0;
+  __syncthreads();
+  if (leader) {
+    w.alpha[dp.aoff + i] = alpha;
+    w.piv[dp.aoff + i] = p;
+    step[p] = i;
+    w.k[q] = i + 1;
+  }
+  const int c0 = g * dp.cpw, c1 = min(m, c0 + dp.cpw);
+  for (int j = c0 + wave; j < c1; j += NW) {
+    if (j == p) continue;
+    const int sj = step[j];
+    if (sj >= 0 && sj < i) continue;
+    double* __restrict__ wj = P.W + (long long)j * P.ldw;
+    double dot = 0.0;
+    for (int r = i + lane; r < d; r += 64) dot = fma(u[r - i], wj[r], dot);
+    const double f = tau * wave_sum(dot);
+    double s = 0.0;
+    for (int r = i + lane; r < d; r += 64) {
+      const double v = fma(-f, u[r - i], wj[r]);
+      wj[r] = v;
+      if (r > i) s = fma(v, v, s);
+    }
+    s = wave_sum(s);
+    if (lane == 0) nrm_next[j] = sqrt(s);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// finishing: permutation, diagonal of R1, blocked E = (R1^{-1} R2)^T
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(NT) void id_perm_kernel(const DevProb* __restrict__ probs,
+                                                    const int* __restrict__ sel, Work w) {
+  __shared__ int cnt[NT];
+  const int q = sel[blockIdx.x];
+  const DevProb dp = probs[q];
+  const IdProblem& P = dp.p;
+  const int m = P.m, k = w.k[q];
+  const int* step = w.step + dp.off;
+  const int tid = threadIdx.x;
+  for (int a = tid; a < k; a += NT) {
+    const int j = w.piv[dp.aoff + a];
+    P.perm[a] = j;
+    P.W[(long long)j * P.ldw + a] = w.alpha[dp.aoff + a];
+  }
   const int per = (m + NT - 1) / NT;
-  const int j0 = tid * per;
-  const int j1 = min(m, j0 + per);
+  const int j0 = tid * per, j1 = min(m, j0 + per);
   int c = 0;
   for (int j = j0; j < j1; ++j) c += (step[j] < 0 || step[j] >= k) ? 1 : 0;
   cnt[tid] = c;
   __syncthreads();
   if (tid == 0) {
     int acc = 0;
-    for (int q = 0; q < NT; ++q) {
-      const int t = cnt[q];
-      cnt[q] = acc;
-      acc += t;
+    for (int t = 0; t < NT; ++t) {
+      const int v = cnt[t];
+      cnt[t] = acc;
+      acc += v;
     }
   }
   __syncthreads();
-  int pos = cnt[tid];
-  for (int j = j0; j < j1; ++j) {
-    const int s = step[j];
-    if (s >= 0 && s < k) perm[s] = j;
-    else perm[k + pos++] = j;
-  }
-  __threadfence_block();
-  __syncthreads();
+  int pos = k + cnt[tid];
+  for (int j = j0; j < j1; ++j)
+    if (step[j] < 0 || step[j] >= k) P.perm[pos++] = j;
+}
 
-  // back substitution for every unselected column c: R1 t = R2(:, c)
-  const double* W = P.W;
-  const long long ldw = P.ldw;
-  for (int cidx = tid; cidx < m - k; cidx += NT) {
-    const int jc = perm[k + cidx];
-    const double* wc = W + (long long)jc * ldw;
-    double* t = P.E + (long long)cidx * k;
-    for (int a = k - 1; a >= 0; --a) {
-      double s = wc[a];
-      for (int b = a + 1; b < k; ++b) s = fma(-W[(long long)perm[b] * ldw + a], t[b], s);
-      t[a] = s / W[(long long)perm[a] * ldw + a];
+// Diagonal block of the solve E * Rt = R2^T with Rt = R1^T lower
+// triangular: for every unselected column c (one thread each),
+// x[a] = (y[a] - sum_{b > a} x[b] Rt[b][a]) / Rt[a][a] on [b0, b1).
+struct DiagDesc {
+  const double* W;
+  long long ldw;
+  const int* perm;
+  double* E;
+  int k, nrest, b0, b1;
+  long long wg0;
+};
+
+__global__ __launch_bounds__(NT) void trsm_diag_kernel(const DiagDesc* __restrict__ descs, int nd) {
+  __shared__ double Rt[64][65];
+  int lo = 0, hi = nd - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (descs[mid].wg0 <= (long long)blockIdx.x) lo = mid;
+    else hi = mid - 1;
+  }
+  const DiagDesc g = descs[lo];
+  const int nb = g.b1 - g.b0;
+  for (int e = threadIdx.x; e < nb * nb; e += NT) {
+    const int bb = e / nb, aa = e % nb;
+    Rt[bb][aa] = (aa <= bb) ? g.W[(long long)g.perm[g.b0 + bb] * g.ldw + g.b0 + aa] : 0.0;
+  }
+  __syncthreads();
+  const int c = (int)(blockIdx.x - g.wg0) * NT + threadIdx.x;
+  if (c >= g.nrest) return;
+  double* x = g.E + (long long)c * g.k + g.b0;
+  double xv[64];
+#pragma unroll
+  for (int a = 0; a < 64; ++a) xv[a] = (a < nb) ? x[a] : 0.0;
+#pragma unroll
+  for (int a = 63; a >= 0; --a) {
+    if (a < nb) {
+      double s = xv[a];
+#pragma unroll
+      for (int b = a + 1; b < 64; ++b)
+        if (b < nb) s = fma(-xv[b], Rt[b][a], s);
+      xv[a] = s / Rt[a][a];
     }
   }
+#pragma unroll
+  for (int a = 0; a < 64; ++a)
+    if (a < nb) x[a] = xv[a];
 }
 
 }  // namespace
 
-hipError_t launch_id_batched(const IdProblem* probs, int nprob, double rtol, int* k_dev,
-                             int* step_dev, double* nrm_dev, const long long* offs, Staging& st,
-                             hipStream_t s) {
+size_t id_workspace_bytes(const IdProblem* probs, int nprob) {
+  long long tm = 0, tk = 0, tw = 0;
+  for (int q = 0; q < nprob; ++q) {
+    tm += probs[q].m;
+    tk += std::min(probs[q].m, probs[q].d);
+    tw += (long long)probs[q].m * probs[q].d;
+  }
+  return al(2 * tm * 8) + al(tm * 4) + al(tk * 8) + al(tk * 4) + 3 * al((size_t)nprob * 8) +
+         al(4) + al(tw * 8) + 4096;
+}
+
+// Register-resident classes (wavefronts, columns per wavefront, rows per
+// lane) chosen so that no instance spills: -1 = use the step kernels.
+constexpr int kSmallClasses = 10;
+static int small_class(const IdProblem& p) {
+  const int m = p.m, d = p.d;
+  if (m > 256 || d > 192 || m == 0 || d == 0) return -1;
+  if (d <= 64) return m <= 32 ? 0 : m <= 64 ? 1 : m <= 128 ? 2 : 3;
+  if (d <= 128) return m <= 64 ? 4 : m <= 128 ? 5 : 6;
+  return m <= 64 ? 7 : m <= 128 ? 8 : 9;
+}
+
+hipError_t launch_id_factor(IdProblem* probs, int nprob, double rtol, void* work, size_t work_bytes,
+                            int* k_host, Staging& st, hipStream_t s) {
   if (nprob <= 0) return hipSuccess;
-  DevIdProblem* h = new DevIdProblem[nprob];
-  int dmax = 1;
+  if (work_bytes < id_workspace_bytes(probs, nprob)) return hipErrorInvalidValue;
+  Work w;
+  long long tm, tk, tw;
+  carve(probs, nprob, work, w, tm, tk, tw);
+  std::vector<DevProb> h(nprob);
+  long long off = 0, aoff = 0, woff = 0;
+  int g = 0, dmax = 1, smax = 0;
+  std::vector<int> wg_prob, small[kSmallClasses];
+  for (int q = 0; q < nprob; ++q) {
+    IdProblem& p = probs[q];
+    p.ldw = p.d > 0 ? p.d : 1;
+    p.W = w.W + woff;
+    woff += (long long)p.m * p.d;
+    DevProb& dp = h[q];
+    dp.p = p;
+    dp.off = off;
+    dp.aoff = aoff;
+    dp.kmax = std::min(p.m, p.d);
+    off += p.m;
+    aoff += dp.kmax;
+    dp.g0 = -1;
+    dp.cpw = 16;
+    if (p.m == 0 || p.d == 0) {
+      dp.kmax = 0;
+    }
+    const int sc = small_class(p);
+    if (sc >= 0) {
+      small[sc].push_back(q);
+    } else {
+      dp.g0 = g;
+      const int G = (p.m + dp.cpw - 1) / dp.cpw;
+      for (int t = 0; t < G; ++t) wg_prob.push_back(q);
+      g += G;
+      dmax = std::max(dmax, p.d);
+      int steps = dp.kmax;
+      if (p.kfail >= 0 && p.m > p.d) steps = std::min(steps, p.kfail + 2);
+      smax = std::max(smax, steps);
+    }
+  }
+  if ((size_t)dmax * 8 > 64 * 1024) return hipErrorInvalidValue;
+  const DevProb* dprobs = static_cast<const DevProb*>(st.push(h.data(), sizeof(DevProb) * nprob));
+  if (!dprobs) return hipErrorOutOfMemory;
+  hipError_t e = hipMemsetAsync(w.ndone, 0, 4, s);
+  if (e != hipSuccess) return e;
+  // small problems: one register-resident workgroup each
+  for (int c = 0; c < kSmallClasses; ++c) {
+    std::vector<int>& L = small[c];
+    if (L.empty()) continue;
+    const int* dl = static_cast<const int*>(st.push(L.data(), L.size() * 4));
+    if (!dl) return hipErrorOutOfMemory;
+    const dim3 grid((unsigned)L.size());
+#define QR_LAUNCH(W_, C_, R_) \
+  hipLaunchKernelGGL((qrcp_reg_kernel<W_, C_, R_>), grid, dim3(W_ * 64), 0, s, dprobs, dl, rtol, w)
+    switch (c) {
+      case 0: QR_LAUNCH(16, 2, 1); break;
+      case 1: QR_LAUNCH(16, 4, 1); break;
+      case 2: QR_LAUNCH(16, 8, 1); break;
+      case 3: QR_LAUNCH(16, 16, 1); break;
+      case 4: QR_LAUNCH(16, 4, 2); break;
+      case 5: QR_LAUNCH(16, 8, 2); break;
+      case 6: QR_LAUNCH(8, 32, 2); break;
+      case 7: QR_LAUNCH(16, 4, 3); break;
+      case 8: QR_LAUNCH(8, 16, 3); break;
+      default: QR_LAUNCH(8, 32, 3); break;
+    }
+#undef QR_LAUNCH
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  // large problems: a launch per pivot step
+  if (g > 0) {
+    const int* dwg = static_cast<const int*>(st.push(wg_prob.data(), wg_prob.size() * 4));
+    if (!dwg) return hipErrorOutOfMemory;
+    hipLaunchKernelGGL(id_init_kernel, dim3(g), dim3(NT), 0, s, dprobs, dwg, w);
+    int nlarge = 0;
+    for (int q = 0; q < nprob; ++q) nlarge += h[q].g0 >= 0 ? 1 : 0;
+    const size_t lds = (size_t)dmax * 8;
+    for (int i = 0; i < smax; ++i) {
+      hipLaunchKernelGGL(id_step_kernel, dim3(g), dim3(NT), lds, s, dprobs, dwg, i, rtol, tm, w);
+      if ((i & 63) == 63 && i + 1 < smax) {  // stop early once every problem is done
+        int nd = 0;
+        e = hipMemcpyAsync(k_host, w.ndone, 4, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return e;
+        nd = k_host[0];
+        if (nd >= nlarge) break;
+      }
+    }
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  e = hipMemcpyAsync(k_host, w.k, (size_t)nprob * 4, hipMemcpyDeviceToHost, s);
+  if (e != hipSuccess) return e;
+  return hipStreamSynchronize(s);
+}
+
+hipError_t launch_id_finish(const IdProblem* probs, int nprob, const int* k_host, const int* sel,
+                            int nsel, void* work, Staging& st, hipStream_t s) {
+  if (nsel <= 0) return hipSuccess;
+  Work w;
+  long long tm, tk, tw;
+  carve(probs, nprob, work, w, tm, tk, tw);
+  std::vector<DevProb> h(nprob);
+  long long off = 0, aoff = 0;
   for (int q = 0; q < nprob; ++q) {
     h[q].p = probs[q];
-    h[q].off = offs[q];
-    h[q].allow_early = probs[q].kfail >= 0 ? 1 : 0;
-    if (probs[q].d > dmax) dmax = probs[q].d;
+    h[q].off = off;
+    h[q].aoff = aoff;
+    h[q].kmax = std::min(probs[q].m, probs[q].d);
+    off += probs[q].m;
+    aoff += h[q].kmax;
   }
-  // the reflector is staged in LDS: d doubles per workgroup
-  if ((size_t)dmax * sizeof(double) > 64 * 1024) {
-    delete[] h;
-    return hipErrorInvalidValue;
-  }
-  void* dd = st.push(h, sizeof(DevIdProblem) * nprob);
-  delete[] h;
-  if (!dd) return hipErrorOutOfMemory;
-  const DevIdProblem* d = static_cast<const DevIdProblem*>(dd);
-  hipLaunchKernelGGL(qrcp_kernel, dim3(nprob), dim3(NT), (size_t)dmax * sizeof(double), s, d, rtol,
-                     k_dev, step_dev, nrm_dev);
+  const DevProb* dprobs = static_cast<const DevProb*>(st.push(h.data(), sizeof(DevProb) * nprob));
+  const int* dsel = static_cast<const int*>(st.push(sel, (size_t)nsel * 4));
+  if (!dprobs || !dsel) return hipErrorOutOfMemory;
+  hipLaunchKernelGGL(id_perm_kernel, dim3(nsel), dim3(NT), 0, s, dprobs, dsel, w);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(id_finish_kernel, dim3(nprob), dim3(NT), 0, s, d, k_dev, step_dev);
-  return hipGetLastError();
+  // blocked back substitution, last block first
+  int maxblk = 0;
+  for (int t = 0; t < nsel; ++t) {
+    const int q = sel[t], k = k_host[q];
+    if (k > 0 && probs[q].m > k) maxblk = std::max(maxblk, (k + 63) / 64);
+  }
+  std::vector<GemmDesc> gd;
+  std::vector<DiagDesc> dd;
+  for (int b = maxblk - 1; b >= 0; --b) {
+    gd.clear();
+    dd.clear();
+    long long wg = 0;
+    for (int t = 0; t < nsel; ++t) {
+      const int q = sel[t], k = k_host[q];
+      const IdProblem& p = probs[q];
+      const int nrest = p.m - k;
+      if (k <= 0 || nrest <= 0 || b * 64 >= k) continue;
+      const int b0 = b * 64, b1 = std::min(k, b0 + 64);
+      GemmDesc g{};
+      g.M = nrest;
+      g.N = b1 - b0;
+      g.K = k - b1;
+      g.A = p.E + b1;
+      g.lda = k;
+      g.B = Seg{p.W + b0, nullptr, p.ldw, INT_MAX, p.perm + b1};
+      g.C = Seg{p.W + b0, nullptr, p.ldw, INT_MAX, p.perm + k};
+      g.D = SegOut{p.E + b0, nullptr, k, INT_MAX, nullptr};
+      g.alpha = -1.0;
+      g.beta = 1.0;
+      gd.push_back(g);
+      DiagDesc x;
+      x.W = p.W;
+      x.ldw = p.ldw;
+      x.perm = p.perm;
+      x.E = p.E;
+      x.k = k;
+      x.nrest = nrest;
+      x.b0 = b0;
+      x.b1 = b1;
+      x.wg0 = wg;
+      wg += (nrest + NT - 1) / NT;
+      dd.push_back(x);
+    }
+    if (dd.empty()) continue;
+    e = launch_gemm_batched(gd.data(), (int)gd.size(), st, s);
+    if (e != hipSuccess) return e;
+    const DiagDesc* ddev = static_cast<const DiagDesc*>(st.push(dd.data(), dd.size() * sizeof(DiagDesc)));
+    if (!ddev) return hipErrorOutOfMemory;
+    hipLaunchKernelGGL(trsm_diag_kernel, dim3((unsigned)wg), dim3(NT), 0, s, ddev, (int)dd.size());
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 }  // namespace hss
