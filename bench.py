@@ -39,11 +39,11 @@ HBM_PEAK_GBS = 8000.0
 
 WORKLOADS = {
     "gauss65536": dict(n=65536, kind="gauss", leaf=256, rtol=1e-6, d0=128, dd=64, d_max=4096,
-                       storage="f32", point_seed=4),
+                       storage="f32", point_seed=4, p_margin=200),
     "circle16384": dict(n=16384, kind="log", leaf=128, rtol=1e-8, d0=128, dd=64, d_max=4096,
-                        storage="f64", point_seed=2),
+                        storage="f64", point_seed=2, p_margin=10),
     "toeplitz1024": dict(n=1024, kind="toeplitz", leaf=64, rtol=1e-6, d0=64, dd=32, d_max=4096,
-                         storage="f64", point_seed=0),
+                         storage="f64", point_seed=0, p_margin=10),
 }
 
 
@@ -77,6 +77,25 @@ def dense_matvec(A, x, block=4096):
     for r0 in range(0, A.shape[0], block):
         out[r0:r0 + block] = A[r0:r0 + block].double() @ x
     return out
+
+
+def frob_error(P, h, A, panel=2048):
+    """||A - A_HSS||_F / ||A||_F exactly, from A_HSS applied to identity
+    column panels (FP64)."""
+    import torch
+
+    n = A.shape[0]
+    num = den = 0.0
+    for c0 in range(0, n, panel):
+        w = min(panel, n - c0)
+        E = torch.zeros((n, w), dtype=torch.float64, device=A.device)
+        E[c0:c0 + w] = torch.eye(w, dtype=torch.float64, device=A.device)
+        Hp = P.hss_matvec(h, E)
+        Ap = A[:, c0:c0 + w].double()
+        num += float(torch.linalg.norm(Hp - Ap)) ** 2
+        den += float(torch.linalg.norm(Ap)) ** 2
+        del E, Hp, Ap
+    return (num / den) ** 0.5
 
 
 def cpu_baseline(cfg, points, d_final, panel_rows):
@@ -140,8 +159,10 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="gauss65536", choices=sorted(WORKLOADS))
     ap.add_argument("--rtol", type=float, default=None)
+    ap.add_argument("--p-margin", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-panel", type=int, default=2048)
+    ap.add_argument("--no-frob", action="store_true", help="skip the exact ||A - A_HSS||_F check")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the compression path has no multi-GPU mode "
@@ -156,6 +177,8 @@ def main() -> int:
     cfg = dict(WORKLOADS[args.workload])
     if args.rtol is not None:
         cfg["rtol"] = args.rtol
+    if args.p_margin is not None:
+        cfg["p_margin"] = args.p_margin
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     print(f"[bench] workload {args.workload}: n={cfg['n']} rtol={cfg['rtol']} assembling A", file=sys.stderr,
@@ -165,7 +188,8 @@ def main() -> int:
     torch.cuda.synchronize()
     x = torch.from_numpy(np.random.default_rng(1).uniform(-1, 1, (cfg["n"], 1))).to(dev)
     b = torch.empty_like(x)
-    kw = dict(rtol=cfg["rtol"], d0=cfg["d0"], dd=cfg["dd"], d_max=cfg["d_max"], leaf_size=cfg["leaf"], seed=0)
+    kw = dict(rtol=cfg["rtol"], d0=cfg["d0"], dd=cfg["dd"], d_max=cfg["d_max"], leaf_size=cfg["leaf"],
+              p_margin=cfg["p_margin"], seed=0)
 
     def step():
         h = P.hss_compress(A, **kw)
@@ -215,6 +239,9 @@ def main() -> int:
     bh = P.hss_matvec(h, xs)
     bd = dense_matvec(A, xs)
     mv_err = float(torch.linalg.norm(bh - bd) / torch.linalg.norm(bd))
+    frob = None
+    if not args.no_frob:
+        frob = frob_error(P, h, A)
     P.hss_destroy(h)
     del A
     torch.cuda.empty_cache()
@@ -239,14 +266,15 @@ def main() -> int:
         "data": "synthetic",
         "config": {
             "workload": f"{args.workload}: n={cfg['n']} {cfg['kind']} kernel, A {cfg['storage']}, "
-                        f"leaf {cfg['leaf']}, rtol {cfg['rtol']}, d0 {cfg['d0']}, dd {cfg['dd']}, FP64 sampling",
+                        f"leaf {cfg['leaf']}, rtol {cfg['rtol']}, d0 {cfg['d0']}, dd {cfg['dd']}, "
+                        f"p_margin {cfg['p_margin']}, FP64 sampling",
             "n": cfg["n"], "rtol": cfg["rtol"], "d_final": st["d_final"], "passes": st["passes"],
             "max_rank": st["max_rank"], "converged": bool(st["converged"]),
             "step": "hss_compress + hss_matvec(nrhs=1) + hss_destroy",
         },
         "roofline": roofline,
         "cpu_baseline": cpu,
-        "accuracy": {"matvec_rel_err_vs_dense": mv_err, "bound": 10 * cfg["rtol"]},
+        "accuracy": {"matvec_rel_err_vs_dense": mv_err, "frob_rel_err": frob, "bound": 10 * cfg["rtol"]},
         "breakdown_ms": {k: round(float(np.median([s[k] for s in stats])), 2)
                          for k in ("t_total_ms", "t_sample_ms", "t_sample_gemm_ms", "t_levels_ms", "t_id_ms")},
     }

@@ -32,6 +32,8 @@
 // bound that still trips the rule.
 #include <climits>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <vector>
 
 #include "hss_internal.h"
@@ -276,6 +278,9 @@ __global__ __launch_bounds__(NT) void id_init_kernel(const DevProb* __restrict__
   }
 }
 
+// T > 0: each wavefront holds its column (rows i..d-1, T per lane) in
+// registers, so every element is read once and written once per step.
+template <int T>
 __global__ __launch_bounds__(NT) void id_step_kernel(const DevProb* __restrict__ probs,
                                                     const int* __restrict__ wg_prob, int i,
                                                     double rtol, long long tm, Work w) {
@@ -358,14 +363,35 @@ __global__ __launch_bounds__(NT) void id_step_kernel(const DevProb* __restrict__
     const int sj = step[j];
     if (sj >= 0 && sj < i) continue;
     double* __restrict__ wj = P.W + (long long)j * P.ldw;
-    double dot = 0.0;
-    for (int r = i + lane; r < d; r += 64) dot = fma(u[r - i], wj[r], dot);
-    const double f = tau * wave_sum(dot);
     double s = 0.0;
-    for (int r = i + lane; r < d; r += 64) {
-      const double v = fma(-f, u[r - i], wj[r]);
-      wj[r] = v;
-      if (r > i) s = fma(v, v, s);
+    if (T > 0) {
+      double v[T > 0 ? T : 1];
+      double dot = 0.0;
+#pragma unroll
+      for (int t = 0; t < T; ++t) {
+        const int r = i + lane + 64 * t;
+        v[t] = (r < d) ? wj[r] : 0.0;
+        dot = fma((r < d) ? u[r - i] : 0.0, v[t], dot);
+      }
+      const double f = tau * wave_sum(dot);
+#pragma unroll
+      for (int t = 0; t < T; ++t) {
+        const int r = i + lane + 64 * t;
+        if (r < d) {
+          const double nv = fma(-f, u[r - i], v[t]);
+          wj[r] = nv;
+          if (r > i) s = fma(nv, nv, s);
+        }
+      }
+    } else {
+      double dot = 0.0;
+      for (int r = i + lane; r < d; r += 64) dot = fma(u[r - i], wj[r], dot);
+      const double f = tau * wave_sum(dot);
+      for (int r = i + lane; r < d; r += 64) {
+        const double v = fma(-f, u[r - i], wj[r]);
+        wj[r] = v;
+        if (r > i) s = fma(v, v, s);
+      }
     }
     s = wave_sum(s);
     if (lane == 0) nrm_next[j] = sqrt(s);
@@ -473,6 +499,8 @@ size_t id_workspace_bytes(const IdProblem* probs, int nprob) {
 // Register-resident classes (wavefronts, columns per wavefront, rows per
 // lane) chosen so that no instance spills: -1 = use the step kernels.
 constexpr int kSmallClasses = 10;
+static int small_class(const IdProblem& p);
+static bool small_problem(const IdProblem& p) { return small_class(p) >= 0; }
 static int small_class(const IdProblem& p) {
   const int m = p.m, d = p.d;
   if (m > 256 || d > 192 || m == 0 || d == 0) return -1;
@@ -558,11 +586,29 @@ hipError_t launch_id_factor(IdProblem* probs, int nprob, double rtol, void* work
     const int* dwg = static_cast<const int*>(st.push(wg_prob.data(), wg_prob.size() * 4));
     if (!dwg) return hipErrorOutOfMemory;
     hipLaunchKernelGGL(id_init_kernel, dim3(g), dim3(NT), 0, s, dprobs, dwg, w);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
     int nlarge = 0;
     for (int q = 0; q < nprob; ++q) nlarge += h[q].g0 >= 0 ? 1 : 0;
+    const char* v = std::getenv("HSS_VERBOSE");
+    if (v && v[0] && v[0] != '0') {
+      std::fprintf(stderr, "[hss-id] %d problems, %d on the step path (%d workgroups, <= %d steps)\n",
+                   nprob, nlarge, g, smax);
+      std::fflush(stderr);
+    }
     const size_t lds = (size_t)dmax * 8;
+    const int tb = (dmax + 63) / 64;
     for (int i = 0; i < smax; ++i) {
-      hipLaunchKernelGGL(id_step_kernel, dim3(g), dim3(NT), lds, s, dprobs, dwg, i, rtol, tm, w);
+#define STEP(T_) hipLaunchKernelGGL(id_step_kernel<T_>, dim3(g), dim3(NT), lds, s, dprobs, dwg, i, rtol, tm, w)
+      if (tb <= 2) STEP(2);
+      else if (tb <= 4) STEP(4);
+      else if (tb <= 8) STEP(8);
+      else if (tb <= 16) STEP(16);
+      else if (tb <= 24) STEP(24);
+      else if (tb <= 32) STEP(32);
+      else if (tb <= 40) STEP(40);
+      else STEP(0);
+#undef STEP
       if ((i & 63) == 63 && i + 1 < smax) {  // stop early once every problem is done
         int nd = 0;
         e = hipMemcpyAsync(k_host, w.ndone, 4, hipMemcpyDeviceToHost, s);
@@ -576,8 +622,9 @@ hipError_t launch_id_factor(IdProblem* probs, int nprob, double rtol, void* work
     if (e != hipSuccess) return e;
   }
   e = hipMemcpyAsync(k_host, w.k, (size_t)nprob * 4, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) return e;
-  return hipStreamSynchronize(s);
+  return hipSuccess;
 }
 
 hipError_t launch_id_finish(const IdProblem* probs, int nprob, const int* k_host, const int* sel,
