@@ -39,7 +39,7 @@ HBM_PEAK_GBS = 8000.0
 
 WORKLOADS = {
     "gauss65536": dict(n=65536, kind="gauss", leaf=256, rtol=1e-6, d0=128, dd=64, d_max=4096,
-                       storage="f32", point_seed=4, p_margin=200),
+                       storage="f32", point_seed=4, p_margin=256),
     "circle16384": dict(n=16384, kind="log", leaf=128, rtol=1e-8, d0=128, dd=64, d_max=4096,
                         storage="f64", point_seed=2, p_margin=10),
     "toeplitz1024": dict(n=1024, kind="toeplitz", leaf=64, rtol=1e-6, d0=64, dd=32, d_max=4096,

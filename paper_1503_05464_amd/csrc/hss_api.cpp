@@ -29,6 +29,12 @@ hss_status fail(hss_status st, const std::string& msg) {
   return st;
 }
 
+}  // namespace
+
+hss_status hss::set_error(hss_status st, const std::string& msg) { return fail(st, msg); }
+
+namespace {
+
 #define HIPCHK(x)                                                                      \
   do {                                                                                 \
     hipError_t e_ = (x);                                                               \

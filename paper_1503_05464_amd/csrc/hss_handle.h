@@ -53,13 +53,14 @@ struct Node {
   double* D = nullptr;    // leaf: size x size
   double* B12 = nullptr;  // inner: kr_a x kc_b
   double* B21 = nullptr;  // inner: kr_b x kc_a
-  // ULV factors (Alg. 3); all row-major FP64
-  double* Wt = nullptr;   // W_t = D_tau(rest) - E D_tau(J): (m-k) x m, then LQ data
-  double* Wb = nullptr;   // W_b = D_tau(J): k x m
-  double* tauq = nullptr; // Householder scalars of the LQ (m-k)
-  double* Vt = nullptr;   // Vt = Q Vh: m x kc
-  double* Dt = nullptr;   // Dt = W_b Q_b^T: k x k
-  double* Dm = nullptr;   // D_tau of an inner node (merged), m x m
+  // ULV factors (Alg. 3).  Z (zrows x md, row-major, md = node dimension
+  // mr, r = md - kr) holds, after the LQ factorization of W_t:
+  //   rows 0..r-1        L (lower, row j entries 0..j) and the reflectors
+  //                      (row i entries i+1..md-1, unit leading entry);
+  //   rows r..r+kc-1     (Q Vh)^T, so columns 0..r-1 are Vt_t^T, r.. Vt_b^T;
+  //   rows r+kc..        W_b Q^T: columns 0..r-1 are W_b Q_t^T, r.. Dt.
+  double* Z = nullptr;
+  double* tau = nullptr;  // r Householder scalars
 };
 
 struct Handle {
@@ -93,12 +94,18 @@ struct Handle {
   double t_total = 0, t_sample = 0, t_levels = 0, t_id = 0, t_sgemm = 0;
   int n_sgemm = 0;
   double sgemm_flops = 0, sgemm_bytes = 0;
-  // ULV root LU (host-driven, device data)
+  // ULV root LU with partial pivoting (device data)
   double* root_lu = nullptr;
   int* root_piv = nullptr;
+  int* root_info = nullptr;
   int root_m = 0;
   long long generator_bytes() const;
 };
+
+// Records the thread-local error message returned by hss_last_error().
+hss_status set_error(hss_status st, const std::string& msg);
+hss_status matvec_impl(Handle& H, int nrhs, const double* x, long long ldx, double* b,
+                       long long ldb, hipStream_t s);
 
 }  // namespace hss
 

@@ -85,11 +85,15 @@ struct IdProblem {
   const double* Y;   // rows of Y^T: m rows, d columns, leading dimension ldy
   long long ldy;
   int m, d;
-  double* W;         // set by launch_id_factor: workspace copy, then R data
+  double* W;         // null: launch_id_factor uses a workspace copy of Y;
+                     // set by the caller: factor in place in W (ld ldw, W == Y)
   long long ldw;
   int* perm;         // m entries out: J (pivot order) then rest (increasing)
   double* E;         // (m-k) x k out (row-major, ld = k)
   int kfail;         // early exit once k > kfail and k < m is certain (-1: never)
+  int nfac;          // 0: pivoted ID; > 0: Householder QR without pivoting of
+                     // columns 0..nfac-1, the other columns only transformed
+  double* tau;       // no-pivot mode: nfac Householder scalars out
 };
 // Device workspace for a batch (carved by the launcher).
 size_t id_workspace_bytes(const IdProblem* probs, int nprob);
@@ -101,6 +105,10 @@ hipError_t launch_id_factor(IdProblem* probs, int nprob, double rtol, void* work
 // launch_id_factor on the same batch and workspace).
 hipError_t launch_id_finish(const IdProblem* probs, int nprob, const int* k_host, const int* sel,
                             int nsel, void* work, Staging& st, hipStream_t s);
+// No-pivot mode: stores reflector i (LAPACK style, unit leading entry
+// implied) in row i of W beyond the diagonal, R_ii on the diagonal, and tau.
+hipError_t launch_qr_reflectors(const IdProblem* probs, int nprob, void* work, Staging& st,
+                                hipStream_t s);
 
 // ---------------------------------------------------------------------------
 // Small helpers (kernels_misc.hip)

@@ -1,0 +1,44 @@
+// Descriptors and launchers of the ULV kernels (kernels_ulv.hip).
+#pragma once
+
+#include "hss_internal.h"
+
+namespace hss {
+
+struct VtLeafDesc {  // V^T of a leaf written as k rows of Z (m columns)
+  double* Z;
+  long long ldz;
+  int m, k;
+  const int* perm;   // J then rest
+  const double* E;   // (m-k) x k
+};
+
+struct TriDesc {     // X <- T^{-1} X on one diagonal block (nb <= 64)
+  const double* T;
+  long long ldt;
+  double* X;
+  long long ldx;
+  int nb, nrhs;
+  int lower, unit;
+};
+
+struct ReflDesc {    // V <- Q^T V or Q V, reflectors in rows of Z
+  const double* Z;
+  long long ldz;
+  const double* tau;
+  int r, m;
+  double* V;
+  long long ldv;
+  int nrhs;
+  int transpose;
+};
+
+hipError_t launch_vt_leaf(const VtLeafDesc* d, int nd, int kmax, Staging& st, hipStream_t s);
+hipError_t launch_tri_block(const TriDesc* d, int nd, Staging& st, hipStream_t s);
+hipError_t launch_reflect(const ReflDesc* d, int nd, Staging& st, hipStream_t s);
+hipError_t launch_lu_panel(double* A, long long ld, int n, int j0, int nb, int* piv, int* info,
+                           hipStream_t s);
+hipError_t launch_lu_swap(double* A, long long ld, int ncols, const int* piv, int j0, int nb,
+                          int skip0, int skip1, hipStream_t s);
+
+}  // namespace hss

@@ -64,13 +64,19 @@ struct Work {
 
 size_t al(size_t b) { return (b + 255) / 256 * 256; }
 
+// pivot steps a problem can take
+int kmax_of(const IdProblem& p) {
+  const int k = std::min(p.m, p.d);
+  return p.nfac > 0 ? std::min(p.nfac, k) : k;
+}
+
 void carve(const IdProblem* probs, int nprob, void* base, Work& w, long long& tm, long long& tk,
            long long& tw) {
   tm = tk = tw = 0;
   for (int q = 0; q < nprob; ++q) {
     tm += probs[q].m;
-    tk += std::min(probs[q].m, probs[q].d);
-    tw += (long long)probs[q].m * probs[q].d;
+    tk += kmax_of(probs[q]);
+    if (!probs[q].W) tw += (long long)probs[q].m * probs[q].d;
   }
   char* c = static_cast<char*>(base);
   auto take = [&](size_t b) {
@@ -165,11 +171,12 @@ __global__ __launch_bounds__(RW * 64) void qrcp_reg_kernel(const DevProb* __rest
       s_p = ix;
     }
     __syncthreads();
-    const double best = s_best;
-    const int p = s_p;
+    const bool nopiv = P.nfac > 0;
+    const double best = nopiv ? nrm_s[i] : s_best;
+    const int p = nopiv ? i : s_p;
     if (i == 0) nu0 = best;
-    if (best <= 0.0 || best <= rtol * nu0) break;
-    if (P.kfail >= 0 && i > P.kfail && m > d) break;
+    if (!nopiv && (best <= 0.0 || best <= rtol * nu0)) break;
+    if (!nopiv && P.kfail >= 0 && i > P.kfail && m > d) break;
     const int wp = p % RW, cp = p / RW;
     if (wave == wp) {
 #pragma unroll
@@ -182,17 +189,18 @@ __global__ __launch_bounds__(RW * 64) void qrcp_reg_kernel(const DevProb* __rest
     if (tid == 0) step_s[p] = i;
     __syncthreads();
     const double x0 = xcol[i];
-    const double alpha = -copysign(best, x0);
+    const bool zero = !(best > 0.0);
+    const double alpha = zero ? 0.0 : -copysign(best, x0);
     const double v0 = x0 - alpha;
-    const double tau = -v0 / alpha;
-    const double inv_v0 = 1.0 / v0;
+    const double tau = zero ? 0.0 : -v0 / alpha;
+    const double inv_v0 = zero ? 0.0 : 1.0 / v0;
     double uu[RPL];
 #pragma unroll
     for (int t = 0; t < RPL; ++t) {
       const int r = lane + 64 * t;
       uu[t] = (r < d && r > i) ? xcol[r] * inv_v0 : (r == i ? 1.0 : 0.0);
     }
-    if (wave == wp) {
+    if (wave == wp && !nopiv) {
 #pragma unroll
       for (int c = 0; c < CPW; ++c)
         if (c == cp) {
@@ -260,10 +268,11 @@ __global__ __launch_bounds__(NT) void id_init_kernel(const DevProb* __restrict__
   for (int j = c0 + wave; j < c1; j += NW) {
     const double* src = P.Y + (long long)j * P.ldy;
     double* dst = P.W + (long long)j * P.ldw;
+    const bool copy = src != dst;
     double s = 0.0;
     for (int r = lane; r < P.d; r += 64) {
       const double v = src[r];
-      dst[r] = v;
+      if (copy) dst[r] = v;
       s = fma(v, v, s);
     }
     s = wave_sum(s);
@@ -309,33 +318,40 @@ __global__ __launch_bounds__(NT) void id_step_kernel(const DevProb* __restrict__
   int* __restrict__ step = w.step + dp.off;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
 
-  // pivot: every workgroup of the problem reduces the same norms the same way
-  double bv = -1.0;
-  int bi = INT_MAX;
-  for (int j = tid; j < m; j += NT) {
-    const int sj = step[j];
-    if (sj < 0 || sj >= i) better(bv, bi, nrm[j], j);
-  }
+  const bool nopiv = P.nfac > 0;
+  double best;
+  int p;
+  if (nopiv) {  // columns in order
+    best = nrm[i];
+    p = i;
+  } else {  // every workgroup of the problem reduces the same norms the same way
+    double bv = -1.0;
+    int bi = INT_MAX;
+    for (int j = tid; j < m; j += NT) {
+      const int sj = step[j];
+      if (sj < 0 || sj >= i) better(bv, bi, nrm[j], j);
+    }
 #pragma unroll
-  for (int o = 32; o > 0; o >>= 1) better(bv, bi, __shfl_xor(bv, o, 64), __shfl_xor(bi, o, 64));
-  if (lane == 0) {
-    red_v[wave] = bv;
-    red_i[wave] = bi;
+    for (int o = 32; o > 0; o >>= 1) better(bv, bi, __shfl_xor(bv, o, 64), __shfl_xor(bi, o, 64));
+    if (lane == 0) {
+      red_v[wave] = bv;
+      red_i[wave] = bi;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      double v = red_v[0];
+      int ix = red_i[0];
+      for (int q2 = 1; q2 < NW; ++q2) better(v, ix, red_v[q2], red_i[q2]);
+      s_best = v;
+      s_p = ix;
+    }
+    __syncthreads();
+    best = s_best;
+    p = s_p;
   }
-  __syncthreads();
-  if (tid == 0) {
-    double v = red_v[0];
-    int ix = red_i[0];
-    for (int q2 = 1; q2 < NW; ++q2) better(v, ix, red_v[q2], red_i[q2]);
-    s_best = v;
-    s_p = ix;
-  }
-  __syncthreads();
-  const double best = s_best;
-  const int p = s_p;
   const double nu0 = (i == 0) ? best : w.nu0[q];
   if (i == 0 && leader) w.nu0[q] = best;
-  const bool stop = (best <= 0.0 || best <= rtol * nu0) || (P.kfail >= 0 && i > P.kfail && m > d);
+  const bool stop = !nopiv && ((best <= 0.0 || best <= rtol * nu0) || (P.kfail >= 0 && i > P.kfail && m > d));
   if (stop) {
     if (leader) {
       w.done[q] = 1;
@@ -345,10 +361,11 @@ __global__ __launch_bounds__(NT) void id_step_kernel(const DevProb* __restrict__
   }
   const double* __restrict__ wp = P.W + (long long)p * P.ldw;
   const double x0 = wp[i];
-  const double alpha = -copysign(best, x0);
+  const bool zero = !(best > 0.0);
+  const double alpha = zero ? 0.0 : -copysign(best, x0);
   const double v0 = x0 - alpha;
-  const double tau = -v0 / alpha;
-  const double inv_v0 = 1.0 / v0;
+  const double tau = zero ? 0.0 : -v0 / alpha;
+  const double inv_v0 = zero ? 0.0 : 1.0 / v0;
   for (int r = i + tid; r < d; r += NT) u[r - i] = (r == i) ? 1.0 : wp[r] * inv_v0;
   __syncthreads();
   if (leader) {
@@ -489,8 +506,8 @@ size_t id_workspace_bytes(const IdProblem* probs, int nprob) {
   long long tm = 0, tk = 0, tw = 0;
   for (int q = 0; q < nprob; ++q) {
     tm += probs[q].m;
-    tk += std::min(probs[q].m, probs[q].d);
-    tw += (long long)probs[q].m * probs[q].d;
+    tk += kmax_of(probs[q]);
+    if (!probs[q].W) tw += (long long)probs[q].m * probs[q].d;
   }
   return al(2 * tm * 8) + al(tm * 4) + al(tk * 8) + al(tk * 4) + 3 * al((size_t)nprob * 8) +
          al(4) + al(tw * 8) + 4096;
@@ -522,14 +539,16 @@ hipError_t launch_id_factor(IdProblem* probs, int nprob, double rtol, void* work
   std::vector<int> wg_prob, small[kSmallClasses];
   for (int q = 0; q < nprob; ++q) {
     IdProblem& p = probs[q];
-    p.ldw = p.d > 0 ? p.d : 1;
-    p.W = w.W + woff;
-    woff += (long long)p.m * p.d;
+    if (!p.W) {
+      p.ldw = p.d > 0 ? p.d : 1;
+      p.W = w.W + woff;
+      woff += (long long)p.m * p.d;
+    }
     DevProb& dp = h[q];
     dp.p = p;
     dp.off = off;
     dp.aoff = aoff;
-    dp.kmax = std::min(p.m, p.d);
+    dp.kmax = kmax_of(p);
     off += p.m;
     aoff += dp.kmax;
     dp.g0 = -1;
@@ -639,7 +658,7 @@ hipError_t launch_id_finish(const IdProblem* probs, int nprob, const int* k_host
     h[q].p = probs[q];
     h[q].off = off;
     h[q].aoff = aoff;
-    h[q].kmax = std::min(probs[q].m, probs[q].d);
+    h[q].kmax = kmax_of(probs[q]);
     off += probs[q].m;
     aoff += h[q].kmax;
   }
@@ -702,6 +721,59 @@ hipError_t launch_id_finish(const IdProblem* probs, int nprob, const int* k_host
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
+}
+
+namespace {
+// one workgroup per factored column i of a no-pivot problem
+struct RefRow {
+  int q;
+  int i;
+};
+__global__ __launch_bounds__(NT) void qr_reflector_kernel(const DevProb* __restrict__ probs,
+                                                         const RefRow* __restrict__ rows, Work w) {
+  const RefRow rr = rows[blockIdx.x];
+  const DevProb dp = probs[rr.q];
+  const IdProblem& P = dp.p;
+  const int i = rr.i;
+  double* wi = P.W + (long long)i * P.ldw;
+  const double alpha = w.alpha[dp.aoff + i];
+  const double x0 = wi[i];
+  const double v0 = x0 - alpha;
+  const bool zero = alpha == 0.0;
+  const double inv_v0 = zero ? 0.0 : 1.0 / v0;
+  __syncthreads();  // every thread has read x0 before it is replaced
+  for (int r = i + 1 + threadIdx.x; r < P.d; r += NT) wi[r] = zero ? 0.0 : wi[r] * inv_v0;
+  if (threadIdx.x == 0) {
+    wi[i] = alpha;
+    P.tau[i] = zero ? 0.0 : -v0 / alpha;
+  }
+}
+}  // namespace
+
+hipError_t launch_qr_reflectors(const IdProblem* probs, int nprob, void* work, Staging& st,
+                                hipStream_t s) {
+  Work w;
+  long long tm, tk, tw;
+  carve(probs, nprob, work, w, tm, tk, tw);
+  std::vector<DevProb> h(nprob);
+  std::vector<RefRow> rows;
+  long long off = 0, aoff = 0;
+  for (int q = 0; q < nprob; ++q) {
+    h[q].p = probs[q];
+    h[q].off = off;
+    h[q].aoff = aoff;
+    h[q].kmax = kmax_of(probs[q]);
+    off += probs[q].m;
+    aoff += h[q].kmax;
+    if (probs[q].nfac > 0)
+      for (int i = 0; i < h[q].kmax; ++i) rows.push_back(RefRow{q, i});
+  }
+  if (rows.empty()) return hipSuccess;
+  const DevProb* dprobs = static_cast<const DevProb*>(st.push(h.data(), sizeof(DevProb) * nprob));
+  const RefRow* drows = static_cast<const RefRow*>(st.push(rows.data(), rows.size() * sizeof(RefRow)));
+  if (!dprobs || !drows) return hipErrorOutOfMemory;
+  hipLaunchKernelGGL(qr_reflector_kernel, dim3((unsigned)rows.size()), dim3(NT), 0, s, dprobs, drows, w);
+  return hipGetLastError();
 }
 
 }  // namespace hss
