@@ -16,11 +16,11 @@
 //    lane l owns rows l, l+64, ...) and runs every pivot step without
 //    touching global memory;
 //  * large problems: one launch per pivot step for the whole batch; a problem
-//    is split over ceil(m/16) workgroups, each owning 16 columns; every
-//    workgroup of a problem selects the same pivot from the same norms
-//    (double-buffered between steps so no workgroup waits on another), builds
-//    the same reflector from the pivot column, and updates its own columns.
-//    Kernel boundaries order the steps.
+//    is split over ceil(m/8) workgroups of 8 wavefronts, one column per
+//    wavefront; every workgroup of a problem selects the same pivot from the
+//    same per-workgroup candidates (double-buffered between steps so no
+//    workgroup waits on another), builds the same reflector from the pivot
+//    column, and updates its own columns.  Kernel boundaries order the steps.
 // A finishing pass forms J (pivot order) and the other columns in increasing
 // order, and E = (R1^{-1} R2)^T by a blocked triangular solve whose
 // off-diagonal updates run on the batched GEMM.  It is skipped for IDs the
@@ -47,8 +47,12 @@ struct DevProb {
   long long aoff;   // into the per-step arrays (sum of kmax)
   int kmax;         // min(m, d)
   int g0;           // first workgroup of this problem (large path)
-  int cpw;          // columns per workgroup (large path)
+  int G;            // workgroups of this problem (large path)
 };
+
+constexpr int NT = 256;      // threads of the finishing kernels
+constexpr int SW = 8;        // wavefronts (= columns) per step workgroup
+constexpr int ST = SW * 64;  // threads per step workgroup
 
 struct Work {
   double* nrm;   // 2 * sum(m): double-buffered norms
@@ -59,6 +63,8 @@ struct Work {
   int* done;     // nprob
   double* nu0;   // nprob
   int* ndone;    // 1
+  double* cand_v;  // 2 * tg: per-workgroup pivot candidates (step parity)
+  int* cand_i;     // 2 * tg
   double* W;     // sum(m * d)
 };
 
@@ -73,7 +79,9 @@ int kmax_of(const IdProblem& p) {
 void carve(const IdProblem* probs, int nprob, void* base, Work& w, long long& tm, long long& tk,
            long long& tw) {
   tm = tk = tw = 0;
+  long long tg = 0;
   for (int q = 0; q < nprob; ++q) {
+    tg += (probs[q].m + SW - 1) / SW;
     tm += probs[q].m;
     tk += kmax_of(probs[q]);
     if (!probs[q].W) tw += (long long)probs[q].m * probs[q].d;
@@ -92,6 +100,8 @@ void carve(const IdProblem* probs, int nprob, void* base, Work& w, long long& tm
   w.done = reinterpret_cast<int*>(take((size_t)nprob * 4));
   w.nu0 = reinterpret_cast<double*>(take((size_t)nprob * 8));
   w.ndone = reinterpret_cast<int*>(take(4));
+  w.cand_v = reinterpret_cast<double*>(take(2 * tg * 8));
+  w.cand_i = reinterpret_cast<int*>(take(2 * tg * 4));
   w.W = reinterpret_cast<double*>(take(tw * 8));
 }
 
@@ -253,19 +263,45 @@ __global__ __launch_bounds__(RW * 64) void qrcp_reg_kernel(const DevProb* __rest
 
 // ---------------------------------------------------------------------------
 // large problems: one launch per pivot step
+//
+// Workgroup g of a problem owns columns g*SW .. g*SW+SW-1, one per
+// wavefront.  After its update every workgroup publishes its best remaining
+// column (norm, index) for the next step (double-buffered by step parity);
+// the next step's workgroups all reduce the same candidates the same way.
+// The workgroup stages the reflector in LDS; each wavefront keeps its own
+// column (rows i..d-1, T per lane) in registers, so every element is read
+// once and written once per step.
 // ---------------------------------------------------------------------------
-constexpr int NT = 256;
-constexpr int NW = NT / 64;
+__device__ __forceinline__ void wg_candidate(double v, int j, double* rv, int* ri, double* cv,
+                                             int* ci) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) {
+    rv[wave] = v;
+    ri[wave] = j;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double bv = rv[0];
+    int bi = ri[0];
+    for (int t = 1; t < SW; ++t) better(bv, bi, rv[t], ri[t]);
+    *cv = bv;
+    *ci = bi;
+  }
+}
 
-__global__ __launch_bounds__(NT) void id_init_kernel(const DevProb* __restrict__ probs,
-                                                    const int* __restrict__ wg_prob, Work w) {
+__global__ __launch_bounds__(ST) void id_init_kernel(const DevProb* __restrict__ probs,
+                                                    const int* __restrict__ wg_prob, long long tg,
+                                                    Work w) {
+  __shared__ double rv[SW];
+  __shared__ int ri[SW];
   const int q = wg_prob[blockIdx.x];
   const DevProb dp = probs[q];
   const IdProblem& P = dp.p;
   const int g = blockIdx.x - dp.g0;
-  const int c0 = g * dp.cpw, c1 = min(P.m, c0 + dp.cpw);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  for (int j = c0 + wave; j < c1; j += NW) {
+  const int j = g * SW + wave;
+  double nv = -1.0;
+  if (j < P.m) {
     const double* src = P.Y + (long long)j * P.ldy;
     double* dst = P.W + (long long)j * P.ldw;
     const bool copy = src != dst;
@@ -275,27 +311,27 @@ __global__ __launch_bounds__(NT) void id_init_kernel(const DevProb* __restrict__
       if (copy) dst[r] = v;
       s = fma(v, v, s);
     }
-    s = wave_sum(s);
+    nv = sqrt(wave_sum(s));
     if (lane == 0) {
-      w.nrm[dp.off + j] = sqrt(s);
+      w.nrm[dp.off + j] = nv;
       w.step[dp.off + j] = -1;
     }
   }
+  wg_candidate(nv, j < P.m ? j : INT_MAX, rv, ri, w.cand_v + blockIdx.x, w.cand_i + blockIdx.x);
   if (g == 0 && threadIdx.x == 0) {
     w.done[q] = 0;
     w.k[q] = 0;
   }
 }
 
-// T > 0: each wavefront holds its column (rows i..d-1, T per lane) in
-// registers, so every element is read once and written once per step.
 template <int T>
-__global__ __launch_bounds__(NT) void id_step_kernel(const DevProb* __restrict__ probs,
+__global__ __launch_bounds__(ST) void id_step_kernel(const DevProb* __restrict__ probs,
                                                     const int* __restrict__ wg_prob, int i,
-                                                    double rtol, long long tm, Work w) {
-  extern __shared__ double u[];
-  __shared__ double red_v[NW];
-  __shared__ int red_i[NW];
+                                                    double rtol, long long tm, long long tg,
+                                                    Work w) {
+  extern __shared__ double u[];  // T > 0: rows i..d-1 of the reflector
+  __shared__ double rv[SW];
+  __shared__ int ri[SW];
   __shared__ double s_best;
   __shared__ int s_p;
 
@@ -317,31 +353,29 @@ __global__ __launch_bounds__(NT) void id_step_kernel(const DevProb* __restrict__
   double* __restrict__ nrm_next = w.nrm + ((i + 1) & 1) * tm + dp.off;
   int* __restrict__ step = w.step + dp.off;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-
   const bool nopiv = P.nfac > 0;
   double best;
   int p;
   if (nopiv) {  // columns in order
     best = nrm[i];
     p = i;
-  } else {  // every workgroup of the problem reduces the same norms the same way
+  } else {  // all workgroups of the problem reduce the same candidates the same way
+    const double* cv = w.cand_v + (i & 1) * tg + dp.g0;
+    const int* ci = w.cand_i + (i & 1) * tg + dp.g0;
     double bv = -1.0;
     int bi = INT_MAX;
-    for (int j = tid; j < m; j += NT) {
-      const int sj = step[j];
-      if (sj < 0 || sj >= i) better(bv, bi, nrm[j], j);
-    }
+    for (int t = tid; t < dp.G; t += ST) better(bv, bi, cv[t], ci[t]);
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) better(bv, bi, __shfl_xor(bv, o, 64), __shfl_xor(bi, o, 64));
     if (lane == 0) {
-      red_v[wave] = bv;
-      red_i[wave] = bi;
+      rv[wave] = bv;
+      ri[wave] = bi;
     }
     __syncthreads();
     if (tid == 0) {
-      double v = red_v[0];
-      int ix = red_i[0];
-      for (int q2 = 1; q2 < NW; ++q2) better(v, ix, red_v[q2], red_i[q2]);
+      double v = rv[0];
+      int ix = ri[0];
+      for (int t = 1; t < SW; ++t) better(v, ix, rv[t], ri[t]);
       s_best = v;
       s_p = ix;
     }
@@ -351,7 +385,8 @@ __global__ __launch_bounds__(NT) void id_step_kernel(const DevProb* __restrict__
   }
   const double nu0 = (i == 0) ? best : w.nu0[q];
   if (i == 0 && leader) w.nu0[q] = best;
-  const bool stop = !nopiv && ((best <= 0.0 || best <= rtol * nu0) || (P.kfail >= 0 && i > P.kfail && m > d));
+  const bool stop =
+      !nopiv && ((best <= 0.0 || best <= rtol * nu0) || (P.kfail >= 0 && i > P.kfail && m > d));
   if (stop) {
     if (leader) {
       w.done[q] = 1;
@@ -366,52 +401,66 @@ __global__ __launch_bounds__(NT) void id_step_kernel(const DevProb* __restrict__
   const double v0 = x0 - alpha;
   const double tau = zero ? 0.0 : -v0 / alpha;
   const double inv_v0 = zero ? 0.0 : 1.0 / v0;
-  for (int r = i + tid; r < d; r += NT) u[r - i] = (r == i) ? 1.0 : wp[r] * inv_v0;
-  __syncthreads();
   if (leader) {
     w.alpha[dp.aoff + i] = alpha;
     w.piv[dp.aoff + i] = p;
     step[p] = i;
     w.k[q] = i + 1;
   }
-  const int c0 = g * dp.cpw, c1 = min(m, c0 + dp.cpw);
-  for (int j = c0 + wave; j < c1; j += NW) {
-    if (j == p) continue;
+  // the reflector u = (1, W[p][i+1..d-1] / v0), staged once per workgroup
+  if (T > 0) {
+    for (int r = i + tid; r < d; r += ST) u[r - i] = (r == i) ? 1.0 : wp[r] * inv_v0;
+    __syncthreads();
+  }
+  const int j = g * SW + wave;
+  bool act = j < m && j != p;
+  if (act) {
     const int sj = step[j];
-    if (sj >= 0 && sj < i) continue;
+    act = !(sj >= 0 && sj < i);
+  }
+  double nv = -1.0;
+  if (act) {
     double* __restrict__ wj = P.W + (long long)j * P.ldw;
     double s = 0.0;
     if (T > 0) {
-      double v[T > 0 ? T : 1];
+      double y[T > 0 ? T : 1];
       double dot = 0.0;
 #pragma unroll
       for (int t = 0; t < T; ++t) {
         const int r = i + lane + 64 * t;
-        v[t] = (r < d) ? wj[r] : 0.0;
-        dot = fma((r < d) ? u[r - i] : 0.0, v[t], dot);
+        y[t] = (r < d) ? wj[r] : 0.0;
+      }
+#pragma unroll
+      for (int t = 0; t < T; ++t) {
+        const int r = i + lane + 64 * t;
+        if (r < d) dot = fma(u[r - i], y[t], dot);
       }
       const double f = tau * wave_sum(dot);
 #pragma unroll
       for (int t = 0; t < T; ++t) {
         const int r = i + lane + 64 * t;
         if (r < d) {
-          const double nv = fma(-f, u[r - i], v[t]);
-          wj[r] = nv;
-          if (r > i) s = fma(nv, nv, s);
+          const double nvv = fma(-f, u[r - i], y[t]);
+          wj[r] = nvv;
+          if (r > i) s = fma(nvv, nvv, s);
         }
       }
     } else {
       double dot = 0.0;
-      for (int r = i + lane; r < d; r += 64) dot = fma(u[r - i], wj[r], dot);
+      for (int r = i + lane; r < d; r += 64) dot = fma(r == i ? 1.0 : wp[r] * inv_v0, wj[r], dot);
       const double f = tau * wave_sum(dot);
       for (int r = i + lane; r < d; r += 64) {
-        const double v = fma(-f, u[r - i], wj[r]);
+        const double v = fma(-f, r == i ? 1.0 : wp[r] * inv_v0, wj[r]);
         wj[r] = v;
         if (r > i) s = fma(v, v, s);
       }
     }
-    s = wave_sum(s);
-    if (lane == 0) nrm_next[j] = sqrt(s);
+    nv = sqrt(wave_sum(s));
+    if (lane == 0) nrm_next[j] = nv;
+  }
+  if (!nopiv) {
+    const long long slot = ((i + 1) & 1) * tg + blockIdx.x;
+    wg_candidate(act ? nv : -1.0, act ? j : INT_MAX, rv, ri, w.cand_v + slot, w.cand_i + slot);
   }
 }
 
@@ -503,14 +552,15 @@ __global__ __launch_bounds__(NT) void trsm_diag_kernel(const DiagDesc* __restric
 }  // namespace
 
 size_t id_workspace_bytes(const IdProblem* probs, int nprob) {
-  long long tm = 0, tk = 0, tw = 0;
+  long long tm = 0, tk = 0, tw = 0, tg = 0;
   for (int q = 0; q < nprob; ++q) {
+    tg += (probs[q].m + SW - 1) / SW;
     tm += probs[q].m;
     tk += kmax_of(probs[q]);
     if (!probs[q].W) tw += (long long)probs[q].m * probs[q].d;
   }
   return al(2 * tm * 8) + al(tm * 4) + al(tk * 8) + al(tk * 4) + 3 * al((size_t)nprob * 8) +
-         al(4) + al(tw * 8) + 4096;
+         al(4) + al(2 * tg * 8) + al(2 * tg * 4) + al(tw * 8) + 4096;
 }
 
 // Register-resident classes (wavefronts, columns per wavefront, rows per
@@ -552,7 +602,7 @@ hipError_t launch_id_factor(IdProblem* probs, int nprob, double rtol, void* work
     off += p.m;
     aoff += dp.kmax;
     dp.g0 = -1;
-    dp.cpw = 16;
+    dp.G = 0;
     if (p.m == 0 || p.d == 0) {
       dp.kmax = 0;
     }
@@ -561,16 +611,15 @@ hipError_t launch_id_factor(IdProblem* probs, int nprob, double rtol, void* work
       small[sc].push_back(q);
     } else {
       dp.g0 = g;
-      const int G = (p.m + dp.cpw - 1) / dp.cpw;
-      for (int t = 0; t < G; ++t) wg_prob.push_back(q);
-      g += G;
+      dp.G = (p.m + SW - 1) / SW;
+      for (int t = 0; t < dp.G; ++t) wg_prob.push_back(q);
+      g += dp.G;
       dmax = std::max(dmax, p.d);
       int steps = dp.kmax;
       if (p.kfail >= 0 && p.m > p.d) steps = std::min(steps, p.kfail + 2);
       smax = std::max(smax, steps);
     }
   }
-  if ((size_t)dmax * 8 > 64 * 1024) return hipErrorInvalidValue;
   const DevProb* dprobs = static_cast<const DevProb*>(st.push(h.data(), sizeof(DevProb) * nprob));
   if (!dprobs) return hipErrorOutOfMemory;
   hipError_t e = hipMemsetAsync(w.ndone, 0, 4, s);
@@ -604,7 +653,9 @@ hipError_t launch_id_factor(IdProblem* probs, int nprob, double rtol, void* work
   if (g > 0) {
     const int* dwg = static_cast<const int*>(st.push(wg_prob.data(), wg_prob.size() * 4));
     if (!dwg) return hipErrorOutOfMemory;
-    hipLaunchKernelGGL(id_init_kernel, dim3(g), dim3(NT), 0, s, dprobs, dwg, w);
+    long long tg = 0;
+    for (int q = 0; q < nprob; ++q) tg += (probs[q].m + SW - 1) / SW;
+    hipLaunchKernelGGL(id_init_kernel, dim3(g), dim3(ST), 0, s, dprobs, dwg, tg, w);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     int nlarge = 0;
@@ -615,18 +666,23 @@ hipError_t launch_id_factor(IdProblem* probs, int nprob, double rtol, void* work
                    nprob, nlarge, g, smax);
       std::fflush(stderr);
     }
-    const size_t lds = (size_t)dmax * 8;
-    const int tb = (dmax + 63) / 64;
+    const size_t lds = dmax <= 64 * 40 ? (size_t)dmax * 8 : 0;
     for (int i = 0; i < smax; ++i) {
-#define STEP(T_) hipLaunchKernelGGL(id_step_kernel<T_>, dim3(g), dim3(NT), lds, s, dprobs, dwg, i, rtol, tm, w)
-      if (tb <= 2) STEP(2);
+      // rows i..d-1 are active: registers per lane follow the largest d - i
+      const int tb = (dmax - i + 63) / 64;
+#define STEP(T_) hipLaunchKernelGGL(id_step_kernel<T_>, dim3(g), dim3(ST), lds, s, dprobs, dwg, i, rtol, tm, tg, w)
+      if (dmax > 64 * 40) STEP(0);
+      else if (tb <= 2) STEP(2);
       else if (tb <= 4) STEP(4);
       else if (tb <= 8) STEP(8);
+      else if (tb <= 12) STEP(12);
       else if (tb <= 16) STEP(16);
+      else if (tb <= 20) STEP(20);
       else if (tb <= 24) STEP(24);
+      else if (tb <= 28) STEP(28);
       else if (tb <= 32) STEP(32);
-      else if (tb <= 40) STEP(40);
-      else STEP(0);
+      else if (tb <= 36) STEP(36);
+      else STEP(40);
 #undef STEP
       if ((i & 63) == 63 && i + 1 < smax) {  // stop early once every problem is done
         int nd = 0;
