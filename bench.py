@@ -155,7 +155,7 @@ def cpu_baseline(cfg, points, d_final, panel_rows):
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="gauss65536", choices=sorted(WORKLOADS))
     ap.add_argument("--rtol", type=float, default=None)
