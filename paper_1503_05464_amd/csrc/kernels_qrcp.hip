@@ -30,10 +30,12 @@
 // m) is certain -- more than kfail pivots accepted and m > d, so the rank can
 // not reach m -- the factorization stops; the reported rank is then a lower
 // bound that still trips the rule.
+#include <algorithm>
 #include <climits>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
+#include <cstring>
 #include <vector>
 
 #include "hss_internal.h"
@@ -65,6 +67,10 @@ struct Work {
   int* ndone;    // 1
   double* cand_v;  // 2 * tg: per-workgroup pivot candidates (step parity)
   int* cand_i;     // 2 * tg
+  double* cbuf;    // 2 * tg * ldcb: candidate columns (persistent path)
+  long long ldcb;  // max d
+  int* stamp;      // 2 * tg: step stamp of each published candidate (persistent path)
+  int* err;        // 1: a wait for a candidate timed out (persistent path)
   double* W;     // sum(m * d)
 };
 
@@ -79,11 +85,12 @@ int kmax_of(const IdProblem& p) {
 void carve(const IdProblem* probs, int nprob, void* base, Work& w, long long& tm, long long& tk,
            long long& tw) {
   tm = tk = tw = 0;
-  long long tg = 0;
+  long long tg = 0, dm = 1;
   for (int q = 0; q < nprob; ++q) {
     tg += (probs[q].m + SW - 1) / SW;
     tm += probs[q].m;
     tk += kmax_of(probs[q]);
+    dm = std::max<long long>(dm, probs[q].d);
     if (!probs[q].W) tw += (long long)probs[q].m * probs[q].d;
   }
   char* c = static_cast<char*>(base);
@@ -102,6 +109,10 @@ void carve(const IdProblem* probs, int nprob, void* base, Work& w, long long& tm
   w.ndone = reinterpret_cast<int*>(take(4));
   w.cand_v = reinterpret_cast<double*>(take(2 * tg * 8));
   w.cand_i = reinterpret_cast<int*>(take(2 * tg * 4));
+  w.ldcb = dm;
+  w.cbuf = reinterpret_cast<double*>(take(2 * tg * dm * 8));
+  w.stamp = reinterpret_cast<int*>(take(2 * tg * 4));
+  w.err = reinterpret_cast<int*>(take(4));
   w.W = reinterpret_cast<double*>(take(tw * 8));
 }
 
@@ -109,6 +120,31 @@ __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
   return v;
+}
+
+// wavefront sums of N values at once: butterfly over lanes, the first four
+// levels by DPP (quad permutes, then half-row and row mirrors), the last two
+// by cross-row shuffles.  Every lane ends with the same sums.
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+template <int N>
+__device__ __forceinline__ void wave_sum_n(double (&v)[N]) {
+#pragma unroll
+  for (int c = 0; c < N; ++c) v[c] += dpp_d<0xB1>(v[c]);  // quad_perm [1,0,3,2]
+#pragma unroll
+  for (int c = 0; c < N; ++c) v[c] += dpp_d<0x4E>(v[c]);  // quad_perm [2,3,0,1]
+#pragma unroll
+  for (int c = 0; c < N; ++c) v[c] += dpp_d<0x141>(v[c]);  // row_half_mirror
+#pragma unroll
+  for (int c = 0; c < N; ++c) v[c] += dpp_d<0x140>(v[c]);  // row_mirror
+#pragma unroll
+  for (int c = 0; c < N; ++c) v[c] += __shfl_xor(v[c], 16, 64);
+#pragma unroll
+  for (int c = 0; c < N; ++c) v[c] += __shfl_xor(v[c], 32, 64);
 }
 
 __device__ __forceinline__ void better(double& bv, int& bi, double ov, int oi) {
@@ -465,6 +501,257 @@ __global__ __launch_bounds__(ST) void id_step_kernel(const DevProb* __restrict__
 }
 
 // ---------------------------------------------------------------------------
+// large problems, persistent: one cooperative launch runs every pivot step.
+//
+// Workgroup g of a problem owns columns g*PW*C .. (g+1)*PW*C-1, C per
+// wavefront, and keeps them in registers for the whole factorization (lane l
+// holds rows l, l+64, ..., T per column).  After each step the workgroup
+// publishes its best remaining column -- norm, index and values -- in a slot
+// of its own (double-buffered by step parity) and then stamps the slot with
+// the step number.  Every workgroup of the problem waits for the G stamps of
+// the step, reduces the same candidates the same way, reads the winner's
+// published values as the reflector and updates its own columns.  Per step,
+// global memory carries only the candidates and one column per workgroup.
+//
+// Published data is written and read with device-scope (coherent) accesses;
+// a workgroup stamps its slot only after its data stores have completed.  No
+// read-modify-write atomics are used.  The wait for a stamp is bounded: a
+// workgroup that waits too long raises the error flag and leaves, and so
+// does every workgroup that sees the flag; the factorization is then
+// reported as failed and nothing is written back.
+// ---------------------------------------------------------------------------
+constexpr int PW = 4;        // wavefronts per persistent workgroup
+constexpr int PT = PW * 64;  // threads per persistent workgroup
+constexpr int kSpinLimit = 1 << 22;
+
+template <typename V>
+__device__ __forceinline__ void st_dev(V* p, V v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename V>
+__device__ __forceinline__ V ld_dev(const V* p) {
+  return __hip_atomic_load(const_cast<V*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <int T, int C>
+__global__ __launch_bounds__(PT) void qrcp_persist_kernel(const DevProb* __restrict__ probs,
+                                                         const int* __restrict__ wg_prob,
+                                                         double rtol, Work w) {
+  __shared__ double u[T * 64];
+  __shared__ double rv[PW];
+  __shared__ int ri[PW];
+  __shared__ double s_best;
+  __shared__ int s_p;
+  __shared__ int s_ok;
+
+  const int q = wg_prob[blockIdx.x];
+  const DevProb dp = probs[q];
+  const IdProblem& P = dp.p;
+  const int m = P.m, d = P.d;
+  const int g = blockIdx.x - dp.g0;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const bool leader = (g == 0 && tid == 0);
+  constexpr int CPG = PW * C;  // columns per workgroup
+  const int jb = g * CPG + wave * C;
+  int* __restrict__ step = w.step + dp.off;
+  const long long ldcb = w.ldcb;
+  const long long nslot = gridDim.x;
+
+  double y[C][T];
+  double nv[C];
+  unsigned sel = 0;  // columns of this wavefront already chosen as pivots
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+    const int j = jb + c;
+    double s = 0.0;
+#pragma unroll
+    for (int t = 0; t < T; ++t) {
+      const int r = lane + 64 * t;
+      const double v = (j < m && r < d) ? P.Y[(long long)j * P.ldy + r] : 0.0;
+      y[c][t] = v;
+      s = fma(v, v, s);
+    }
+    nv[c] = (j < m) ? sqrt(wave_sum(s)) : -1.0;
+    if (j < m && lane == 0) step[j] = -1;
+    asm volatile("" ::: "memory");  // one column's loads in flight at a time
+  }
+  if (tid == 0) s_ok = 1;
+
+  // publish this workgroup's best column for step i (norm, index, rows >= i)
+  auto publish = [&](int i) {
+    double bv = -1.0;
+    int bi = INT_MAX;
+#pragma unroll
+    for (int c = 0; c < C; ++c)
+      if (!((sel >> c) & 1u) && jb + c < m) better(bv, bi, nv[c], jb + c);
+    if (lane == 0) {
+      rv[wave] = bv;
+      ri[wave] = bi;
+    }
+    __syncthreads();
+    double v = rv[0];
+    int ix = ri[0];
+#pragma unroll
+    for (int t = 1; t < PW; ++t) better(v, ix, rv[t], ri[t]);
+    const long long slot = (long long)(i & 1) * nslot + blockIdx.x;
+    if (tid == 0) {
+      st_dev(w.cand_v + slot, v);
+      st_dev(w.cand_i + slot, ix);
+    }
+    double* dst = w.cbuf + slot * ldcb;
+#pragma unroll
+    for (int c = 0; c < C; ++c)
+      if (jb + c == ix) {
+#pragma unroll
+        for (int t = 0; t < T; ++t) {
+          const int r = lane + 64 * t;
+          if (r >= i && r < d) st_dev(dst + r, y[c][t]);
+        }
+      }
+    __builtin_amdgcn_s_waitcnt(0);  // this thread's stores have completed
+    __syncthreads();                // ... and every other thread's
+    if (tid == 0) st_dev(w.stamp + slot, i + 1);
+  };
+
+  // wait for the problem's G candidates of step i; false on a timeout
+  auto gather = [&](int i) -> bool {
+    const long long base = (long long)(i & 1) * nslot + dp.g0;
+    double bv = -1.0;
+    int bi = INT_MAX;
+    bool ok = true;
+    for (int t = tid; t < dp.G && ok; t += PT) {
+      int spins = 0;
+      while (ld_dev(w.stamp + base + t) != i + 1) {
+        if ((++spins & 63) == 0) {
+          if (ld_dev(w.err)) {
+            ok = false;
+            break;
+          }
+          if (spins >= kSpinLimit) {
+            st_dev(w.err, 1);
+            ok = false;
+            break;
+          }
+        }
+        __builtin_amdgcn_s_sleep(1);
+      }
+      if (ok) better(bv, bi, ld_dev(w.cand_v + base + t), ld_dev(w.cand_i + base + t));
+    }
+    if (!ok) s_ok = 0;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) better(bv, bi, __shfl_xor(bv, o, 64), __shfl_xor(bi, o, 64));
+    if (lane == 0) {
+      rv[wave] = bv;
+      ri[wave] = bi;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      double v = rv[0];
+      int ix = ri[0];
+      for (int t = 1; t < PW; ++t) better(v, ix, rv[t], ri[t]);
+      s_best = v;
+      s_p = ix;
+    }
+    __syncthreads();
+    return s_ok != 0;
+  };
+
+  publish(0);
+  double nu0 = 0.0;
+  int k = 0;
+  for (int i = 0; i < dp.kmax; ++i) {
+    if (!gather(i)) return;
+    const double best = s_best;
+    const int p = s_p;
+    if (i == 0) nu0 = best;
+    if (best <= 0.0 || best <= rtol * nu0) break;
+    if (P.kfail >= 0 && i > P.kfail && m > d) break;
+    const int gp = p / CPG;  // the workgroup that published column p
+    const double* xp = w.cbuf + ((long long)(i & 1) * nslot + dp.g0 + gp) * ldcb;
+    // the winner's rows i..d-1 into LDS, all loads in flight together
+#pragma unroll
+    for (int t = 0; t < T / PW; ++t) {
+      const int r = tid + PT * t;
+      const double v = ld_dev(xp + min(max(r, i), d - 1));  // in bounds, unconditional
+      u[r] = (r >= i && r < d) ? v : 0.0;
+    }
+    __syncthreads();
+    const double x0 = u[i];
+    const double alpha = -copysign(best, x0);
+    const double v0 = x0 - alpha;
+    const double tau = -v0 / alpha;
+    const double inv_v0 = 1.0 / v0;
+    __syncthreads();  // x0 read before row i is rewritten
+#pragma unroll
+    for (int t = 0; t < T / PW; ++t) {
+      const int r = tid + PT * t;
+      u[r] = (r == i) ? 1.0 : u[r] * inv_v0;
+    }
+    if (p >= jb && p < jb + C) {
+      sel |= 1u << (p - jb);
+      // the owner marks its column: the same wavefront wrote its -1, and
+      // plain stores from different workgroups may sit in different caches
+      if (lane == 0) step[p] = i;
+    }
+    if (leader) {
+      w.alpha[dp.aoff + i] = alpha;
+      w.piv[dp.aoff + i] = p;
+    }
+    __syncthreads();
+    // rows below i are finished: slices t < i/64 are skipped (uniform
+    // branch).  The C columns go through each phase together, so their
+    // dependency chains and reductions overlap.
+    const int ti = i >> 6;
+    double f[C], s2[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) f[c] = 0.0;
+#pragma unroll
+    for (int t = 0; t < T; ++t) {
+      if (t < ti) continue;
+      const double ut = u[lane + 64 * t];
+#pragma unroll
+      for (int c = 0; c < C; ++c) f[c] = fma(ut, y[c][t], f[c]);
+    }
+    wave_sum_n<C>(f);
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      const bool live = !((sel >> c) & 1u) && jb + c < m;  // pivots stay as they are
+      f[c] = live ? tau * f[c] : 0.0;
+      s2[c] = 0.0;
+    }
+#pragma unroll
+    for (int t = 0; t < T; ++t) {
+      if (t < ti) continue;
+      const double ut = u[lane + 64 * t];
+      const bool below = t > ti || lane > (i & 63);
+#pragma unroll
+      for (int c = 0; c < C; ++c) {
+        const double v = fma(-f[c], ut, y[c][t]);
+        y[c][t] = v;
+        if (below) s2[c] = fma(v, v, s2[c]);
+      }
+    }
+    wave_sum_n<C>(s2);
+#pragma unroll
+    for (int c = 0; c < C; ++c) nv[c] = sqrt(s2[c]);
+    k = i + 1;
+    if (i + 1 < dp.kmax) publish(i + 1);
+  }
+  if (leader) w.k[q] = k;
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+    const int j = jb + c;
+    if (j >= m) continue;
+#pragma unroll
+    for (int t = 0; t < T; ++t) {
+      const int r = lane + 64 * t;
+      if (r < d) P.W[(long long)j * P.ldw + r] = y[c][t];
+    }
+    asm volatile("" ::: "memory");
+  }
+}
+
+// ---------------------------------------------------------------------------
 // finishing: permutation, diagonal of R1, blocked E = (R1^{-1} R2)^T
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(NT) void id_perm_kernel(const DevProb* __restrict__ probs,
@@ -552,15 +839,17 @@ __global__ __launch_bounds__(NT) void trsm_diag_kernel(const DiagDesc* __restric
 }  // namespace
 
 size_t id_workspace_bytes(const IdProblem* probs, int nprob) {
-  long long tm = 0, tk = 0, tw = 0, tg = 0;
+  long long tm = 0, tk = 0, tw = 0, tg = 0, dm = 1;
   for (int q = 0; q < nprob; ++q) {
     tg += (probs[q].m + SW - 1) / SW;
     tm += probs[q].m;
     tk += kmax_of(probs[q]);
+    dm = std::max<long long>(dm, probs[q].d);
     if (!probs[q].W) tw += (long long)probs[q].m * probs[q].d;
   }
   return al(2 * tm * 8) + al(tm * 4) + al(tk * 8) + al(tk * 4) + 3 * al((size_t)nprob * 8) +
-         al(4) + al(2 * tg * 8) + al(2 * tg * 4) + al(tw * 8) + 4096;
+         al(4) + al(2 * tg * 8) + al(2 * tg * 4) + al(2 * tg * dm * 8) + al(2 * tg * 4) +
+         al(4) + al(tw * 8) + 4096;
 }
 
 // Register-resident classes (wavefronts, columns per wavefront, rows per
@@ -576,6 +865,141 @@ static int small_class(const IdProblem& p) {
   return m <= 64 ? 7 : m <= 128 ? 8 : 9;
 }
 
+// Persistent-path variants: T rows per lane (d <= 64 T), C columns per
+// wavefront, sized so that the columns fit in the register file.
+struct PVariant {
+  int T, C;
+  const void* fn;
+};
+static const PVariant kPVariants[] = {
+    {8, 20, reinterpret_cast<const void*>(&qrcp_persist_kernel<8, 20>)},
+    {16, 12, reinterpret_cast<const void*>(&qrcp_persist_kernel<16, 12>)},
+    {24, 8, reinterpret_cast<const void*>(&qrcp_persist_kernel<24, 8>)},
+    {32, 6, reinterpret_cast<const void*>(&qrcp_persist_kernel<32, 6>)},
+    {40, 4, reinterpret_cast<const void*>(&qrcp_persist_kernel<40, 4>)},
+};
+
+// cost model constants (measured on gfx950): time per pivot step of a
+// persistent launch, the floor of one step-path launch, and the HBM rate the
+// step path reaches
+constexpr double kPersistStepUs = 16.0;
+constexpr double kStepFloorUs = 25.0;
+constexpr double kStepBytesPerS = 4.5e12;
+
+static int resident_workgroups(const void* fn) {
+  int dev = 0, cus = 0, per = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fn, PT, 0) != hipSuccess) return 0;
+  return per * cus;
+}
+
+// Runs the pivoted problems of `large` whose columns fit in registers as
+// cooperative launches (problems grouped while their workgroups fit on the
+// device at once); the others are returned in `rest`.
+static hipError_t run_persistent(std::vector<DevProb>& h, const std::vector<int>& large, double rtol,
+                                 const Work& w, Staging& st, hipStream_t s, std::vector<int>& rest,
+                                 int& npersist, int& nlaunch) {
+  int dmax = 0;
+  std::vector<int> cand;
+  for (int q : large) {
+    const IdProblem& p = h[q].p;
+    if (p.nfac > 0 || h[q].kmax == 0 || p.d > 64 * 40) rest.push_back(q);
+    else {
+      cand.push_back(q);
+      dmax = std::max(dmax, p.d);
+    }
+  }
+  if (cand.empty()) return hipSuccess;
+  // HSS_QRCP_PATH = step | persistent forces a path; otherwise a cost model
+  // picks one for the whole batch
+  const char* env = std::getenv("HSS_QRCP_PATH");
+  const bool force_step = env && std::strcmp(env, "step") == 0;
+  const bool force_pers = env && std::strcmp(env, "persistent") == 0;
+  if (force_step) {
+    rest.insert(rest.end(), cand.begin(), cand.end());
+    return hipSuccess;
+  }
+  int v = 0;
+  while (kPVariants[v].T * 64 < dmax) ++v;
+  const PVariant& pv = kPVariants[v];
+  const int cpg = PW * pv.C;
+  const int maxwg = resident_workgroups(pv.fn);
+  if (!force_pers) {
+    // persistent: launches run one after another, each ~kPersistStepUs per
+    // step; step path: one launch per step for the whole batch, bound by
+    // the larger of the launch floor and the traffic (read + write of the
+    // active rows)
+    double t_pers = 0.0, bytes = 0.0;
+    int smax = 0, nwg = 0, lsteps = 0;
+    for (int q : cand) {
+      const IdProblem& p = h[q].p;
+      int steps = h[q].kmax;
+      if (p.kfail >= 0 && p.m > p.d) steps = std::min(steps, p.kfail + 2);
+      smax = std::max(smax, steps);
+      bytes += 16.0 * p.m * std::max(1.0, p.d - 0.5 * steps);  // per step, averaged
+      const int G = (p.m + cpg - 1) / cpg;
+      if (G > maxwg) continue;
+      if (nwg + G > maxwg) {
+        t_pers += lsteps * kPersistStepUs;
+        nwg = 0;
+        lsteps = 0;
+      }
+      nwg += G;
+      lsteps = std::max(lsteps, steps);
+    }
+    t_pers += lsteps * kPersistStepUs;
+    const double t_step = smax * std::max(kStepFloorUs, bytes * 1e6 / kStepBytesPerS);
+    if (maxwg <= 0 || t_pers >= t_step) {
+      rest.insert(rest.end(), cand.begin(), cand.end());
+      return hipSuccess;
+    }
+  }
+  size_t i0 = 0;
+  while (i0 < cand.size()) {
+    std::vector<int> batch, wgp;
+    int nwg = 0;
+    size_t i1 = i0;
+    for (; i1 < cand.size(); ++i1) {
+      const int q = cand[i1];
+      const int G = (h[q].p.m + cpg - 1) / cpg;
+      if (G > maxwg) {  // never fits: step path
+        rest.push_back(q);
+        continue;
+      }
+      if (nwg + G > maxwg) break;
+      h[q].g0 = nwg;
+      h[q].G = G;
+      for (int t = 0; t < G; ++t) wgp.push_back(q);
+      nwg += G;
+      batch.push_back(q);
+    }
+    i0 = i1;
+    if (batch.empty()) continue;
+    const DevProb* dprobs = static_cast<const DevProb*>(st.push(h.data(), sizeof(DevProb) * h.size()));
+    const int* dwg = static_cast<const int*>(st.push(wgp.data(), wgp.size() * 4));
+    if (!dprobs || !dwg) return hipErrorOutOfMemory;
+    hipError_t e = hipMemsetAsync(w.stamp, 0, 2 * (size_t)nwg * 4, s);
+    if (e == hipSuccess) e = hipMemsetAsync(w.err, 0, 4, s);
+    if (e != hipSuccess) return e;
+    Work wa = w;
+    void* args[] = {(void*)&dprobs, (void*)&dwg, (void*)&rtol, (void*)&wa};
+    e = hipLaunchCooperativeKernel(pv.fn, dim3(nwg), dim3(PT), args, 0, s);
+    if (e == hipSuccess) {
+      npersist += (int)batch.size();
+      ++nlaunch;
+    } else {  // not launchable as one co-resident grid: the step path takes them
+      (void)hipGetLastError();
+      rest.insert(rest.end(), batch.begin(), batch.end());
+    }
+    for (int q : batch) {
+      h[q].g0 = -1;
+      h[q].G = 0;
+    }
+  }
+  return hipSuccess;
+}
+
 hipError_t launch_id_factor(IdProblem* probs, int nprob, double rtol, void* work, size_t work_bytes,
                             int* k_host, Staging& st, hipStream_t s) {
   if (nprob <= 0) return hipSuccess;
@@ -586,7 +1010,7 @@ hipError_t launch_id_factor(IdProblem* probs, int nprob, double rtol, void* work
   std::vector<DevProb> h(nprob);
   long long off = 0, aoff = 0, woff = 0;
   int g = 0, dmax = 1, smax = 0;
-  std::vector<int> wg_prob, small[kSmallClasses];
+  std::vector<int> wg_prob, small[kSmallClasses], large;
   for (int q = 0; q < nprob; ++q) {
     IdProblem& p = probs[q];
     if (!p.W) {
@@ -607,18 +1031,29 @@ hipError_t launch_id_factor(IdProblem* probs, int nprob, double rtol, void* work
       dp.kmax = 0;
     }
     const int sc = small_class(p);
-    if (sc >= 0) {
-      small[sc].push_back(q);
-    } else {
-      dp.g0 = g;
-      dp.G = (p.m + SW - 1) / SW;
-      for (int t = 0; t < dp.G; ++t) wg_prob.push_back(q);
-      g += dp.G;
-      dmax = std::max(dmax, p.d);
-      int steps = dp.kmax;
-      if (p.kfail >= 0 && p.m > p.d) steps = std::min(steps, p.kfail + 2);
-      smax = std::max(smax, steps);
-    }
+    if (sc >= 0) small[sc].push_back(q);
+    else large.push_back(q);
+  }
+  // large pivoted problems: persistent launches where they fit, the rest
+  // one launch per step
+  int npersist = 0, nplaunch = 0;
+  {
+    std::vector<int> rest;
+    hipError_t e = run_persistent(h, large, rtol, w, st, s, rest, npersist, nplaunch);
+    if (e != hipSuccess) return e;
+    large.swap(rest);
+  }
+  for (int q : large) {
+    DevProb& dp = h[q];
+    const IdProblem& p = probs[q];
+    dp.g0 = g;
+    dp.G = (p.m + SW - 1) / SW;
+    for (int t = 0; t < dp.G; ++t) wg_prob.push_back(q);
+    g += dp.G;
+    dmax = std::max(dmax, p.d);
+    int steps = dp.kmax;
+    if (p.kfail >= 0 && p.m > p.d) steps = std::min(steps, p.kfail + 2);
+    smax = std::max(smax, steps);
   }
   const DevProb* dprobs = static_cast<const DevProb*>(st.push(h.data(), sizeof(DevProb) * nprob));
   if (!dprobs) return hipErrorOutOfMemory;
@@ -649,6 +1084,16 @@ hipError_t launch_id_factor(IdProblem* probs, int nprob, double rtol, void* work
     e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
+  {
+    const char* v = std::getenv("HSS_VERBOSE");
+    if (v && v[0] && v[0] != '0' && (npersist > 0 || g > 0)) {
+      std::fprintf(stderr,
+                   "[hss-id] %d problems, %d persistent (%d launches), %d step-path workgroups "
+                   "(<= %d steps)\n",
+                   nprob, npersist, nplaunch, g, smax);
+      std::fflush(stderr);
+    }
+  }
   // large problems: a launch per pivot step
   if (g > 0) {
     const int* dwg = static_cast<const int*>(st.push(wg_prob.data(), wg_prob.size() * 4));
@@ -660,12 +1105,6 @@ hipError_t launch_id_factor(IdProblem* probs, int nprob, double rtol, void* work
     if (e != hipSuccess) return e;
     int nlarge = 0;
     for (int q = 0; q < nprob; ++q) nlarge += h[q].g0 >= 0 ? 1 : 0;
-    const char* v = std::getenv("HSS_VERBOSE");
-    if (v && v[0] && v[0] != '0') {
-      std::fprintf(stderr, "[hss-id] %d problems, %d on the step path (%d workgroups, <= %d steps)\n",
-                   nprob, nlarge, g, smax);
-      std::fflush(stderr);
-    }
     const size_t lds = dmax <= 64 * 40 ? (size_t)dmax * 8 : 0;
     for (int i = 0; i < smax; ++i) {
       // rows i..d-1 are active: registers per lane follow the largest d - i
@@ -696,10 +1135,12 @@ hipError_t launch_id_factor(IdProblem* probs, int nprob, double rtol, void* work
     e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
+  int herr = 0;
   e = hipMemcpyAsync(k_host, w.k, (size_t)nprob * 4, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess && npersist > 0) e = hipMemcpyAsync(&herr, w.err, 4, hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) return e;
-  return hipSuccess;
+  return herr ? hipErrorLaunchTimeOut : hipSuccess;
 }
 
 hipError_t launch_id_finish(const IdProblem* probs, int nprob, const int* k_host, const int* sel,
