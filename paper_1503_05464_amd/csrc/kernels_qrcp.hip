@@ -501,7 +501,7 @@ __global__ __launch_bounds__(ST) void id_step_kernel(const DevProb* __restrict__
 }
 
 // ---------------------------------------------------------------------------
-// large problems, persistent: one cooperative launch runs every pivot step.
+// large problems, persistent: one launch runs every pivot step.
 //
 // Workgroup g of a problem owns columns g*PW*C .. (g+1)*PW*C-1, C per
 // wavefront, and keeps them in registers for the whole factorization (lane l
@@ -895,8 +895,9 @@ static int resident_workgroups(const void* fn) {
 }
 
 // Runs the pivoted problems of `large` whose columns fit in registers as
-// cooperative launches (problems grouped while their workgroups fit on the
-// device at once); the others are returned in `rest`.
+// persistent launches (problems grouped while their workgroups fit on the
+// device at once: the grid never exceeds the resident capacity); the others
+// are returned in `rest`.
 static hipError_t run_persistent(std::vector<DevProb>& h, const std::vector<int>& large, double rtol,
                                  const Work& w, Staging& st, hipStream_t s, std::vector<int>& rest,
                                  int& npersist, int& nlaunch) {
@@ -955,6 +956,7 @@ static hipError_t run_persistent(std::vector<DevProb>& h, const std::vector<int>
       return hipSuccess;
     }
   }
+  std::vector<int> done;
   size_t i0 = 0;
   while (i0 < cand.size()) {
     std::vector<int> batch, wgp;
@@ -980,15 +982,16 @@ static hipError_t run_persistent(std::vector<DevProb>& h, const std::vector<int>
     const int* dwg = static_cast<const int*>(st.push(wgp.data(), wgp.size() * 4));
     if (!dprobs || !dwg) return hipErrorOutOfMemory;
     hipError_t e = hipMemsetAsync(w.stamp, 0, 2 * (size_t)nwg * 4, s);
-    if (e == hipSuccess) e = hipMemsetAsync(w.err, 0, 4, s);
+    if (e == hipSuccess && done.empty()) e = hipMemsetAsync(w.err, 0, 4, s);
     if (e != hipSuccess) return e;
     Work wa = w;
     void* args[] = {(void*)&dprobs, (void*)&dwg, (void*)&rtol, (void*)&wa};
-    e = hipLaunchCooperativeKernel(pv.fn, dim3(nwg), dim3(PT), args, 0, s);
+    e = hipLaunchKernel(pv.fn, dim3(nwg), dim3(PT), args, 0, s);
     if (e == hipSuccess) {
       npersist += (int)batch.size();
       ++nlaunch;
-    } else {  // not launchable as one co-resident grid: the step path takes them
+      done.insert(done.end(), batch.begin(), batch.end());
+    } else {
       (void)hipGetLastError();
       rest.insert(rest.end(), batch.begin(), batch.end());
     }
@@ -996,6 +999,18 @@ static hipError_t run_persistent(std::vector<DevProb>& h, const std::vector<int>
       h[q].g0 = -1;
       h[q].G = 0;
     }
+  }
+  if (done.empty()) return hipSuccess;
+  // a wait that timed out (workgroups not all resident at once): the inputs
+  // are untouched, so the per-step path factors those problems again
+  int herr = 0;
+  hipError_t e = hipMemcpyAsync(&herr, w.err, 4, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return e;
+  if (herr) {
+    rest.insert(rest.end(), done.begin(), done.end());
+    npersist = 0;
+    nlaunch = 0;
   }
   return hipSuccess;
 }
@@ -1135,12 +1150,9 @@ hipError_t launch_id_factor(IdProblem* probs, int nprob, double rtol, void* work
     e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
-  int herr = 0;
   e = hipMemcpyAsync(k_host, w.k, (size_t)nprob * 4, hipMemcpyDeviceToHost, s);
-  if (e == hipSuccess && npersist > 0) e = hipMemcpyAsync(&herr, w.err, 4, hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
-  if (e != hipSuccess) return e;
-  return herr ? hipErrorLaunchTimeOut : hipSuccess;
+  return e;
 }
 
 hipError_t launch_id_finish(const IdProblem* probs, int nprob, const int* k_host, const int* sel,
