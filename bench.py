@@ -35,6 +35,8 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 FP64_MFMA_PEAK_TFLOPS = 78.6
+FP32_MFMA_PEAK_TFLOPS = 157.3
+BF16_MFMA_PEAK_TFLOPS = 2500.0
 HBM_PEAK_GBS = 8000.0
 
 WORKLOADS = {
@@ -163,6 +165,8 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-panel", type=int, default=2048)
     ap.add_argument("--no-frob", action="store_true", help="skip the exact ||A - A_HSS||_F check")
+    ap.add_argument("--sample-prec", default="f64", choices=["f64", "f32", "bf16x3"],
+                    help="precision of the sampling products (reduced modes need the FP32 A)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the compression path has no multi-GPU mode "
@@ -189,7 +193,7 @@ def main() -> int:
     x = torch.from_numpy(np.random.default_rng(1).uniform(-1, 1, (cfg["n"], 1))).to(dev)
     b = torch.empty_like(x)
     kw = dict(rtol=cfg["rtol"], d0=cfg["d0"], dd=cfg["dd"], d_max=cfg["d_max"], leaf_size=cfg["leaf"],
-              p_margin=cfg["p_margin"], seed=0)
+              p_margin=cfg["p_margin"], seed=0, sample_prec=args.sample_prec)
 
     def step():
         h = P.hss_compress(A, **kw)
@@ -216,20 +220,29 @@ def main() -> int:
               f"levels {st['t_levels_ms']:.1f} id {st['t_id_ms']:.1f} ms", file=sys.stderr, flush=True)
 
     # dominant kernel: the sampling GEMM, measured with HIP events on its stream
-    flops = sum(s["sample_gemm_flops"] for s in stats)
+    flops = sum(s["sample_gemm_flops"] for s in stats)      # algorithmic: 2 n^2 per column and side
+    nbytes = sum(s["sample_gemm_bytes"] for s in stats)     # A once per product, R read, S written
     t_gemm = sum(s["t_sample_gemm_ms"] for s in stats) / 1e3
     launches = sum(s["n_sample_launches"] for s in stats)
-    achieved = flops / t_gemm / 1e12 if t_gemm > 0 else 0.0
+    terms, peak, kname = {"f64": (1, FP64_MFMA_PEAK_TFLOPS, "sample_kernel (FP64 MFMA 16x16x4)"),
+                          "f32": (1, FP32_MFMA_PEAK_TFLOPS, "sample_mixed_kernel (FP32 MFMA 16x16x4)"),
+                          "bf16x3": (3, BF16_MFMA_PEAK_TFLOPS,
+                                     "sample_mixed_kernel (3 BF16 terms, BF16 MFMA 16x16x32)")}[args.sample_prec]
+    issued = terms * flops / t_gemm / 1e12 if t_gemm > 0 else 0.0
+    gbs = nbytes / t_gemm / 1e9 if t_gemm > 0 else 0.0
+    hbm_bound = nbytes / (HBM_PEAK_GBS * 1e9) > terms * flops / (peak * 1e12)
     roofline = {
-        "bound": "mfma",
-        "achieved": round(achieved, 2),
-        "peak": FP64_MFMA_PEAK_TFLOPS,
-        "unit": "TFLOP/s",
-        "frac": round(achieved / FP64_MFMA_PEAK_TFLOPS, 4),
+        "bound": "hbm" if hbm_bound else "mfma",
+        "achieved": round(gbs, 1) if hbm_bound else round(issued, 2),
+        "peak": HBM_PEAK_GBS if hbm_bound else peak,
+        "unit": "GB/s" if hbm_bound else "TFLOP/s",
+        "frac": round(gbs / HBM_PEAK_GBS if hbm_bound else issued / peak, 4),
         "traffic": None,
-        "kernel": "sample_kernel (FP64 MFMA 16x16x4)",
+        "kernel": kname,
         "avg_launch_ms": round(t_gemm * 1e3 / max(1, launches), 4),
         "launches": launches,
+        "algorithmic_tflops": round(flops / t_gemm / 1e12, 2) if t_gemm > 0 else 0.0,
+        "achieved_gbs": round(gbs, 1),
     }
 
     # acceptance on a fresh compression (not timed)
@@ -262,12 +275,13 @@ def main() -> int:
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64" if args.sample_prec == "f64" else f"{args.sample_prec} sampling, f64 ID",
         "data": "synthetic",
         "config": {
             "workload": f"{args.workload}: n={cfg['n']} {cfg['kind']} kernel, A {cfg['storage']}, "
                         f"leaf {cfg['leaf']}, rtol {cfg['rtol']}, d0 {cfg['d0']}, dd {cfg['dd']}, "
-                        f"p_margin {cfg['p_margin']}, FP64 sampling",
+                        f"p_margin {cfg['p_margin']}, {args.sample_prec.upper()} sampling",
+            "sample_prec": args.sample_prec,
             "n": cfg["n"], "rtol": cfg["rtol"], "d_final": st["d_final"], "passes": st["passes"],
             "max_rank": st["max_rank"], "converged": bool(st["converged"]),
             "step": "hss_compress + hss_matvec(nrhs=1) + hss_destroy",

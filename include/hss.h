@@ -44,9 +44,19 @@ typedef enum {
 
 typedef enum { HSS_F64 = 0, HSS_F32 = 1 } hss_dtype; /* storage type of A */
 
-/* Precision of the sampling products S^r = A R^r, S^c = A^T R^c. */
+/*
+ * Precision of the sampling products S^r = A R^r, S^c = A^T R^c.  In the
+ * reduced modes R is rounded once, when drawn (round to nearest even from the
+ * FP64 value), and that rounded R is what every later step of the compression
+ * uses, so the sampled products differ from FP64 products of the same A and R
+ * only by accumulation: FP32 over chunks of 256 values of k, FP64 across
+ * chunks.  The IDs, the B and D blocks and everything after them stay FP64.
+ */
 typedef enum {
-  HSS_SAMPLE_F64 = 0  /* FP64 MFMA; an FP32 A is widened exactly */
+  HSS_SAMPLE_F64 = 0,    /* FP64 MFMA; an FP32 A is widened exactly */
+  HSS_SAMPLE_F32 = 1,    /* FP32 MFMA; A must be stored in FP32; R rounded to FP32 */
+  HSS_SAMPLE_BF16X3 = 2  /* A must be stored in FP32 and is split exactly into three
+                            BF16 terms; BF16 MFMA; R rounded to BF16 */
 } hss_sample_prec;
 
 /* Node states of the adaptive sampling (Sec. 3.3). */
@@ -213,10 +223,13 @@ const char* hss_last_error(void);
  * (i/4, j, which, 0) gives four words; word w maps to
  * u = ((w >> 12) + 1/2) 2^-52; rows 4q, 4q+1 are the Box-Muller pair of
  * (u0, u1), rows 4q+2, 4q+3 that of (u2, u3): sqrt(-2 ln ua) cos(2 pi ub),
- * sqrt(-2 ln ua) sin(2 pi ub).  Stream-ordered.
+ * sqrt(-2 ln ua) sin(2 pi ub).  With sample_prec HSS_SAMPLE_F32 or
+ * HSS_SAMPLE_BF16X3 every entry is then rounded to nearest even to FP32 or
+ * to BF16 (8 significant bits), as hss_compress does in that mode.
+ * Stream-ordered.
  */
 hss_status hss_random_normal(unsigned long long seed, int which, long long n, int col0,
-                             int col1, double* R, long long ld, void* stream);
+                             int col1, int sample_prec, double* R, long long ld, void* stream);
 
 /*
  * Sampling products (Sec. 2.2): Sr = (A - M) Rr and Sc = (A - M)^T Rc for
@@ -226,9 +239,12 @@ hss_status hss_random_normal(unsigned long long seed, int which, long long n, in
  * contiguous), which yields the leaves' local samples directly:
  * S^(l) = (A - D^(l)) R (Sec. 2.2).  A: DEVICE n x n (dtype), Rr, Rc: DEVICE
  * n x ncols (ldr); Sr, Sc: DEVICE n x ncols (lds).  Either of Sr/Rr or
- * Sc/Rc may be NULL.  Stream-ordered.
+ * Sc/Rc may be NULL.  sample_prec as in hss_sample_prec: the reduced modes
+ * need dtype HSS_F32 and R already representable in their precision
+ * (hss_random_normal with the same sample_prec); HSS_ERR_ARG otherwise.
+ * Stream-ordered.
  */
-hss_status hss_sample(const void* A, int dtype, long long n, long long lda,
+hss_status hss_sample(const void* A, int dtype, int sample_prec, long long n, long long lda,
                       const int* leaf_of, int ncols, const double* Rr, const double* Rc,
                       long long ldr, double* Sr, double* Sc, long long lds, void* stream);
 

@@ -64,6 +64,10 @@ class Options:
     p_margin: int = 10
     seed: int = 0
     leaf_size: int = 64
+    # precision of the sampling products: "f64", or "f32" / "bf16x3" (A
+    # stored in FP32); in the reduced modes R is rounded once when drawn
+    # (see round_random) and the rounded R is used everywhere after that
+    sample_prec: str = "f64"
 
 
 @dataclass
@@ -90,14 +94,43 @@ class HSSForm:
         return max([max(kr, kc) for kr, kc in self.ranks().values()], default=0)
 
 
+def round_random(R, prec: str):
+    """R rounded to nearest, ties to even, from its float64 value: to FP32
+    ("f32"), or to 8 significant bits, the precision of BF16 ("bf16x3");
+    unchanged for "f64".  This is the random matrix the reduced-precision
+    sampling modes use in every later step (their products are then exact
+    up to the rounding of accumulation, which the oracle does not model: it
+    forms the products in float64)."""
+    R = np.asarray(R, dtype=np.float64)
+    if prec == "f64":
+        return R.copy()
+    if prec == "f32":
+        return R.astype(np.float32).astype(np.float64)
+    if prec != "bf16x3":
+        raise ValueError(prec)
+    # 8 significant bits keep the top 7 of the 52 stored fraction bits: round
+    # the low 45 bits away, to nearest, ties to even (a carry may bump the
+    # exponent, which is the correct rounding)
+    u = np.ascontiguousarray(R).view(np.uint64).copy()
+    low = np.uint64((1 << 45) - 1)
+    half = np.uint64(1 << 44)
+    rem = u & low
+    keep_odd = (u >> np.uint64(45)) & np.uint64(1)
+    up = (rem > half) | ((rem == half) & (keep_odd == np.uint64(1)))
+    u = u & ~low
+    u = u + np.where(up, np.uint64(1 << 45), np.uint64(0))
+    return u.view(np.float64).reshape(R.shape)
+
+
 class _Sampler:
     """Random matrices and the samples S^r = A R^r, S^c = A^T R^c, grown by
     columns.  A may be float32 (upcast exactly by row panels)."""
 
-    def __init__(self, A, seed, R_r=None, R_c=None, panel=4096):
+    def __init__(self, A, seed, R_r=None, R_c=None, panel=4096, prec="f64"):
         self.A = A
         self.n = A.shape[0]
         self.seed = seed
+        self.prec = prec
         self.R_user = (R_r, R_c)
         self.panel = panel
         self.Rr = np.zeros((self.n, 0))
@@ -112,6 +145,8 @@ class _Sampler:
         else:
             rr = philox.gaussian_columns(self.seed, 0, self.n, c0, c1)
             rc = philox.gaussian_columns(self.seed, 1, self.n, c0, c1)
+        rr = round_random(rr, self.prec)
+        rc = round_random(rc, self.prec)
         sr = np.zeros((self.n, c1 - c0))
         sc = np.zeros((self.n, c1 - c0))
         for r0 in range(0, self.n, self.panel):
@@ -163,7 +198,9 @@ def compress(A, opts: Options, tree: ClusterTree | None = None, R_r=None, R_c=No
     def A_sub(rows, cols):
         return np.asarray(A[np.ix_(rows, cols)], dtype=np.float64)
 
-    smp = _Sampler(A, opts.seed, R_r, R_c)
+    if opts.sample_prec != "f64" and np.asarray(A).dtype != np.float32:
+        raise ValueError("reduced-precision sampling needs A stored in float32")
+    smp = _Sampler(A, opts.seed, R_r, R_c, prec=opts.sample_prec)
     d = min(opts.d0, opts.d_max)
     smp.grow(0, d)
     forced = False

@@ -25,6 +25,9 @@ HSS_OK, HSS_NOT_CONVERGED = 0, 1
 HSS_ERR_ARG, HSS_ERR_ALLOC, HSS_ERR_HIP, HSS_ERR_STATE, HSS_ERR_SINGULAR = -1, -2, -3, -4, -5
 HSS_F64, HSS_F32 = 0, 1
 HSS_SAMPLE_F64 = 0
+HSS_SAMPLE_F32 = 1
+HSS_SAMPLE_BF16X3 = 2
+_PREC = {"f64": HSS_SAMPLE_F64, "f32": HSS_SAMPLE_F32, "bf16x3": HSS_SAMPLE_BF16X3}
 
 EXPORTED = [
     "hss_default_opts", "hss_compress", "hss_matvec", "hss_factor", "hss_solve", "hss_stats",
@@ -94,8 +97,8 @@ def lib() -> C.CDLL:
         L.hss_import.argtypes = [ll, C.POINTER(hss_tree), vp, vp, vp, C.POINTER(vp)]
         L.hss_destroy.argtypes = [vp]
         L.hss_destroy.restype = None
-        L.hss_random_normal.argtypes = [C.c_ulonglong, i, ll, i, i, vp, ll, vp]
-        L.hss_sample.argtypes = [vp, i, ll, ll, vp, i, vp, vp, ll, vp, vp, ll, vp]
+        L.hss_random_normal.argtypes = [C.c_ulonglong, i, ll, i, i, i, vp, ll, vp]
+        L.hss_sample.argtypes = [vp, i, i, ll, ll, vp, i, vp, vp, ll, vp, vp, ll, vp]
         L.hss_id_batched.argtypes = [i, vp, vp, vp, vp, d, vp, vp, vp, vp]
         for f in EXPORTED:
             if f not in ("hss_default_opts", "hss_destroy", "hss_last_error"):
@@ -162,10 +165,11 @@ class HSSHandle:
 
 
 def hss_compress(A, tree=None, *, rtol=1e-6, d0=64, dd=32, d_max=4096, p_margin=10, seed=0,
-                 leaf_size=64, R_user=None, stream=None) -> HSSHandle:
+                 leaf_size=64, R_user=None, sample_prec="f64", stream=None) -> HSSHandle:
     """Compress the square CUDA tensor A (float32 or float64, row-major
     with unit column stride).  R_user: optional (R^r, R^c) CUDA float64
-    tensors n x >= d_max (row-major) used instead of the Philox columns."""
+    tensors n x >= d_max (row-major) used instead of the Philox columns.
+    sample_prec: "f64", or "f32" / "bf16x3" for a float32 A."""
     import torch
 
     if A.dim() != 2 or A.shape[0] != A.shape[1] or A.stride(1) != 1 or not A.is_cuda:
@@ -176,6 +180,7 @@ def hss_compress(A, tree=None, *, rtol=1e-6, d0=64, dd=32, d_max=4096, p_margin=
     o = hss_default_opts()
     o.rtol, o.d0, o.dd, o.d_max, o.p_margin = float(rtol), int(d0), int(dd), int(d_max), int(p_margin)
     o.seed, o.leaf_size = int(seed), int(leaf_size)
+    o.sample_prec = _PREC[sample_prec]
     keep = [A]
     if R_user is not None:
         rr, rc = R_user
@@ -299,19 +304,22 @@ def hss_destroy(h: HSSHandle) -> None:
         h.ptr = C.c_void_p()
 
 
-def hss_random_normal(seed: int, which: int, n: int, col0: int, col1: int, out=None, stream=None):
+def hss_random_normal(seed: int, which: int, n: int, col0: int, col1: int, out=None, stream=None,
+                      sample_prec: str = "f64"):
     import torch
 
     if out is None:
         out = torch.empty((n, col1 - col0), dtype=torch.float64, device="cuda")
-    _check(lib().hss_random_normal(int(seed), int(which), int(n), int(col0), int(col1), _ptr(out),
-                                   out.stride(0), _stream(stream)))
+    _check(lib().hss_random_normal(int(seed), int(which), int(n), int(col0), int(col1),
+                                   _PREC[sample_prec], _ptr(out), out.stride(0), _stream(stream)))
     return out
 
 
-def hss_sample(A, Rr=None, Rc=None, leaf_of=None, stream=None):
+def hss_sample(A, Rr=None, Rc=None, leaf_of=None, stream=None, sample_prec: str = "f64"):
     """(Sr, Sc) = ((A - M) Rr, (A - M)^T Rc); M = leaf diagonal blocks
-    when leaf_of (CUDA int32, leaf ordinal of each index) is given."""
+    when leaf_of (CUDA int32, leaf ordinal of each index) is given.
+    sample_prec "f32" / "bf16x3" need FP32 A and R from hss_random_normal
+    with the same sample_prec."""
     import torch
 
     dt = {torch.float64: HSS_F64, torch.float32: HSS_F32}[A.dtype]
@@ -322,7 +330,7 @@ def hss_sample(A, Rr=None, Rc=None, leaf_of=None, stream=None):
     if Rr is not None and Rc is not None and Rr.stride(0) != Rc.stride(0):
         raise ValueError("Rr and Rc must share a leading dimension")
     S = Sr if Sr is not None else Sc
-    _check(lib().hss_sample(_ptr(A), dt, A.shape[0], A.stride(0),
+    _check(lib().hss_sample(_ptr(A), dt, _PREC[sample_prec], A.shape[0], A.stride(0),
                             _ptr(leaf_of) if leaf_of is not None else None, ncols,
                             _ptr(Rr) if Rr is not None else None, _ptr(Rc) if Rc is not None else None,
                             R.stride(0), _ptr(Sr) if Sr is not None else None,

@@ -305,15 +305,25 @@ hss_status sample_columns(Handle& H, const void* A, long long lda, int c0, int c
     launch_random_normal(H.opts.seed, 0, H.n, c0, c1, H.Rr + c0, H.ldg, H.stream);
     launch_random_normal(H.opts.seed, 1, H.n, c0, c1, H.Rc + c0, H.ldg, H.stream);
   }
-  const long long wd = sample_workspace_doubles(H.n, nc);
+  const int prec = H.opts.sample_prec;
+  if (prec != HSS_SAMPLE_F64) {  // R in the products' precision, used as such from here on
+    launch_round_r(H.Rr, H.ldg, H.n, c0, c1, prec, H.stream);
+    launch_round_r(H.Rc, H.ldg, H.n, c0, c1, prec, H.stream);
+  }
+  const long long wd = prec == HSS_SAMPLE_F64 ? sample_workspace_doubles(H.n, nc)
+                                              : sample_mixed_workspace_doubles(H.n, nc);
   double* work = nullptr;
   if (wd > 0) {
     work = static_cast<double*>(H.work_sample.ensure((size_t)wd * 8));
     if (!work) return fail(HSS_ERR_ALLOC, "sampling workspace");
   }
   const int evg = tm.begin();
-  launch_sample(A, H.dtype, H.n, lda, H.leaf_of, nc, H.Rr + c0, H.Rc + c0, H.ldg, H.Sr + c0,
-                H.Sc + c0, H.ldg, work, H.stream);
+  if (prec == HSS_SAMPLE_F64)
+    launch_sample(A, H.dtype, H.n, lda, H.leaf_of, nc, H.Rr + c0, H.Rc + c0, H.ldg, H.Sr + c0,
+                  H.Sc + c0, H.ldg, work, H.stream);
+  else
+    launch_sample_mixed(static_cast<const float*>(A), H.n, lda, H.leaf_of, nc, prec, H.Rr + c0,
+                        H.Rc + c0, H.ldg, H.Sr + c0, H.Sc + c0, H.ldg, work, H.stream);
   HIPCHK(hipGetLastError());
   tm.end(evg, 3);
   tm.end(ev0, 0);
@@ -937,7 +947,11 @@ hss_status hss_compress(const void* A, int dtype, long long n, long long lda,
   else hss_default_opts(&o);
   if (!(o.rtol >= 0.0) || o.d0 < 1 || o.dd < 1 || o.d_max < o.d0 || o.p_margin < 0)
     return fail(HSS_ERR_ARG, "rtol / d0 / dd / d_max / p_margin invalid");
-  if (o.sample_prec != HSS_SAMPLE_F64) return fail(HSS_ERR_ARG, "unsupported sample precision");
+  if (o.sample_prec != HSS_SAMPLE_F64 && o.sample_prec != HSS_SAMPLE_F32 &&
+      o.sample_prec != HSS_SAMPLE_BF16X3)
+    return fail(HSS_ERR_ARG, "unknown sample precision");
+  if (o.sample_prec != HSS_SAMPLE_F64 && dtype != HSS_F32)
+    return fail(HSS_ERR_ARG, "reduced-precision sampling needs A stored in FP32");
   if ((o.R_user_r == nullptr) != (o.R_user_c == nullptr))
     return fail(HSS_ERR_ARG, "R_user_r and R_user_c must both be given or both NULL");
   if (o.R_user_r && o.ld_R_user < o.d_max) return fail(HSS_ERR_ARG, "ld_R_user < d_max");
@@ -1138,29 +1152,42 @@ hss_status hss_import(long long n, const hss_tree* tree, const int* kr, const in
 void hss_destroy(hss_handle h) { free_handle(h); }
 
 hss_status hss_random_normal(unsigned long long seed, int which, long long n, int col0, int col1,
-                             double* R, long long ld, void* stream) {
+                             int sample_prec, double* R, long long ld, void* stream) {
   g_err.clear();
   if (n < 0 || col0 < 0 || col1 < col0 || (n > 0 && !R) || ld < col1 - col0 || (which != 0 && which != 1))
     return fail(HSS_ERR_ARG, "random_normal arguments");
-  launch_random_normal(seed, which, n, col0, col1, R, ld, static_cast<hipStream_t>(stream));
+  if (sample_prec < HSS_SAMPLE_F64 || sample_prec > HSS_SAMPLE_BF16X3)
+    return fail(HSS_ERR_ARG, "unknown sample precision");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  launch_random_normal(seed, which, n, col0, col1, R, ld, s);
+  launch_round_r(R, ld, n, 0, col1 - col0, sample_prec, s);
   HIPCHK(hipGetLastError());
   return HSS_OK;
 }
 
-hss_status hss_sample(const void* A, int dtype, long long n, long long lda, const int* leaf_of,
-                      int ncols, const double* Rr, const double* Rc, long long ldr, double* Sr,
-                      double* Sc, long long lds, void* stream) {
+hss_status hss_sample(const void* A, int dtype, int sample_prec, long long n, long long lda,
+                      const int* leaf_of, int ncols, const double* Rr, const double* Rc,
+                      long long ldr, double* Sr, double* Sc, long long lds, void* stream) {
   g_err.clear();
   if (!A || n < 1 || lda < n || ncols < 0 || ldr < ncols || lds < ncols)
     return fail(HSS_ERR_ARG, "sample arguments");
   if ((Sr == nullptr) != (Rr == nullptr) || (Sc == nullptr) != (Rc == nullptr))
     return fail(HSS_ERR_ARG, "S and R must be given together");
   if (dtype != HSS_F64 && dtype != HSS_F32) return fail(HSS_ERR_ARG, "dtype");
+  if (sample_prec < HSS_SAMPLE_F64 || sample_prec > HSS_SAMPLE_BF16X3)
+    return fail(HSS_ERR_ARG, "unknown sample precision");
+  if (sample_prec != HSS_SAMPLE_F64 && dtype != HSS_F32)
+    return fail(HSS_ERR_ARG, "reduced-precision sampling needs A stored in FP32");
   hipStream_t s = static_cast<hipStream_t>(stream);
-  const long long wd = sample_workspace_doubles(n, ncols);
+  const long long wd = sample_prec == HSS_SAMPLE_F64 ? sample_workspace_doubles(n, ncols)
+                                                     : sample_mixed_workspace_doubles(n, ncols);
   double* work = nullptr;
   if (wd > 0) HIPCHK(hipMallocAsync(reinterpret_cast<void**>(&work), (size_t)wd * 8, s));
-  launch_sample(A, dtype, n, lda, leaf_of, ncols, Rr, Rc, ldr, Sr, Sc, lds, work, s);
+  if (sample_prec == HSS_SAMPLE_F64)
+    launch_sample(A, dtype, n, lda, leaf_of, ncols, Rr, Rc, ldr, Sr, Sc, lds, work, s);
+  else
+    launch_sample_mixed(static_cast<const float*>(A), n, lda, leaf_of, ncols, sample_prec, Rr, Rc,
+                        ldr, Sr, Sc, lds, work, s);
   hipError_t e = hipGetLastError();
   if (work) hipFreeAsync(work, s);
   HIPCHK(e);

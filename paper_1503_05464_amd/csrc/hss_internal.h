@@ -40,6 +40,20 @@ void launch_random_normal(unsigned long long seed, int which, long long n, int c
 // partial sums); it may be null when that size is 0.
 // ---------------------------------------------------------------------------
 long long sample_workspace_doubles(long long n, int ncols);
+
+// Reduced-precision sampling for FP32 A (kernels_sample_mixed.hip): mode 1 =
+// FP32 MFMA, mode 2 = A split into three BF16 terms on BF16 MFMA; R must be
+// representable in the mode's precision.  FP32 accumulation over chunks of
+// 256 k, FP64 across chunks.
+long long sample_mixed_workspace_doubles(long long n, int ncols);
+void launch_sample_mixed(const float* A, long long n, long long lda, const int* leaf_of, int ncols,
+                         int mode, const double* Rr, const double* Rc, long long ldr, double* Sr,
+                         double* Sc, long long lds, double* work, hipStream_t s);
+// R columns col0..col1-1 (rows 0..n-1, leading dimension ld, R points at row
+// 0 column 0) rounded to nearest even in place: mode 1 to FP32, mode 2 to
+// BF16; mode 0 leaves R unchanged.
+void launch_round_r(double* R, long long ld, long long n, int col0, int col1, int mode,
+                    hipStream_t s);
 void launch_sample(const void* A, int dtype, long long n, long long lda, const int* leaf_of,
                    int ncols, const double* Rr, const double* Rc, long long ldr, double* Sr,
                    double* Sc, long long lds, double* work, hipStream_t s);

@@ -1,0 +1,406 @@
+// Sampling products of randomized HSS compression (Sec. 2.2) in reduced
+// precision, for A stored in FP32:
+//   S^r = (A - M) R^r      and      S^c = (A - M)^T R^c
+// (M: zero or the leaf diagonal blocks, as in the FP64 kernel).
+//
+// R has already been rounded to the precision of the products (FP32 or
+// BF16) when it was drawn, and the rest of the compression uses that same R,
+// so the products below differ from the FP64 products of the same A and R
+// only by the rounding of their accumulation.
+//
+// Two modes:
+//  * F32: the 16x16x4 FP32 MFMA on FP32 A and R;
+//  * BF16X3: every FP32 entry of A is split exactly into three BF16 terms,
+//    a = h1 + h2 + h3 (h1 = bf16(a), h2 = bf16(a - h1), h3 = a - h1 - h2), and
+//    the three products h_t R run on the 16x16x32 BF16 MFMA.  Each product of
+//    two BF16 numbers is exact in FP32.
+// In both modes the MFMA accumulates in FP32 over a chunk of KF = 256 values
+// of k; the chunk sum is then added into an FP64 accumulator, so rounding
+// grows with the chunk length rather than with n.
+//
+// Tiling: a 256-thread workgroup computes a 128 x 64 tile of S, its four
+// wavefronts 64 x 32 each as 4 x 2 blocks of 16 x 16.  A and R pass through
+// LDS in k-slices of 32, both stored with k contiguous per row (A split into
+// its three BF16 planes on the way in), so that a lane reads its eight k
+// values for one MFMA operand in a single 16-byte access: lane l takes
+// k = 8 (l / 16) + e, e < 8, of row l % 16 -- the same k for A and R, which is
+// all the product needs.  The output layout of both MFMAs (checked on the
+// device): lane l, register r -> row 4 (l / 16) + r, column l % 16.
+#include <cstdint>
+
+#include "hss_internal.h"
+
+namespace hss {
+namespace {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int BM = 128;
+constexpr int BN = 64;
+constexpr int BK = 32;
+constexpr int NT = 256;
+constexpr int KF = 256;        // k values accumulated in FP32 before the FP64 carry
+// LDS row pitches (elements) chosen so that the 16 rows read by one 16-byte
+// access per lane start on distinct bank groups: 144 B rows for FP32, 80 B
+// rows for BF16
+constexpr int AP1 = BK + 4;
+constexpr int AP2 = BK + 8;
+
+// round-to-nearest-even FP32 -> BF16 (finite inputs)
+__device__ __forceinline__ unsigned short bf16_rn(float x) {
+  unsigned int u = __float_as_uint(x);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (unsigned short)(u >> 16);
+}
+__device__ __forceinline__ float bf16_to_f(unsigned short h) {
+  return __uint_as_float((unsigned int)h << 16);
+}
+
+template <int MODE>
+struct Smem;
+template <>
+struct alignas(16) Smem<1> {  // FP32
+  float A[BM][AP1];
+  float B[BN][AP1];
+};
+template <>
+struct alignas(16) Smem<2> {  // BF16 x 3
+  unsigned short A[3][BM][AP2];
+  unsigned short B[BN][AP2];
+};
+
+// this thread's 16 entries of the A slice: NN rows i, 16 consecutive k;
+// TN 16 consecutive i (columns of A) of one k
+template <bool TRANS>
+__device__ __forceinline__ void load_a(float (&v)[16], const float* __restrict__ A, long long lda,
+                                       int n, int i0, int k0, int kend,
+                                       const int* __restrict__ leaf_of, bool vec_ok,
+                                       bool need_mask) {
+  const int tid = threadIdx.x;
+  int row, col, ie, ke;
+  if (!TRANS) {
+    const int r = tid >> 1, kseg = (tid & 1) * 16;
+    row = i0 + r;
+    col = k0 + kseg;
+    ie = row;
+    ke = col;
+  } else {
+    const int kk = tid >> 3, iseg = (tid & 7) * 16;
+    row = k0 + kk;
+    col = i0 + iseg;
+    ie = col;
+    ke = row;
+  }
+  const bool full = !TRANS ? (row < n && col + 16 <= kend) : (row < kend && col + 16 <= n);
+  if (full && vec_ok) {
+    const u32x4* p = reinterpret_cast<const u32x4*>(A + (long long)row * lda + col);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const u32x4 w = __builtin_nontemporal_load(p + q);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) v[4 * q + e] = __uint_as_float(w[e]);
+    }
+  } else {
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      const bool ok = !TRANS ? (row < n && col + e < kend) : (row < kend && col + e < n);
+      v[e] = ok ? A[(long long)row * lda + col + e] : 0.0f;
+    }
+  }
+  if (need_mask) {
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      const int i = !TRANS ? ie : ie + e;
+      const int k = !TRANS ? ke + e : ke;
+      if (i < n && k < n && leaf_of[i] == leaf_of[k]) v[e] = 0.0f;
+    }
+  }
+}
+
+template <int MODE, bool TRANS>
+__device__ __forceinline__ void store_a(Smem<MODE>& sm, const float (&v)[16]) {
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int e = 0; e < 16; ++e) {
+    int r, k;
+    if (!TRANS) {
+      r = tid >> 1;
+      k = (tid & 1) * 16 + e;
+    } else {
+      r = (tid & 7) * 16 + e;
+      k = tid >> 3;
+    }
+    if constexpr (MODE == 1) {
+      sm.A[r][k] = v[e];
+    } else {
+      const unsigned short h1 = bf16_rn(v[e]);
+      const float r1 = v[e] - bf16_to_f(h1);
+      const unsigned short h2 = bf16_rn(r1);
+      const float r2 = r1 - bf16_to_f(h2);
+      sm.A[0][r][k] = h1;
+      sm.A[1][r][k] = h2;
+      sm.A[2][r][k] = bf16_rn(r2);
+    }
+  }
+}
+
+// R slice: rows k0 .. k0+31, columns c0 .. c0+63; 8 values per thread
+__device__ __forceinline__ void load_r(double (&v)[8], const double* __restrict__ R, long long ldr,
+                                       int k0, int kend, int c0, int ncols) {
+  const int tid = threadIdx.x;
+  const int rr = tid >> 3, cc = (tid & 7) * 8;
+  const int k = k0 + rr, c = c0 + cc;
+#pragma unroll
+  for (int e = 0; e < 8; ++e) v[e] = (k < kend && c + e < ncols) ? R[(long long)k * ldr + c + e] : 0.0;
+}
+
+template <int MODE>
+__device__ __forceinline__ void store_r(Smem<MODE>& sm, const double (&v)[8]) {
+  const int tid = threadIdx.x;
+  const int rr = tid >> 3, cc = (tid & 7) * 8;
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    if constexpr (MODE == 1) sm.B[cc + e][rr] = (float)v[e];
+    else sm.B[cc + e][rr] = bf16_rn((float)v[e]);  // exact: R is BF16-representable
+  }
+}
+
+template <int MODE, bool TRANS>
+__global__ __launch_bounds__(NT) void sample_mixed_kernel(
+    const float* __restrict__ A, long long lda, int n, const int* __restrict__ leaf_of,
+    const double* __restrict__ R, long long ldr, double* __restrict__ S, long long lds, int ncols,
+    int n_nt, int ksplit, int kchunk, double* __restrict__ work) {
+  __shared__ Smem<MODE> sm;
+
+  const int nblk = gridDim.x;
+  int L = blockIdx.x;
+  if ((nblk & 7) == 0) L = (blockIdx.x & 7) * (nblk >> 3) + (blockIdx.x >> 3);
+  const int nt = L % n_nt;
+  const int rest = L / n_nt;
+  const int ks = rest % ksplit;
+  const int mt = rest / ksplit;
+  const int i0 = mt * BM, c0 = nt * BN;
+  const int kbeg = ks * kchunk;
+  const int kend = min(n, kbeg + kchunk);
+
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int lr = lane & 15, lk = (lane >> 4) * 8;
+
+  const bool vec_a = ((lda * 4) % 16 == 0) && ((reinterpret_cast<uintptr_t>(A) & 15) == 0);
+  int li0 = 0, li1 = -1;
+  if (leaf_of) {
+    li0 = leaf_of[min(i0, n - 1)];
+    li1 = leaf_of[min(i0 + BM, n) - 1];
+  }
+  auto mask_for = [&](int k0) -> bool {
+    if (!leaf_of || k0 >= kend) return false;
+    const int lk0 = leaf_of[k0];
+    const int lk1 = leaf_of[min(k0 + BK, kend) - 1];
+    return !(lk1 < li0 || li1 < lk0);
+  };
+
+  f32x4 acc[4][2];
+  double accd[4][2][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int r = 0; r < 4; ++r) accd[a][b][r] = 0.0;
+    }
+
+  float va[16];
+  double vr[8];
+  int k0 = kbeg;
+  if (k0 < kend) {
+    load_a<TRANS>(va, A, lda, n, i0, k0, kend, leaf_of, vec_a, mask_for(k0));
+    load_r(vr, R, ldr, k0, kend, c0, ncols);
+    store_a<MODE, TRANS>(sm, va);
+    store_r<MODE>(sm, vr);
+  }
+  __syncthreads();
+  int since = 0;  // k values accumulated in FP32 since the last carry
+  for (; k0 < kend; k0 += BK) {
+    const int kn = k0 + BK;
+    if (kn < kend) {
+      load_a<TRANS>(va, A, lda, n, i0, kn, kend, leaf_of, vec_a, mask_for(kn));
+      load_r(vr, R, ldr, kn, kend, c0, ncols);
+    }
+    if constexpr (MODE == 1) {
+      float a[4][8], b[2][8];
+#pragma unroll
+      for (int mb = 0; mb < 4; ++mb) {
+        const float* p = &sm.A[wm * 64 + mb * 16 + lr][lk];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) a[mb][e] = p[e];
+      }
+#pragma unroll
+      for (int nb = 0; nb < 2; ++nb) {
+        const float* p = &sm.B[wn * 32 + nb * 16 + lr][lk];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) b[nb][e] = p[e];
+      }
+#pragma unroll
+      for (int e = 0; e < 8; ++e)
+#pragma unroll
+        for (int mb = 0; mb < 4; ++mb)
+#pragma unroll
+          for (int nb = 0; nb < 2; ++nb)
+            acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[mb][e], b[nb][e], acc[mb][nb], 0, 0, 0);
+    } else {
+      bf16x8 b[2];
+#pragma unroll
+      for (int nb = 0; nb < 2; ++nb)
+        b[nb] = *reinterpret_cast<const bf16x8*>(&sm.B[wn * 32 + nb * 16 + lr][lk]);
+#pragma unroll
+      for (int t = 0; t < 3; ++t) {
+        bf16x8 a[4];
+#pragma unroll
+        for (int mb = 0; mb < 4; ++mb)
+          a[mb] = *reinterpret_cast<const bf16x8*>(&sm.A[t][wm * 64 + mb * 16 + lr][lk]);
+#pragma unroll
+        for (int mb = 0; mb < 4; ++mb)
+#pragma unroll
+          for (int nb = 0; nb < 2; ++nb)
+            acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[mb], b[nb], acc[mb][nb], 0, 0, 0);
+      }
+    }
+    since += BK;
+    if (since >= KF || kn >= kend) {  // carry the FP32 chunk sums into FP64
+#pragma unroll
+      for (int mb = 0; mb < 4; ++mb)
+#pragma unroll
+        for (int nb = 0; nb < 2; ++nb) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) accd[mb][nb][r] += (double)acc[mb][nb][r];
+          acc[mb][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
+        }
+      since = 0;
+    }
+    __syncthreads();
+    if (kn < kend) {
+      store_a<MODE, TRANS>(sm, va);
+      store_r<MODE>(sm, vr);
+    }
+    __syncthreads();
+  }
+
+  double* out = S;
+  long long ldo = lds;
+  if (ksplit > 1) {
+    out = work + (long long)ks * n * ncols;
+    ldo = ncols;
+  }
+#pragma unroll
+  for (int mb = 0; mb < 4; ++mb)
+#pragma unroll
+    for (int nb = 0; nb < 2; ++nb) {
+      const int c = c0 + wn * 32 + nb * 16 + lr;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = i0 + wm * 64 + mb * 16 + 4 * (lane >> 4) + r;
+        if (i < n && c < ncols) out[(long long)i * ldo + c] = accd[mb][nb][r];
+      }
+    }
+}
+
+__global__ void reduce_splits_mixed_kernel(const double* __restrict__ work, int ksplit, long long n,
+                                           int ncols, double* __restrict__ S, long long lds) {
+  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long total = n * ncols;
+  if (idx >= total) return;
+  const long long i = idx / ncols;
+  const int c = (int)(idx % ncols);
+  double s = 0.0;
+  for (int q = 0; q < ksplit; ++q) s += work[(long long)q * total + idx];
+  S[i * lds + c] = s;
+}
+
+// R rounded in place to the precision of the products: FP32 (mode 1) or
+// BF16 (mode 2), round to nearest even from the FP64 value itself.
+__global__ void round_r_kernel(double* __restrict__ R, long long ld, long long n, int col0, int col1,
+                               int mode) {
+  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int w = col1 - col0;
+  if (idx >= n * w) return;
+  double* p = R + (idx / w) * ld + col0 + (int)(idx % w);
+  if (mode == 1) {
+    *p = (double)(float)*p;
+  } else {
+    // keep 8 significant bits: round away the low 45 bits of the FP64
+    // fraction (bias of half minus one, plus the kept lowest bit for ties)
+    unsigned long long u = (unsigned long long)__double_as_longlong(*p);
+    u += 0x00000FFFFFFFFFFFull + ((u >> 45) & 1ull);
+    u &= ~0x00001FFFFFFFFFFFull;
+    *p = __longlong_as_double((long long)u);
+  }
+}
+
+struct Plan {
+  int n_mt, n_nt, ksplit, kchunk;
+};
+
+Plan make_plan(long long n, int ncols) {
+  Plan p;
+  p.n_mt = (int)((n + BM - 1) / BM);
+  p.n_nt = (ncols + BN - 1) / BN;
+  const long long tiles = (long long)p.n_mt * p.n_nt;
+  long long want = (512 + tiles - 1) / tiles;
+  long long maxs = n / 1024;
+  if (maxs < 1) maxs = 1;
+  if (want > maxs) want = maxs;
+  if (want < 1) want = 1;
+  long long chunk = (n + want - 1) / want;
+  chunk = (chunk + KF - 1) / KF * KF;  // split boundaries on carry boundaries
+  p.ksplit = (int)((n + chunk - 1) / chunk);
+  p.kchunk = (int)chunk;
+  return p;
+}
+
+template <int MODE, bool TRANS>
+void run(const float* A, long long lda, long long n, const int* leaf_of, int ncols, const double* R,
+         long long ldr, double* S, long long lds, double* work, hipStream_t s) {
+  Plan p = make_plan(n, ncols);
+  const long long nblocks = (long long)p.n_mt * p.n_nt * p.ksplit;
+  hipLaunchKernelGGL((sample_mixed_kernel<MODE, TRANS>), dim3((unsigned)nblocks), dim3(NT), 0, s, A,
+                     lda, (int)n, leaf_of, R, ldr, S, lds, ncols, p.n_nt, p.ksplit, p.kchunk, work);
+  if (p.ksplit > 1) {
+    const long long total = n * ncols;
+    hipLaunchKernelGGL(reduce_splits_mixed_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256),
+                       0, s, work, p.ksplit, n, ncols, S, lds);
+  }
+}
+
+}  // namespace
+
+long long sample_mixed_workspace_doubles(long long n, int ncols) {
+  Plan p = make_plan(n, ncols);
+  return p.ksplit > 1 ? (long long)p.ksplit * n * ncols : 0;
+}
+
+void launch_sample_mixed(const float* A, long long n, long long lda, const int* leaf_of, int ncols,
+                         int mode, const double* Rr, const double* Rc, long long ldr, double* Sr,
+                         double* Sc, long long lds, double* work, hipStream_t s) {
+  if (n <= 0 || ncols <= 0) return;
+  if (mode == 1) {
+    if (Sr) run<1, false>(A, lda, n, leaf_of, ncols, Rr, ldr, Sr, lds, work, s);
+    if (Sc) run<1, true>(A, lda, n, leaf_of, ncols, Rc, ldr, Sc, lds, work, s);
+  } else {
+    if (Sr) run<2, false>(A, lda, n, leaf_of, ncols, Rr, ldr, Sr, lds, work, s);
+    if (Sc) run<2, true>(A, lda, n, leaf_of, ncols, Rc, ldr, Sc, lds, work, s);
+  }
+}
+
+void launch_round_r(double* R, long long ld, long long n, int col0, int col1, int mode,
+                    hipStream_t s) {
+  const long long total = n * (long long)(col1 - col0);
+  if (total <= 0 || mode == 0) return;
+  hipLaunchKernelGGL(round_r_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, R, ld,
+                     n, col0, col1, mode);
+}
+
+}  // namespace hss

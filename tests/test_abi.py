@@ -48,7 +48,19 @@ def test_host_side_argument_errors():
     st = L.hss_compress(ctypes.c_void_p(16), 0, 10, 10, None, ctypes.byref(o), None, ctypes.byref(out))
     assert st == P.HSS_ERR_ARG
     assert L.hss_matvec(None, 1, None, 1, None, 1, None) == P.HSS_ERR_STATE
-    assert L.hss_random_normal(0, 3, 10, 0, 1, ctypes.c_void_p(16), 1, None) == P.HSS_ERR_ARG
+    assert L.hss_random_normal(0, 3, 10, 0, 1, 0, ctypes.c_void_p(16), 1, None) == P.HSS_ERR_ARG
+    assert L.hss_random_normal(0, 0, 10, 0, 1, 5, ctypes.c_void_p(16), 1, None) == P.HSS_ERR_ARG
+    # reduced-precision sampling needs FP32 storage; unknown modes are rejected
+    o = P.hss_default_opts()
+    o.sample_prec = P.HSS_SAMPLE_BF16X3
+    st = L.hss_compress(ctypes.c_void_p(16), P.HSS_F64, 10, 10, None, ctypes.byref(o), None, ctypes.byref(out))
+    assert st == P.HSS_ERR_ARG and b"FP32" in L.hss_last_error()
+    o.sample_prec = 9
+    st = L.hss_compress(ctypes.c_void_p(16), P.HSS_F32, 10, 10, None, ctypes.byref(o), None, ctypes.byref(out))
+    assert st == P.HSS_ERR_ARG
+    st = L.hss_sample(ctypes.c_void_p(16), P.HSS_F64, P.HSS_SAMPLE_F32, 10, 10, None, 1, ctypes.c_void_p(16),
+                      None, 1, ctypes.c_void_p(16), None, 1, None)
+    assert st == P.HSS_ERR_ARG
     assert L.hss_id_batched(-1, None, None, None, None, 0.1, None, None, None, None) == P.HSS_ERR_ARG
 
 
