@@ -154,12 +154,150 @@ def cpu_baseline(cfg, points, d_final, panel_rows):
     }
 
 
+def run_batched(args) -> int:
+    """The batched workload: 512 independent planar 1/(4 pi r) matrices (N
+    log-uniform in [256, 4096], k-d ordered, FP32 storage), compressed by one
+    hss_compress_batched call with BF16x3 sampling at rtol 1e-4.  A step is
+    the batched compression, one matvec per matrix and the destruction of
+    the handles; `value` is seconds per step.  The CPU baseline runs the
+    oracle on a sample of the matrices and scales by sum(N^2)."""
+    import numpy as np
+    import torch
+
+    import paper_1503_05464_amd as P
+    import workloads as W
+
+    cfg = dict(W.CONFIGS["batched512"])
+    if args.rtol is not None:
+        cfg["rtol"] = args.rtol
+    prec = args.sample_prec if args.sample_prec != "f64" else cfg["sample_prec"]
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    print(f"[bench] workload batched512: {cfg['count']} matrices, assembling", file=sys.stderr, flush=True)
+    sets = W.batch_instances(cfg["count"], cfg["n_lo"], cfg["n_hi"], cfg["point_seed"], cfg["leaf"])
+    As = [W.device_kernel_matrix(cfg["kind"], p, torch.float32, dev) for p in sets]
+    ns = np.array([a.shape[0] for a in As])
+    xs = [torch.from_numpy(np.random.default_rng(int(n)).uniform(-1, 1, (int(n), 1))).to(dev) for n in ns]
+    bs = [torch.empty_like(x) for x in xs]
+    torch.cuda.synchronize()
+    kw = dict(rtol=cfg["rtol"], d0=cfg["d0"], dd=cfg["dd"], d_max=cfg["d_max"], leaf_size=cfg["leaf"],
+              p_margin=args.p_margin if args.p_margin is not None else 10, sample_prec=prec)
+
+    def step():
+        hs = P.hss_compress_batched(As, **kw)
+        for h, x, b in zip(hs, xs, bs):
+            P.hss_matvec(h, x, b)
+        st = P.hss_stats(hs[0])
+        conv = sum(1 for h in hs if h.converged)
+        dmax = max(P.hss_stats(h)["d_final"] for h in hs)
+        for h in hs:
+            P.hss_destroy(h)
+        return st, conv, dmax
+
+    for w in range(args.warmup):
+        st, conv, dmax = step()
+        torch.cuda.synchronize()
+        print(f"[bench] warmup {w}: {st['t_total_ms']:.1f} ms, {conv} converged, max d {dmax}",
+              file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    stats = [step() for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / max(1, args.steps)
+    sts = [s[0] for s in stats]
+    flops = sum(s["sample_gemm_flops"] for s in sts)
+    nbytes = sum(s["sample_gemm_bytes"] for s in sts)
+    t_gemm = sum(s["t_sample_gemm_ms"] for s in sts) / 1e3
+    launches = sum(s["n_sample_launches"] for s in sts)
+    terms, peak = (3, BF16_MFMA_PEAK_TFLOPS) if prec == "bf16x3" else \
+        ((1, FP32_MFMA_PEAK_TFLOPS) if prec == "f32" else (1, FP64_MFMA_PEAK_TFLOPS))
+    issued = terms * flops / t_gemm / 1e12
+    gbs = nbytes / t_gemm / 1e9
+    hbm_bound = nbytes / (HBM_PEAK_GBS * 1e9) > terms * flops / (peak * 1e12)
+    roofline = {
+        "bound": "hbm" if hbm_bound else "mfma",
+        "achieved": round(gbs, 1) if hbm_bound else round(issued, 2),
+        "peak": HBM_PEAK_GBS if hbm_bound else peak,
+        "unit": "GB/s" if hbm_bound else "TFLOP/s",
+        "frac": round(gbs / HBM_PEAK_GBS if hbm_bound else issued / peak, 4),
+        "traffic": None,
+        "kernel": f"sampling products ({prec}) over all matrices",
+        "avg_launch_ms": round(t_gemm * 1e3 / max(1, launches), 4),
+        "launches": launches,
+        "algorithmic_tflops": round(flops / t_gemm / 1e12, 2),
+        "achieved_gbs": round(gbs, 1),
+    }
+    # acceptance: every matrix's matvec against its dense product
+    hs = P.hss_compress_batched(As, **kw)
+    worst = 0.0
+    for A, h in zip(As, hs):
+        x = torch.from_numpy(np.random.default_rng(7).uniform(-1, 1, (A.shape[0], 1))).to(dev)
+        ref = A.double() @ x
+        worst = max(worst, float(torch.linalg.norm(P.hss_matvec(h, x) - ref) / torch.linalg.norm(ref)))
+    conv = sum(1 for h in hs if h.converged)
+    del hs
+    cpu = None
+    if not args.no_cpu_baseline:
+        from oracle import hss as ohss
+
+        print("[bench] cpu baseline (oracle on a sample of the matrices)", file=sys.stderr, flush=True)
+        pick = np.random.default_rng(0).choice(len(sets), 6, replace=False)
+        t_s, n2 = 0.0, 0.0
+        for q in pick:
+            Ah = W.kernel_rows(cfg["kind"], sets[q], np.arange(len(sets[q])), np.float32).astype(np.float32)
+            t1 = time.perf_counter()
+            ohss.compress(Ah, ohss.Options(rtol=kw["rtol"], d0=kw["d0"], dd=kw["dd"], d_max=kw["d_max"],
+                                           p_margin=kw["p_margin"], leaf_size=kw["leaf_size"],
+                                           sample_prec=prec))
+            t_s += time.perf_counter() - t1
+            n2 += float(len(sets[q])) ** 2
+        scale = float((ns.astype(float) ** 2).sum()) / n2
+        try:
+            from threadpoolctl import threadpool_info
+
+            cores = max([int(i.get("num_threads", 1)) for i in threadpool_info()] or [1])
+        except Exception:  # pragma: no cover
+            cores = len(os.sched_getaffinity(0))
+        cpu = {"value": round(t_s * scale, 3), "unit": "s", "cores": cores, "kind": "oracle",
+               "sample": f"oracle compression of 6 of the {len(sets)} matrices (N = "
+                         f"{sorted(int(len(sets[q])) for q in pick)}, {t_s:.2f} s) scaled by sum(N^2)"}
+    out = {
+        "metric": f"HSS batched compress s, {cfg['count']} matrices N in [{cfg['n_lo']}, {cfg['n_hi']}]",
+        "value": round(ms / 1e3, 4),
+        "unit": "s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 2),
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": f"{prec} sampling, f64 ID",
+        "data": "synthetic",
+        "config": {
+            "workload": f"batched512: {cfg['count']} planar 1/(4 pi r) matrices, N log-uniform in "
+                        f"[{cfg['n_lo']}, {cfg['n_hi']}] (sum N^2 = {float((ns.astype(float) ** 2).sum()):.3g}), "
+                        f"A f32, leaf {cfg['leaf']}, rtol {cfg['rtol']}, d0 {cfg['d0']}, dd {cfg['dd']}, "
+                        f"{prec.upper()} sampling",
+            "count": cfg["count"], "converged": conv,
+            "step": "hss_compress_batched + hss_matvec(nrhs=1) per matrix + hss_destroy",
+        },
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "accuracy": {"worst_matvec_rel_err_vs_dense": worst, "bound": 10 * cfg["rtol"]},
+        "breakdown_ms": {k: round(float(np.median([s[k] for s in sts])), 2)
+                         for k in ("t_total_ms", "t_sample_ms", "t_sample_gemm_ms", "t_levels_ms", "t_id_ms")},
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="gauss65536", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="gauss65536", choices=sorted(WORKLOADS) + ["batched512"])
     ap.add_argument("--rtol", type=float, default=None)
     ap.add_argument("--p-margin", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -172,6 +310,8 @@ def main() -> int:
         print("bench.py runs on one GPU only: the compression path has no multi-GPU mode "
               "(see DESIGN.md for how it would shard)", file=sys.stderr)
         return 2
+    if args.workload == "batched512":
+        return run_batched(args)
 
     import numpy as np
     import torch

@@ -129,6 +129,31 @@ hss_status hss_compress(const void* A, int dtype, long long n, long long lda,
                         hss_handle* out);
 
 /*
+ * Compression of nmat independent matrices in one call, for callers with
+ * many small problems (e.g. the frontal matrices of a sparse solver).  Each
+ * matrix is compressed exactly as hss_compress would (Alg. 1 with the
+ * adaptive sampling of Sec. 3.3 / Alg. 5): its own random matrices, its own
+ * d, its own fail/retry decisions.  What is shared is the schedule: the
+ * passes of all matrices run together, and each height of every unfinished
+ * matrix is one batched launch of each phase (gathers, local-sample
+ * products, IDs, index sets, R_tau), so small matrices fill the device
+ * together.
+ *  A[i]     DEVICE n[i] x n[i] row-major, leading dimension lda[i], all of
+ *           one dtype; read during the call only.
+ *  trees    NULL (bisection with opts->leaf_size) or nmat trees (as in
+ *           hss_compress).
+ *  opts     shared by all matrices; no user random matrices.
+ *  out      nmat handles (each owned by the caller, hss_destroy each);
+ *  status   optional host array: HSS_OK or HSS_NOT_CONVERGED per matrix.
+ * Returns HSS_OK if every matrix converged, HSS_NOT_CONVERGED if any did
+ * not (all handles valid), or an error, in which case no handle is
+ * returned.  Host-synchronous; all work on `stream`.
+ */
+hss_status hss_compress_batched(int nmat, const void* const* A, int dtype, const long long* n,
+                                const long long* lda, const hss_tree* trees, const hss_opts* opts,
+                                void* stream, hss_handle* out, int* status);
+
+/*
  * b = A_HSS x (Alg. 2) for nrhs columns.  x: DEVICE n x nrhs (ldx >= nrhs),
  * b: DEVICE n x nrhs (ldb >= nrhs), must not overlap x.  Stream-ordered.
  */

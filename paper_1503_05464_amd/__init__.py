@@ -30,7 +30,8 @@ HSS_SAMPLE_BF16X3 = 2
 _PREC = {"f64": HSS_SAMPLE_F64, "f32": HSS_SAMPLE_F32, "bf16x3": HSS_SAMPLE_BF16X3}
 
 EXPORTED = [
-    "hss_default_opts", "hss_compress", "hss_matvec", "hss_factor", "hss_solve", "hss_stats",
+    "hss_default_opts", "hss_compress", "hss_compress_batched", "hss_matvec", "hss_factor",
+    "hss_solve", "hss_stats",
     "hss_ranks", "hss_export_node", "hss_import", "hss_destroy", "hss_last_error",
     "hss_random_normal", "hss_sample", "hss_id_batched",
 ]
@@ -88,6 +89,8 @@ def lib() -> C.CDLL:
         L.hss_default_opts.restype = None
         L.hss_compress.argtypes = [vp, i, ll, ll, C.POINTER(hss_tree), C.POINTER(hss_opts), vp,
                                    C.POINTER(vp)]
+        L.hss_compress_batched.argtypes = [i, vp, i, vp, vp, C.POINTER(hss_tree), C.POINTER(hss_opts),
+                                           vp, vp, vp]
         L.hss_matvec.argtypes = [vp, i, vp, ll, vp, ll, vp]
         L.hss_factor.argtypes = [vp, vp]
         L.hss_solve.argtypes = [vp, i, vp, ll, vp, ll, vp]
@@ -196,6 +199,47 @@ def hss_compress(A, tree=None, *, rtol=1e-6, d0=64, dd=32, d_max=4096, p_margin=
                             C.byref(o), _stream(stream), C.byref(out))
     _check(st, (HSS_OK, HSS_NOT_CONVERGED))
     return HSSHandle(out, A.shape[0], st)
+
+
+def hss_compress_batched(As, trees=None, *, rtol=1e-6, d0=64, dd=32, d_max=4096, p_margin=10, seed=0,
+                         leaf_size=64, sample_prec="f64", stream=None) -> list:
+    """Compress the square CUDA tensors in As (all float32 or all float64)
+    together: one adaptive pass schedule for all, each level of every
+    unfinished matrix in one batched launch per phase.  trees: None or one
+    (lo, hi, left, right) per matrix.  Returns one HSSHandle per matrix."""
+    import torch
+
+    if not As:
+        return []
+    dts = {A.dtype for A in As}
+    if len(dts) != 1 or next(iter(dts)) not in (torch.float32, torch.float64):
+        raise ValueError("the matrices must all be float32 or all float64")
+    for A in As:
+        if A.dim() != 2 or A.shape[0] != A.shape[1] or A.stride(1) != 1 or not A.is_cuda:
+            raise ValueError("each A must be a square CUDA matrix with unit column stride")
+    dt = HSS_F32 if As[0].dtype == torch.float32 else HSS_F64
+    nm = len(As)
+    o = hss_default_opts()
+    o.rtol, o.d0, o.dd, o.d_max, o.p_margin = float(rtol), int(d0), int(dd), int(d_max), int(p_margin)
+    o.seed, o.leaf_size = int(seed), int(leaf_size)
+    o.sample_prec = _PREC[sample_prec]
+    ptrs = np.array([A.data_ptr() for A in As], dtype=np.uint64)
+    ns = np.array([A.shape[0] for A in As], dtype=np.int64)
+    lds = np.array([A.stride(0) for A in As], dtype=np.int64)
+    keep = []
+    tarr = None
+    if trees is not None:
+        tarr = (hss_tree * nm)()
+        for q, tr in enumerate(trees):
+            t, arrs = _tree_struct(tr)
+            tarr[q] = t
+            keep.append(arrs)
+    outs = (C.c_void_p * nm)()
+    status = np.zeros(nm, dtype=np.int32)
+    st = lib().hss_compress_batched(nm, _np_ptr(ptrs), dt, _np_ptr(ns), _np_ptr(lds), tarr, C.byref(o),
+                                    _stream(stream), outs, _np_ptr(status))
+    _check(st, (HSS_OK, HSS_NOT_CONVERGED))
+    return [HSSHandle(C.c_void_p(outs[q]), int(ns[q]), int(status[q])) for q in range(nm)]
 
 
 def hss_matvec(h: HSSHandle, x, b=None, stream=None):

@@ -66,7 +66,7 @@ namespace hss {
 void* Arena::alloc(size_t bytes) {
   bytes = round_up(bytes ? bytes : 1, 256);
   if (bytes > left) {
-    const size_t chunk = std::max(bytes, (size_t)64 << 20);
+    const size_t chunk = std::max(bytes, this->chunk);
     void* p = nullptr;
     if (hipMalloc(&p, chunk) != hipSuccess) return nullptr;
     chunks.push_back(p);
@@ -292,45 +292,48 @@ struct EventTimer {  // HIP events on the compression stream, summed at the end
   }
 };
 
-hss_status sample_columns(Handle& H, const void* A, long long lda, int c0, int c1, EventTimer& tm) {
+// Columns c0..c1-1 of R^r, R^c and of the samples of one matrix, on the
+// lead handle's stream and sampling workspace (batches share both).
+hss_status sample_columns(Handle& L, Handle& H, const void* A, long long lda, int c0, int c1,
+                          EventTimer& tm) {
   const int nc = c1 - c0;
   if (nc <= 0) return HSS_OK;
   const int ev0 = tm.begin();
   if (H.opts.R_user_r) {
     HIPCHK(hipMemcpy2DAsync(H.Rr + c0, H.ldg * 8, H.opts.R_user_r + c0, H.opts.ld_R_user * 8,
-                            (size_t)nc * 8, H.n, hipMemcpyDeviceToDevice, H.stream));
+                            (size_t)nc * 8, H.n, hipMemcpyDeviceToDevice, L.stream));
     HIPCHK(hipMemcpy2DAsync(H.Rc + c0, H.ldg * 8, H.opts.R_user_c + c0, H.opts.ld_R_user * 8,
-                            (size_t)nc * 8, H.n, hipMemcpyDeviceToDevice, H.stream));
+                            (size_t)nc * 8, H.n, hipMemcpyDeviceToDevice, L.stream));
   } else {
-    launch_random_normal(H.opts.seed, 0, H.n, c0, c1, H.Rr + c0, H.ldg, H.stream);
-    launch_random_normal(H.opts.seed, 1, H.n, c0, c1, H.Rc + c0, H.ldg, H.stream);
+    launch_random_normal(H.opts.seed, 0, H.n, c0, c1, H.Rr + c0, H.ldg, L.stream);
+    launch_random_normal(H.opts.seed, 1, H.n, c0, c1, H.Rc + c0, H.ldg, L.stream);
   }
   const int prec = H.opts.sample_prec;
   if (prec != HSS_SAMPLE_F64) {  // R in the products' precision, used as such from here on
-    launch_round_r(H.Rr, H.ldg, H.n, c0, c1, prec, H.stream);
-    launch_round_r(H.Rc, H.ldg, H.n, c0, c1, prec, H.stream);
+    launch_round_r(H.Rr, H.ldg, H.n, c0, c1, prec, L.stream);
+    launch_round_r(H.Rc, H.ldg, H.n, c0, c1, prec, L.stream);
   }
   const long long wd = prec == HSS_SAMPLE_F64 ? sample_workspace_doubles(H.n, nc)
                                               : sample_mixed_workspace_doubles(H.n, nc);
   double* work = nullptr;
   if (wd > 0) {
-    work = static_cast<double*>(H.work_sample.ensure((size_t)wd * 8));
+    work = static_cast<double*>(L.work_sample.ensure((size_t)wd * 8));
     if (!work) return fail(HSS_ERR_ALLOC, "sampling workspace");
   }
   const int evg = tm.begin();
   if (prec == HSS_SAMPLE_F64)
     launch_sample(A, H.dtype, H.n, lda, H.leaf_of, nc, H.Rr + c0, H.Rc + c0, H.ldg, H.Sr + c0,
-                  H.Sc + c0, H.ldg, work, H.stream);
+                  H.Sc + c0, H.ldg, work, L.stream);
   else
     launch_sample_mixed(static_cast<const float*>(A), H.n, lda, H.leaf_of, nc, prec, H.Rr + c0,
-                        H.Rc + c0, H.ldg, H.Sr + c0, H.Sc + c0, H.ldg, work, H.stream);
+                        H.Rc + c0, H.ldg, H.Sr + c0, H.Sc + c0, H.ldg, work, L.stream);
   HIPCHK(hipGetLastError());
   tm.end(evg, 3);
   tm.end(ev0, 0);
   // two launches (S^r and S^c), each 2 n^2 nc flops; bytes: A once, R read, S written
-  H.n_sgemm += 2;
-  H.sgemm_flops += 4.0 * (double)H.n * (double)H.n * nc;
-  H.sgemm_bytes += 2.0 * ((double)H.n * (double)H.n * (H.dtype == HSS_F32 ? 4 : 8) +
+  L.n_sgemm += 2;
+  L.sgemm_flops += 4.0 * (double)H.n * (double)H.n * nc;
+  L.sgemm_bytes += 2.0 * ((double)H.n * (double)H.n * (H.dtype == HSS_F32 ? 4 : 8) +
                           2.0 * (double)H.n * nc * 8);
   return HSS_OK;
 }
@@ -353,26 +356,33 @@ Seg r_in(const Handle& H, int t, bool row_side, int c0) {
   return s;
 }
 
-hss_status process_level(Handle& H, const void* A, long long lda, const std::vector<int>& lvl,
-                         const std::vector<char>& ext, int d, bool forced, bool& any_fail,
-                         EventTimer& tm) {
-  std::vector<Node>& nd = H.nodes;
-  std::vector<int> todo;
-  for (int t : lvl) {
-    const Node& v = nd[t];
-    if (!v.leaf() && !(nd[v.left].state == HSS_COMPRESSED && nd[v.right].state == HSS_COMPRESSED))
-      continue;
-    if (v.state == HSS_COMPRESSED && !ext[t]) continue;
-    if (v.state == HSS_COMPRESSED && v.cdone >= d) continue;
-    todo.push_back(t);
-  }
-  if (todo.empty()) return HSS_OK;
+// One node of one matrix in a level batch: node t of handle H, whose matrix
+// has d sample columns so far; `forced` accepts every ID (d_max reached).
+struct Item {
+  Handle* H;
+  const void* A;
+  long long lda;
+  int t;
+  int d;
+  bool forced;
+  char* any_fail;  // set when an ID of this node fails the rule
+};
+
+// The level step of Alg. 1 / Alg. 5 for a batch of nodes that may belong to
+// different matrices: every phase is one batched launch over all of them.
+// L (the lead handle) provides the stream, staging buffer, ID workspace and
+// rank readback; all handles of a batch share L's stream.
+hss_status process_items(Handle& L, std::vector<Item>& items, EventTimer& tm) {
+  if (items.empty()) return HSS_OK;
   const int ev_level = tm.begin();
+  auto node = [](const Item& it) -> Node& { return it.H->nodes[it.t]; };
 
   // (1) first visit: sizes, buffers, D or B
   std::vector<GatherDesc> gath;
-  for (int t : todo) {
-    Node& v = nd[t];
+  for (Item& it : items) {
+    Handle& H = *it.H;
+    std::vector<Node>& nd = H.nodes;
+    Node& v = nd[it.t];
     if (v.set_up) continue;
     if (v.leaf()) {
       const int m = v.size();
@@ -386,6 +396,8 @@ hss_status process_level(Handle& H, const void* A, long long lda, const std::vec
       g.out = v.D;
       g.ldo = m;
       g.row_off = g.col_off = v.lo;
+      g.A = it.A;
+      g.lda = it.lda;
       gath.push_back(g);
     } else {
       const Node& a = nd[v.left];
@@ -398,6 +410,8 @@ hss_status process_level(Handle& H, const void* A, long long lda, const std::vec
       v.Sc = arena_alloc<double>(H, (size_t)v.mc * H.ldg);
       if (!v.B12 || !v.B21 || !v.Sr || !v.Sc) return fail(HSS_ERR_ALLOC, "inner node buffers");
       GatherDesc g{};
+      g.A = it.A;
+      g.lda = it.lda;
       g.rows = a.Ir;
       g.cols = b.Ic;
       g.nr = a.kr;
@@ -421,12 +435,16 @@ hss_status process_level(Handle& H, const void* A, long long lda, const std::vec
     v.cdone = 0;
     v.set_up = true;
   }
-  HIPCHK(launch_gather(A, H.dtype, lda, gath.data(), (int)gath.size(), H.staging, H.stream));
+  HIPCHK(launch_gather(items[0].A, L.dtype, items[0].lda, gath.data(), (int)gath.size(), L.staging,
+                       L.stream));
 
   // (2) local samples of inner nodes, columns [cdone, d) (Alg. 1 / Alg. 5)
   std::vector<GemmDesc> gd;
-  for (int t : todo) {
-    Node& v = nd[t];
+  for (Item& it : items) {
+    Handle& H = *it.H;
+    std::vector<Node>& nd = H.nodes;
+    Node& v = nd[it.t];
+    const int d = it.d;
     if (v.leaf() || v.cdone >= d) continue;
     const Node& a = nd[v.left];
     const Node& b = nd[v.right];
@@ -454,50 +472,54 @@ hss_status process_level(Handle& H, const void* A, long long lda, const std::vec
     mk(a.kc, b.kr, v.B21, a.kc, 1, b.Rc + c0, a.Sc + c0, a.perm_c, v.Sc + c0);
     mk(b.kc, a.kr, v.B12, b.kc, 1, a.Rc + c0, b.Sc + c0, b.perm_c, v.Sc + (long long)a.kc * H.ldg + c0);
   }
-  HIPCHK(launch_gemm_batched(gd.data(), (int)gd.size(), H.staging, H.stream));
+  HIPCHK(launch_gemm_batched(gd.data(), (int)gd.size(), L.staging, L.stream));
 
   // (3) interpolative decompositions of the nodes not yet compressed
-  std::vector<int> idn;
-  for (int t : todo)
-    if (nd[t].state != HSS_COMPRESSED) idn.push_back(t);
-  std::vector<int> passed;
+  std::vector<int> idn;  // indices into items
+  for (size_t q = 0; q < items.size(); ++q)
+    if (node(items[q]).state != HSS_COMPRESSED) idn.push_back((int)q);
+  std::vector<char> passed(items.size(), 0);
   if (!idn.empty()) {
     const int np = 2 * (int)idn.size();
     std::vector<IdProblem> pr(np);
     for (int q = 0; q < np; ++q) {
-      const Node& v = nd[idn[q / 2]];
+      const Item& it = items[idn[q / 2]];
+      const Node& v = node(it);
       const bool rs = (q % 2) == 0;
       IdProblem& p = pr[q];
       p.Y = rs ? v.Sr : v.Sc;
-      p.ldy = H.ldg;
+      p.ldy = it.H->ldg;
       p.m = rs ? v.mr : v.mc;
-      p.d = d;
+      p.d = it.d;
       p.perm = rs ? v.perm_r : v.perm_c;
       p.E = rs ? v.Er : v.Ec;
-      p.kfail = (forced || d - H.opts.p_margin < 0) ? -1 : d - H.opts.p_margin;
+      const int pm = it.H->opts.p_margin;
+      p.kfail = (it.forced || it.d - pm < 0) ? -1 : it.d - pm;
     }
     const size_t wb = id_workspace_bytes(pr.data(), np);
-    void* wk = H.work_id.ensure(wb);
+    void* wk = L.work_id.ensure(wb);
     if (!wk) return fail(HSS_ERR_ALLOC, "ID workspace");
-    if (H.k_host_cap < np) {
-      if (H.k_host) hipHostFree(H.k_host);
-      H.k_host = nullptr;
-      HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&H.k_host), (size_t)np * 2 * 4, hipHostMallocDefault));
-      H.k_host_cap = np * 2;
+    if (L.k_host_cap < np) {
+      if (L.k_host) hipHostFree(L.k_host);
+      L.k_host = nullptr;
+      HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&L.k_host), (size_t)np * 2 * 4, hipHostMallocDefault));
+      L.k_host_cap = np * 2;
     }
     const int ev_id = tm.begin();
-    HIPCHK(launch_id_factor(pr.data(), np, H.opts.rtol, wk, H.work_id.cap, H.k_host, H.staging,
-                            H.stream));
-    H.staging.reset();
-    const int kf = d - H.opts.p_margin;
+    HIPCHK(launch_id_factor(pr.data(), np, L.opts.rtol, wk, L.work_id.cap, L.k_host, L.staging,
+                            L.stream));
+    L.staging.reset();
     std::vector<int> sel;
     for (size_t q = 0; q < idn.size(); ++q) {
-      Node& v = nd[idn[q]];
-      const int kr = H.k_host[2 * q], kc = H.k_host[2 * q + 1];
+      Item& it = items[idn[q]];
+      Handle& H = *it.H;
+      Node& v = node(it);
+      const int kf = it.d - H.opts.p_margin;
+      const int kr = L.k_host[2 * q], kc = L.k_host[2 * q + 1];
       const bool fr = (kr > kf && kr < v.mr), fc = (kc > kf && kc < v.mc);
-      if (!forced && (fr || fc)) {
+      if (!it.forced && (fr || fc)) {
         v.state = HSS_PARTIALLY_COMPRESSED;
-        any_fail = true;
+        *it.any_fail = 1;
         continue;
       }
       v.kr = kr;
@@ -508,19 +530,21 @@ hss_status process_level(Handle& H, const void* A, long long lda, const std::vec
       v.Ic = arena_alloc<int>(H, (size_t)kc);
       if (!v.Rr || !v.Rc || !v.Ir || !v.Ic) return fail(HSS_ERR_ALLOC, "node R / index buffers");
       v.state = HSS_COMPRESSED;
-      passed.push_back(idn[q]);
+      passed[idn[q]] = 1;
       sel.push_back(2 * (int)q);
       sel.push_back(2 * (int)q + 1);
     }
-    HIPCHK(launch_id_finish(pr.data(), np, H.k_host, sel.data(), (int)sel.size(), wk, H.staging,
-                            H.stream));
+    HIPCHK(launch_id_finish(pr.data(), np, L.k_host, sel.data(), (int)sel.size(), wk, L.staging,
+                            L.stream));
     tm.end(ev_id, 2);
   }
 
   // (4) skeleton index sets of the nodes compressed now: I_tau = I_in(J)
   std::vector<IndexDesc> ix;
-  for (int t : passed) {
-    const Node& v = nd[t];
+  for (size_t q = 0; q < items.size(); ++q) {
+    if (!passed[q]) continue;
+    const std::vector<Node>& nd = items[q].H->nodes;
+    const Node& v = nd[items[q].t];
     IndexDesc a{}, c{};
     a.perm = v.perm_r;
     a.k = v.kr;
@@ -544,22 +568,24 @@ hss_status process_level(Handle& H, const void* A, long long lda, const std::vec
     if (a.k > 0) ix.push_back(a);
     if (c.k > 0) ix.push_back(c);
   }
-  HIPCHK(launch_index_compose(ix.data(), (int)ix.size(), H.staging, H.stream));
+  HIPCHK(launch_index_compose(ix.data(), (int)ix.size(), L.staging, L.stream));
 
   // (5) R^r_tau = V^T R^r_in and R^c_tau = U^T R^c_in on the new columns
   gd.clear();
-  for (int t : todo) {
-    Node& v = nd[t];
+  for (size_t q = 0; q < items.size(); ++q) {
+    const Item& it = items[q];
+    const Handle& H = *it.H;
+    Node& v = node(it);
     if (v.state != HSS_COMPRESSED) continue;
-    const bool fresh = std::find(passed.begin(), passed.end(), t) != passed.end();
-    const int c0 = fresh ? 0 : v.cdone;
+    const int d = it.d;
+    const int c0 = passed[q] ? 0 : v.cdone;
     if (c0 >= d) continue;
     for (int side = 0; side < 2; ++side) {
       // side 0: R^r_tau uses V (perm_c, Ec, kc, mc); side 1: R^c_tau uses U
       const int k = side == 0 ? v.kc : v.kr;
       const int m = side == 0 ? v.mc : v.mr;
       const int* perm = side == 0 ? v.perm_c : v.perm_r;
-      Seg src = r_in(H, t, side == 0, c0);
+      Seg src = r_in(H, it.t, side == 0, c0);
       GemmDesc g{};
       g.M = k;
       g.N = d - c0;
@@ -577,99 +603,167 @@ hss_status process_level(Handle& H, const void* A, long long lda, const std::vec
       gd.push_back(g);
     }
   }
-  HIPCHK(launch_gemm_batched(gd.data(), (int)gd.size(), H.staging, H.stream));
-  for (int t : todo) nd[t].cdone = d;
+  HIPCHK(launch_gemm_batched(gd.data(), (int)gd.size(), L.staging, L.stream));
+  for (Item& it : items) node(it).cdone = it.d;
   tm.end(ev_level, 1);
-  HIPCHK(hipStreamSynchronize(H.stream));
-  H.staging.reset();
+  HIPCHK(hipStreamSynchronize(L.stream));
+  L.staging.reset();
   return HSS_OK;
 }
 
-hss_status compress_impl(Handle& H, const void* A, long long lda) {
+// One matrix of a compression batch.
+struct Job {
+  Handle* H;
+  const void* A;
+  long long lda;
+  int d = 0;
+  bool forced = false;
+  bool done = false;
+  std::vector<char> ext;
+};
+
+// Adaptive randomized compression (Alg. 1 with the late-notification
+// schedule of Alg. 5, level-synchronous) of every matrix of the batch
+// together: a pass visits the heights 0, 1, ... and each height is one
+// level batch over the unfinished matrices; a matrix that still has failed
+// nodes after a pass draws dd more random columns; the passes go on until
+// every matrix is done.  jobs[0].H is the lead handle.
+hss_status compress_batch(std::vector<Job>& jobs) {
   const double t0 = now_ms();
+  Handle& L = *jobs[0].H;
   EventTimer tm;
-  tm.s = H.stream;
-  std::vector<Node>& nd = H.nodes;
-  const long long n = H.n;
-  if (nd[0].leaf()) {  // a single leaf: D = A
-    Node& r = nd[0];
-    r.D = arena_alloc<double>(H, (size_t)n * n);
-    if (!r.D) return fail(HSS_ERR_ALLOC, "D");
-    GatherDesc g{};
-    g.nr = g.nc = (int)n;
-    g.out = r.D;
-    g.ldo = n;
-    HIPCHK(launch_gather(A, H.dtype, lda, &g, 1, H.staging, H.stream));
-    HIPCHK(hipStreamSynchronize(H.stream));
-    H.compressed = true;
-    H.t_total = now_ms() - t0;
-    return HSS_OK;
-  }
-  const int dmax = H.opts.d_max;
-  H.ldg = (long long)round_up((size_t)dmax, 8);
-  H.Rr = arena_alloc<double>(H, (size_t)n * H.ldg);
-  H.Rc = arena_alloc<double>(H, (size_t)n * H.ldg);
-  H.Sr = arena_alloc<double>(H, (size_t)n * H.ldg);
-  H.Sc = arena_alloc<double>(H, (size_t)n * H.ldg);
-  H.leaf_of = arena_alloc<int>(H, (size_t)n);
-  if (!H.Rr || !H.Rc || !H.Sr || !H.Sc || !H.leaf_of)
-    return fail(HSS_ERR_ALLOC, "random matrices / samples (n x d_max doubles each)");
-  {
+  tm.s = L.stream;
+  std::vector<GatherDesc> single;
+  int maxh = 0;
+  for (Job& j : jobs) {
+    Handle& H = *j.H;
+    std::vector<Node>& nd = H.nodes;
+    const long long n = H.n;
+    if (nd[0].leaf()) {  // a single leaf: D = A
+      Node& r = nd[0];
+      r.D = arena_alloc<double>(H, (size_t)n * n);
+      if (!r.D) return fail(HSS_ERR_ALLOC, "D");
+      GatherDesc g{};
+      g.nr = g.nc = (int)n;
+      g.out = r.D;
+      g.ldo = n;
+      g.A = j.A;
+      g.lda = j.lda;
+      single.push_back(g);
+      j.done = true;
+      continue;
+    }
+    const int dmax = H.opts.d_max;
+    H.ldg = (long long)round_up((size_t)dmax, 8);
+    H.Rr = arena_alloc<double>(H, (size_t)n * H.ldg);
+    H.Rc = arena_alloc<double>(H, (size_t)n * H.ldg);
+    H.Sr = arena_alloc<double>(H, (size_t)n * H.ldg);
+    H.Sc = arena_alloc<double>(H, (size_t)n * H.ldg);
+    H.leaf_of = arena_alloc<int>(H, (size_t)n);
+    if (!H.Rr || !H.Rc || !H.Sr || !H.Sc || !H.leaf_of)
+      return fail(HSS_ERR_ALLOC, "random matrices / samples (n x d_max doubles each)");
     const int nl = (int)H.leaves.size();
     std::vector<int> lo(nl), hi(nl);
     for (int q = 0; q < nl; ++q) {
       lo[q] = nd[H.leaves[q]].lo;
       hi[q] = nd[H.leaves[q]].hi;
     }
-    int* dlo = static_cast<int*>(H.staging.push(lo.data(), lo.size() * 4));
-    int* dhi = static_cast<int*>(H.staging.push(hi.data(), hi.size() * 4));
+    int* dlo = static_cast<int*>(L.staging.push(lo.data(), lo.size() * 4));
+    int* dhi = static_cast<int*>(L.staging.push(hi.data(), hi.size() * 4));
     if (!dlo || !dhi) return fail(HSS_ERR_HIP, "staging");
-    launch_leaf_of(nl, dlo, dhi, H.leaf_of, H.stream);
+    launch_leaf_of(nl, dlo, dhi, H.leaf_of, L.stream);
     HIPCHK(hipGetLastError());
+    j.d = std::min(H.opts.d0, dmax);
+    CHK(sample_columns(L, H, j.A, j.lda, 0, j.d, tm));
+    H.passes = 0;
+    H.converged = true;
+    j.ext.assign(nd.size(), 0);
+    maxh = std::max(maxh, H.height);
   }
-  int d = std::min(H.opts.d0, dmax);
-  CHK(sample_columns(H, A, lda, 0, d, tm));
-  bool forced = false;
-  H.passes = 0;
-  H.converged = true;
-  std::vector<char> ext(nd.size(), 0);
+  if (!single.empty())
+    HIPCHK(launch_gather(single[0].A, L.dtype, single[0].lda, single.data(), (int)single.size(),
+                         L.staging, L.stream));
+  int pass = 0;
   while (true) {
-    ++H.passes;
-    // a compressed node extends its samples iff a non-root ancestor is
-    // unfinished (only then does anyone read the new columns)
-    for (size_t t = 1; t < nd.size(); ++t) ext[t] = 0;
-    for (int h = H.height - 1; h >= 0; --h)
-      for (int t : H.levels[h]) {
-        const int p = nd[t].parent;
-        ext[t] = (p != 0) && (nd[p].state != HSS_COMPRESSED || ext[p]);
-      }
-    bool any_fail = false;
-    for (int h = 0; h < H.height; ++h)
-      CHK(process_level(H, A, lda, H.levels[h], ext, d, forced, any_fail, tm));
-    bool done = true;
-    int ncomp = 0, nmax = 0;
-    for (size_t t = 1; t < nd.size(); ++t) {
-      if (nd[t].state != HSS_COMPRESSED) done = false;
-      else ++ncomp;
-      nmax = std::max(nmax, std::max(nd[t].kr, nd[t].kc));
+    std::vector<Job*> act;
+    for (Job& j : jobs)
+      if (!j.done) act.push_back(&j);
+    if (act.empty()) break;
+    ++pass;
+    std::vector<char> fail_of(jobs.size(), 0);
+    for (Job* j : act) {
+      Handle& H = *j->H;
+      std::vector<Node>& nd = H.nodes;
+      ++H.passes;
+      // a compressed node extends its samples iff a non-root ancestor is
+      // unfinished (only then does anyone read the new columns)
+      for (size_t t = 1; t < nd.size(); ++t) j->ext[t] = 0;
+      for (int h = H.height - 1; h >= 0; --h)
+        for (int t : H.levels[h]) {
+          const int p = nd[t].parent;
+          j->ext[t] = (p != 0) && (nd[p].state != HSS_COMPRESSED || j->ext[p]);
+        }
     }
-    if (H.verbose) {
-      std::fprintf(stderr, "[hss] pass %d d=%d compressed %d/%d max rank %d (%.1f ms)\n", H.passes, d,
-                   ncomp, (int)nd.size() - 1, nmax, now_ms() - t0);
+    for (int h = 0; h < maxh; ++h) {
+      std::vector<Item> items;
+      for (Job* j : act) {
+        Handle& H = *j->H;
+        if (h >= H.height) continue;
+        std::vector<Node>& nd = H.nodes;
+        char* af = &fail_of[j - jobs.data()];
+        for (int t : H.levels[h]) {
+          const Node& v = nd[t];
+          if (!v.leaf() && !(nd[v.left].state == HSS_COMPRESSED && nd[v.right].state == HSS_COMPRESSED))
+            continue;
+          if (v.state == HSS_COMPRESSED && !j->ext[t]) continue;
+          if (v.state == HSS_COMPRESSED && v.cdone >= j->d) continue;
+          items.push_back(Item{&H, j->A, j->lda, t, j->d, j->forced, af});
+        }
+      }
+      CHK(process_items(L, items, tm));
+    }
+    for (Job* j : act) {
+      Handle& H = *j->H;
+      const std::vector<Node>& nd = H.nodes;
+      bool done = true;
+      int ncomp = 0, nmax = 0;
+      for (size_t t = 1; t < nd.size(); ++t) {
+        if (nd[t].state != HSS_COMPRESSED) done = false;
+        else ++ncomp;
+        nmax = std::max(nmax, std::max(nd[t].kr, nd[t].kc));
+      }
+      if (L.verbose && jobs.size() == 1) {
+        std::fprintf(stderr, "[hss] pass %d d=%d compressed %d/%d max rank %d (%.1f ms)\n", H.passes,
+                     j->d, ncomp, (int)nd.size() - 1, nmax, now_ms() - t0);
+        std::fflush(stderr);
+      }
+      if (done) {
+        j->done = true;
+        continue;
+      }
+      if (j->d >= H.opts.d_max) {
+        j->forced = true;
+        H.converged = false;
+        continue;
+      }
+      const int dn = std::min(j->d + H.opts.dd, H.opts.d_max);
+      CHK(sample_columns(L, H, j->A, j->lda, j->d, dn, tm));
+      j->d = dn;
+    }
+    if (L.verbose && jobs.size() > 1) {
+      int left = 0;
+      for (Job& j : jobs) left += j.done ? 0 : 1;
+      std::fprintf(stderr, "[hss] batch pass %d: %d of %d matrices unfinished (%.1f ms)\n", pass, left,
+                   (int)jobs.size(), now_ms() - t0);
       std::fflush(stderr);
     }
-    if (done) break;
-    if (d >= dmax) {
-      forced = true;
-      H.converged = false;
-      continue;
-    }
-    const int dn = std::min(d + H.opts.dd, dmax);
-    CHK(sample_columns(H, A, lda, d, dn, tm));
-    d = dn;
   }
-  // root: B_ab = A(I^r_a, I^c_b), B_ba = A(I^r_b, I^c_a)
-  {
+  // roots: B_ab = A(I^r_a, I^c_b), B_ba = A(I^r_b, I^c_a)
+  std::vector<GatherDesc> rg;
+  for (Job& j : jobs) {
+    Handle& H = *j.H;
+    std::vector<Node>& nd = H.nodes;
+    if (nd[0].leaf()) continue;
     Node& r = nd[0];
     const Node& a = nd[r.left];
     const Node& b = nd[r.right];
@@ -678,32 +772,53 @@ hss_status compress_impl(Handle& H, const void* A, long long lda) {
     r.B12 = arena_alloc<double>(H, (size_t)a.kr * b.kc);
     r.B21 = arena_alloc<double>(H, (size_t)b.kr * a.kc);
     if (!r.B12 || !r.B21) return fail(HSS_ERR_ALLOC, "root B");
-    GatherDesc g[2] = {};
-    g[0].rows = a.Ir;
-    g[0].cols = b.Ic;
-    g[0].nr = a.kr;
-    g[0].nc = b.kc;
-    g[0].out = r.B12;
-    g[0].ldo = b.kc;
-    g[1].rows = b.Ir;
-    g[1].cols = a.Ic;
-    g[1].nr = b.kr;
-    g[1].nc = a.kc;
-    g[1].out = r.B21;
-    g[1].ldo = a.kc;
-    HIPCHK(launch_gather(A, H.dtype, lda, g, 2, H.staging, H.stream));
+    GatherDesc g{};
+    g.A = j.A;
+    g.lda = j.lda;
+    g.rows = a.Ir;
+    g.cols = b.Ic;
+    g.nr = a.kr;
+    g.nc = b.kc;
+    g.out = r.B12;
+    g.ldo = b.kc;
+    rg.push_back(g);
+    g.rows = b.Ir;
+    g.cols = a.Ic;
+    g.nr = b.kr;
+    g.nc = a.kc;
+    g.out = r.B21;
+    g.ldo = a.kc;
+    rg.push_back(g);
   }
+  if (!rg.empty())
+    HIPCHK(launch_gather(rg[0].A, L.dtype, rg[0].lda, rg.data(), (int)rg.size(), L.staging, L.stream));
   double acc[4] = {0, 0, 0, 0};
   tm.finish(acc);
-  H.t_sgemm = acc[3];
-  HIPCHK(hipStreamSynchronize(H.stream));
-  H.staging.reset();
-  H.d = d;
-  H.t_sample = acc[0];
-  H.t_levels = acc[1];
-  H.t_id = acc[2];
-  H.compressed = true;
-  H.t_total = now_ms() - t0;
+  HIPCHK(hipStreamSynchronize(L.stream));
+  L.staging.reset();
+  const double total = now_ms() - t0;
+  for (Job& j : jobs) {  // timings are those of the whole batch
+    Handle& H = *j.H;
+    H.d = j.d;
+    H.t_sgemm = acc[3];
+    H.t_sample = acc[0];
+    H.t_levels = acc[1];
+    H.t_id = acc[2];
+    H.t_total = total;
+    H.n_sgemm = L.n_sgemm;
+    H.sgemm_flops = L.sgemm_flops;
+    H.sgemm_bytes = L.sgemm_bytes;
+    H.compressed = true;
+  }
+  return HSS_OK;
+}
+
+hss_status compress_impl(Handle& H, const void* A, long long lda) {
+  std::vector<Job> jobs(1);
+  jobs[0].H = &H;
+  jobs[0].A = A;
+  jobs[0].lda = lda;
+  CHK(compress_batch(jobs));
   return H.converged ? HSS_OK : HSS_NOT_CONVERGED;
 }
 
@@ -712,7 +827,10 @@ hss_status new_handle(hss_handle* out, long long n, hipStream_t s, hss_handle_s*
   if (!p) return fail(HSS_ERR_ALLOC, "handle");
   p->h.n = n;
   p->h.stream = s;
-  if (p->h.staging.init((size_t)4 << 20, s) != hipSuccess) {
+  // device arena chunks sized to the matrix (a batch holds many small handles)
+  p->h.arena.chunk = std::min<size_t>((size_t)64 << 20, std::max<size_t>((size_t)1 << 20, (size_t)n * 4096));
+  // descriptor staging grows on demand (only the lead handle of a batch uses much)
+  if (p->h.staging.init((size_t)256 << 10, s) != hipSuccess) {
     delete p;
     return fail(HSS_ERR_ALLOC, "staging buffers");
   }
@@ -974,6 +1092,68 @@ hss_status hss_compress(const void* A, int dtype, long long n, long long lda,
   }
   *out = p;
   return st;
+}
+
+hss_status hss_compress_batched(int nmat, const void* const* A, int dtype, const long long* n,
+                                const long long* lda, const hss_tree* trees, const hss_opts* opts,
+                                void* stream, hss_handle* out, int* status) {
+  g_err.clear();
+  if (nmat < 1 || !A || !n || !lda || !out) return fail(HSS_ERR_ARG, "batch arguments");
+  if (dtype != HSS_F64 && dtype != HSS_F32) return fail(HSS_ERR_ARG, "dtype");
+  hss_opts o;
+  if (opts) o = *opts;
+  else hss_default_opts(&o);
+  if (!(o.rtol >= 0.0) || o.d0 < 1 || o.dd < 1 || o.d_max < o.d0 || o.p_margin < 0)
+    return fail(HSS_ERR_ARG, "rtol / d0 / dd / d_max / p_margin invalid");
+  if (o.sample_prec < HSS_SAMPLE_F64 || o.sample_prec > HSS_SAMPLE_BF16X3)
+    return fail(HSS_ERR_ARG, "unknown sample precision");
+  if (o.sample_prec != HSS_SAMPLE_F64 && dtype != HSS_F32)
+    return fail(HSS_ERR_ARG, "reduced-precision sampling needs A stored in FP32");
+  if (o.R_user_r || o.R_user_c) return fail(HSS_ERR_ARG, "no user random matrices in a batch");
+  for (int i = 0; i < nmat; ++i) {
+    out[i] = nullptr;
+    if (!A[i] || n[i] < 1 || lda[i] < n[i] || n[i] > INT_MAX / 2)
+      return fail(HSS_ERR_ARG, "matrix " + std::to_string(i) + ": A, n or lda invalid");
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  std::vector<hss_handle_s*> hs(nmat, nullptr);
+  auto free_all = [&]() {
+    const std::string msg = g_err;
+    for (hss_handle_s* p : hs) free_handle(p);
+    g_err = msg;
+  };
+  const char* v = std::getenv("HSS_VERBOSE");
+  std::vector<Job> jobs(nmat);
+  for (int i = 0; i < nmat; ++i) {
+    hss_status st = new_handle(&out[i], n[i], s, &hs[i]);
+    if (st == HSS_OK) {
+      Handle& H = hs[i]->h;
+      H.dtype = dtype;
+      H.opts = o;
+      H.verbose = v && v[0] && v[0] != '0';
+      st = build_tree(H, n[i], trees ? &trees[i] : nullptr, o.leaf_size);
+      jobs[i].H = &H;
+      jobs[i].A = A[i];
+      jobs[i].lda = lda[i];
+    }
+    if (st != HSS_OK) {
+      free_all();
+      return st;
+    }
+  }
+  const hss_status st = compress_batch(jobs);
+  if (st != HSS_OK) {
+    free_all();
+    return st;
+  }
+  bool all = true;
+  for (int i = 0; i < nmat; ++i) {
+    out[i] = hs[i];
+    const bool c = hs[i]->h.converged;
+    all = all && c;
+    if (status) status[i] = c ? HSS_OK : HSS_NOT_CONVERGED;
+  }
+  return all ? HSS_OK : HSS_NOT_CONVERGED;
 }
 
 hss_status hss_matvec(hss_handle h, int nrhs, const double* x, long long ldx, double* b,

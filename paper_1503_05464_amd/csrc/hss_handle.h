@@ -17,6 +17,7 @@ struct Arena {
   char* cur = nullptr;
   size_t left = 0;
   size_t total = 0;
+  size_t chunk = (size_t)64 << 20;  // minimum chunk size
   void* alloc(size_t bytes);
   void release();
 };

@@ -134,6 +134,8 @@ struct GatherDesc {   // out[r*ldo + c] = A[rows[r]*lda + cols[c]] (widened)
   double* out;
   long long ldo;
   int row_off, col_off;  // added to rows/cols (for contiguous ranges: rows = null)
+  const void* A;         // this problem's matrix (same dtype as the launch), or null:
+  long long lda;         // the launch's A and lda
 };
 hipError_t launch_gather(const void* A, int dtype, long long lda, const GatherDesc* descs,
                          int nprob, Staging& st, hipStream_t s);

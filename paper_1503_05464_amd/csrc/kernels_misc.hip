@@ -31,7 +31,7 @@ __global__ __launch_bounds__(NT) void gather_kernel(const TA* __restrict__ A, lo
   const GatherDesc& g = descs[lo].g;
   const int r = (int)(t - descs[lo].row0);
   const long long ar = g.rows ? g.rows[r] : (long long)g.row_off + r;
-  const TA* arow = A + ar * lda;
+  const TA* arow = g.A ? static_cast<const TA*>(g.A) + ar * g.lda : A + ar * lda;
   double* out = g.out + (long long)r * g.ldo;
   for (int c = threadIdx.x; c < g.nc; c += NT) {
     const long long ac = g.cols ? g.cols[c] : (long long)g.col_off + c;

@@ -1,0 +1,72 @@
+"""Batched compression of independent matrices (hss_compress_batched) on the
+GPU, through the C ABI.
+
+* Every matrix of the batch is compressed as hss_compress compresses it
+  alone: the same number of passes and final d, ranks equal except at most
+  a few nodes by one (the batch may take the other QRCP path, whose
+  reductions round differently, so a near-tie can pivot differently), and
+  the same acceptance bound, ||A x - A_HSS x|| <= 10 rtol ||A x||.
+* Mixed sizes, including matrices that are a single leaf, FP64 and FP32
+  storage with BF16x3 sampling, and the handles work afterwards for matvec,
+  factor and solve.
+"""
+import numpy as np
+import pytest
+import torch
+
+import paper_1503_05464_amd as P
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _matrices(count, n_lo, n_hi, seed, dtype, leaf):
+    sets = W.batch_instances(count, n_lo, n_hi, seed, leaf)
+    return [W.device_kernel_matrix("laplace", p, dtype, torch.device("cuda:0")) for p in sets]
+
+
+@pytest.mark.parametrize("dtype,prec,rtol", [(torch.float64, "f64", 1e-6),
+                                             (torch.float32, "bf16x3", 1e-4)])
+def test_batched_equals_single(dtype, prec, rtol):
+    leaf = 64
+    As = _matrices(14, 40, 1500, 11, dtype, leaf)
+    kw = dict(rtol=rtol, d0=32, dd=16, d_max=1024, leaf_size=leaf, p_margin=10, sample_prec=prec)
+    print(f"batched: {len(As)} matrices n={[a.shape[0] for a in As]} prec={prec}", flush=True)
+    hs = P.hss_compress_batched(As, **kw)
+    assert len(hs) == len(As)
+    for A, h in zip(As, hs):
+        n = A.shape[0]
+        h1 = P.hss_compress(A, **kw)
+        s, s1 = P.hss_stats(h), P.hss_stats(h1)
+        assert (s["passes"], s["d_final"], s["converged"]) == (s1["passes"], s1["d_final"], s1["converged"])
+        kr, kc, _, _ = P.hss_ranks(h)
+        kr1, kc1, _, _ = P.hss_ranks(h1)
+        diff = np.flatnonzero((kr != kr1) | (kc != kc1))
+        assert len(diff) <= 2 and np.all(np.abs(kr - kr1) <= 1) and np.all(np.abs(kc - kc1) <= 1)
+        x = torch.from_numpy(np.random.default_rng(n).uniform(-1, 1, (n, 2))).cuda()
+        ref = A.double() @ x
+        err = float(torch.linalg.norm(P.hss_matvec(h, x) - ref) / torch.linalg.norm(ref))
+        assert err <= 10 * rtol, (n, err)
+
+
+def test_batched_handles_factor_and_solve():
+    As = _matrices(6, 50, 700, 3, torch.float64, 64)
+    hs = P.hss_compress_batched(As, rtol=1e-10, d0=32, dd=16, leaf_size=64)
+    for A, h in zip(As, hs):
+        n = A.shape[0]
+        P.hss_factor(h)
+        b = torch.from_numpy(W.normal_rhs(n, 3, n)).cuda()
+        x = P.hss_solve(h, b)
+        r = A @ x - b
+        assert float(torch.linalg.norm(r) / torch.linalg.norm(b)) < 1e-6
+
+
+def test_batched_argument_errors():
+    A = torch.eye(100, dtype=torch.float64, device="cuda")
+    B = torch.eye(80, dtype=torch.float32, device="cuda")
+    with pytest.raises(ValueError):
+        P.hss_compress_batched([A, B])
+    with pytest.raises(P.HSSError) as e:
+        P.hss_compress_batched([A], sample_prec="bf16x3")
+    assert e.value.status == P.HSS_ERR_ARG
+    assert P.hss_compress_batched([]) == []

@@ -237,6 +237,21 @@ def device_kernel_matrix(kind: str, points: np.ndarray, dtype, device, block: in
     return out
 
 
+def batch_instances(count: int, n_lo: int, n_hi: int, seed: int, leaf_size: int):
+    """`count` planar point sets for a batch of independent matrices: sizes
+    N = floor(exp(U(ln n_lo, ln n_hi))), points p ~ U[0,1]^2 x {0}, each set
+    ordered by k-d bisection with `leaf_size`.  One seeded generator draws
+    the sizes, then the point sets in order."""
+    g = _rng(seed)
+    sizes = np.floor(np.exp(g.uniform(math.log(n_lo), math.log(n_hi), size=count))).astype(int)
+    sets = []
+    for n in sizes:
+        p = np.zeros((int(n), 3))
+        p[:, :2] = g.uniform(0.0, 1.0, size=(int(n), 2))
+        sets.append(p[kd_order(p, leaf_size)])
+    return sets
+
+
 # --------------------------------------------------------------------------
 # the named workloads
 # --------------------------------------------------------------------------
@@ -250,6 +265,11 @@ CONFIGS = {
     # 3-D Gaussian kernel, k-d ordered, FP32 storage
     "gauss65536": dict(n=65536, kind="gauss", leaf=256, rtol=1e-6, d0=128, dd=64,
                        storage="f32", point_seed=4, rhs_seed=1),
+    # 512 independent planar 1/(4 pi r) matrices (frontal-matrix stand-ins),
+    # N log-uniform in [256, 4096], FP32 storage, BF16x3 sampling
+    "batched512": dict(count=512, n_lo=256, n_hi=4096, kind="laplace", leaf=64, rtol=1e-4,
+                       d0=64, dd=32, d_max=1024, storage="f32", sample_prec="bf16x3",
+                       point_seed=5),
 }
 
 
