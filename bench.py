@@ -181,7 +181,7 @@ def run_batched(args) -> int:
     bs = [torch.empty_like(x) for x in xs]
     torch.cuda.synchronize()
     kw = dict(rtol=cfg["rtol"], d0=cfg["d0"], dd=cfg["dd"], d_max=cfg["d_max"], leaf_size=cfg["leaf"],
-              p_margin=args.p_margin if args.p_margin is not None else 10, sample_prec=prec)
+              p_margin=args.p_margin if args.p_margin is not None else cfg["p_margin"], sample_prec=prec)
 
     def step():
         hs = P.hss_compress_batched(As, **kw)

@@ -122,7 +122,9 @@ typedef struct {
  *  opts    NULL: hss_default_opts.
  *  *out    receives a new handle (also on HSS_NOT_CONVERGED).
  * Host-synchronous: returns when the handle is complete.  All device work is
- * issued on `stream`.
+ * issued on `stream`.  The random matrices, samples and other buffers of the
+ * compression (about 4 n d_max doubles and more) are freed before the call
+ * returns; the handle keeps only the generators.
  */
 hss_status hss_compress(const void* A, int dtype, long long n, long long lda,
                         const hss_tree* tree, const hss_opts* opts, void* stream,
@@ -147,7 +149,9 @@ hss_status hss_compress(const void* A, int dtype, long long n, long long lda,
  *  status   optional host array: HSS_OK or HSS_NOT_CONVERGED per matrix.
  * Returns HSS_OK if every matrix converged, HSS_NOT_CONVERGED if any did
  * not (all handles valid), or an error, in which case no handle is
- * returned.  Host-synchronous; all work on `stream`.
+ * returned.  Host-synchronous; all work on `stream`.  The handles of one
+ * call keep their generators in one shared device pool, freed when the last
+ * of them is destroyed.
  */
 hss_status hss_compress_batched(int nmat, const void* const* A, int dtype, const long long* n,
                                 const long long* lda, const hss_tree* trees, const hss_opts* opts,

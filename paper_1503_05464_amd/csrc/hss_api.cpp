@@ -64,6 +64,7 @@ double now_ms() {
 namespace hss {
 
 void* Arena::alloc(size_t bytes) {
+  std::lock_guard<std::mutex> lock(mu);
   bytes = round_up(bytes ? bytes : 1, 256);
   if (bytes > left) {
     const size_t chunk = std::max(bytes, this->chunk);
@@ -91,10 +92,10 @@ void Arena::release() {
 void* Scratch::ensure(size_t bytes) {
   bytes = round_up(bytes ? bytes : 1, 256);
   if (bytes <= cap) return p;
+  const size_t want = std::max(bytes, cap * 3 / 2);
   if (p) hipFree(p);
   p = nullptr;
   cap = 0;
-  const size_t want = std::max(bytes, cap * 3 / 2);
   if (hipMalloc(&p, want) != hipSuccess) return nullptr;
   cap = want;
   return p;
@@ -128,9 +129,9 @@ void* Staging::push(const void* src, size_t bytes) {
     // every queued copy must have read its region before it is rewritten
     if (hipStreamSynchronize(stream) != hipSuccess) return nullptr;
     used = 0;
-    if (need > cap) {
+    if (need > cap) {  // first use or growth
       release();
-      if (init(need * 2, stream) != hipSuccess) return nullptr;
+      if (init(std::max(need * 2, (size_t)256 << 10), stream) != hipSuccess) return nullptr;
     }
   }
   std::memcpy(host + used, src, bytes);
@@ -252,9 +253,16 @@ hss_status build_tree(Handle& H, long long n, const hss_tree* tree, int leaf_siz
   return HSS_OK;
 }
 
+// generators: kept with the handle
 template <typename T>
 T* arena_alloc(Handle& H, size_t count) {
-  return static_cast<T*>(H.arena.alloc(count * sizeof(T)));
+  return static_cast<T*>(H.gen->alloc(count * sizeof(T)));
+}
+// compression-only buffers (global R and S, local samples, R_tau): freed
+// when the compression returns
+template <typename T>
+T* work_alloc(Arena& W, size_t count) {
+  return static_cast<T*>(W.alloc(count * sizeof(T)));
 }
 
 // ---------------------------------------------------------------------------
@@ -292,49 +300,91 @@ struct EventTimer {  // HIP events on the compression stream, summed at the end
   }
 };
 
-// Columns c0..c1-1 of R^r, R^c and of the samples of one matrix, on the
-// lead handle's stream and sampling workspace (batches share both).
-hss_status sample_columns(Handle& L, Handle& H, const void* A, long long lda, int c0, int c1,
-                          EventTimer& tm) {
-  const int nc = c1 - c0;
-  if (nc <= 0) return HSS_OK;
+// New sample columns for several matrices: columns c0..c1-1 of R^r, R^c and
+// of S^r, S^c of each, on the lead handle's stream and sampling workspace.
+struct SampleReq {
+  Handle* H;
+  const void* A;
+  long long lda;
+  int c0, c1;
+};
+
+hss_status sample_batch(Handle& L, const std::vector<SampleReq>& reqs, EventTimer& tm) {
+  if (reqs.empty()) return HSS_OK;
   const int ev0 = tm.begin();
-  if (H.opts.R_user_r) {
-    HIPCHK(hipMemcpy2DAsync(H.Rr + c0, H.ldg * 8, H.opts.R_user_r + c0, H.opts.ld_R_user * 8,
-                            (size_t)nc * 8, H.n, hipMemcpyDeviceToDevice, L.stream));
-    HIPCHK(hipMemcpy2DAsync(H.Rc + c0, H.ldg * 8, H.opts.R_user_c + c0, H.opts.ld_R_user * 8,
-                            (size_t)nc * 8, H.n, hipMemcpyDeviceToDevice, L.stream));
-  } else {
-    launch_random_normal(H.opts.seed, 0, H.n, c0, c1, H.Rr + c0, H.ldg, L.stream);
-    launch_random_normal(H.opts.seed, 1, H.n, c0, c1, H.Rc + c0, H.ldg, L.stream);
-  }
-  const int prec = H.opts.sample_prec;
-  if (prec != HSS_SAMPLE_F64) {  // R in the products' precision, used as such from here on
-    launch_round_r(H.Rr, H.ldg, H.n, c0, c1, prec, L.stream);
-    launch_round_r(H.Rc, H.ldg, H.n, c0, c1, prec, L.stream);
-  }
-  const long long wd = prec == HSS_SAMPLE_F64 ? sample_workspace_doubles(H.n, nc)
-                                              : sample_mixed_workspace_doubles(H.n, nc);
-  double* work = nullptr;
-  if (wd > 0) {
-    work = static_cast<double*>(L.work_sample.ensure((size_t)wd * 8));
-    if (!work) return fail(HSS_ERR_ALLOC, "sampling workspace");
+  const int prec = L.opts.sample_prec;
+  for (const SampleReq& q : reqs) {
+    Handle& H = *q.H;
+    const int c0 = q.c0, c1 = q.c1, nc = c1 - c0;
+    if (nc <= 0) continue;
+    if (H.opts.R_user_r) {
+      HIPCHK(hipMemcpy2DAsync(H.Rr + c0, H.ldg * 8, H.opts.R_user_r + c0, H.opts.ld_R_user * 8,
+                              (size_t)nc * 8, H.n, hipMemcpyDeviceToDevice, L.stream));
+      HIPCHK(hipMemcpy2DAsync(H.Rc + c0, H.ldg * 8, H.opts.R_user_c + c0, H.opts.ld_R_user * 8,
+                              (size_t)nc * 8, H.n, hipMemcpyDeviceToDevice, L.stream));
+    } else {
+      launch_random_normal(H.opts.seed, 0, H.n, c0, c1, H.Rr + c0, H.ldg, L.stream);
+      launch_random_normal(H.opts.seed, 1, H.n, c0, c1, H.Rc + c0, H.ldg, L.stream);
+    }
+    if (prec != HSS_SAMPLE_F64) {  // R in the products' precision, used as such from here on
+      launch_round_r(H.Rr, H.ldg, H.n, c0, c1, prec, L.stream);
+      launch_round_r(H.Rc, H.ldg, H.n, c0, c1, prec, L.stream);
+    }
   }
   const int evg = tm.begin();
-  if (prec == HSS_SAMPLE_F64)
-    launch_sample(A, H.dtype, H.n, lda, H.leaf_of, nc, H.Rr + c0, H.Rc + c0, H.ldg, H.Sr + c0,
-                  H.Sc + c0, H.ldg, work, L.stream);
-  else
-    launch_sample_mixed(static_cast<const float*>(A), H.n, lda, H.leaf_of, nc, prec, H.Rr + c0,
-                        H.Rc + c0, H.ldg, H.Sr + c0, H.Sc + c0, H.ldg, work, L.stream);
-  HIPCHK(hipGetLastError());
+  if (prec != HSS_SAMPLE_F64 && reqs.size() > 1) {  // all matrices in one launch per side
+    std::vector<SampleJob> jobs;
+    for (const SampleReq& q : reqs) {
+      const Handle& H = *q.H;
+      if (q.c1 <= q.c0) continue;
+      SampleJob j{};
+      j.A = static_cast<const float*>(q.A);
+      j.lda = q.lda;
+      j.n = H.n;
+      j.leaf_of = H.leaf_of;
+      j.ncols = q.c1 - q.c0;
+      j.Rr = H.Rr + q.c0;
+      j.Rc = H.Rc + q.c0;
+      j.ldr = H.ldg;
+      j.Sr = H.Sr + q.c0;
+      j.Sc = H.Sc + q.c0;
+      j.lds = H.ldg;
+      jobs.push_back(j);
+    }
+    HIPCHK(launch_sample_mixed_grouped(jobs.data(), (int)jobs.size(), prec, L.staging, L.stream));
+    L.n_sgemm += 2;
+  } else {
+    for (const SampleReq& q : reqs) {
+      const Handle& H = *q.H;
+      const int c0 = q.c0, nc = q.c1 - q.c0;
+      if (nc <= 0) continue;
+      const long long wd = prec == HSS_SAMPLE_F64 ? sample_workspace_doubles(H.n, nc)
+                                                  : sample_mixed_workspace_doubles(H.n, nc);
+      double* work = nullptr;
+      if (wd > 0) {
+        work = static_cast<double*>(L.work_sample.ensure((size_t)wd * 8));
+        if (!work) return fail(HSS_ERR_ALLOC, "sampling workspace");
+      }
+      if (prec == HSS_SAMPLE_F64)
+        launch_sample(q.A, H.dtype, H.n, q.lda, H.leaf_of, nc, H.Rr + c0, H.Rc + c0, H.ldg, H.Sr + c0,
+                      H.Sc + c0, H.ldg, work, L.stream);
+      else
+        launch_sample_mixed(static_cast<const float*>(q.A), H.n, q.lda, H.leaf_of, nc, prec, H.Rr + c0,
+                            H.Rc + c0, H.ldg, H.Sr + c0, H.Sc + c0, H.ldg, work, L.stream);
+      HIPCHK(hipGetLastError());
+      L.n_sgemm += 2;
+    }
+  }
   tm.end(evg, 3);
   tm.end(ev0, 0);
-  // two launches (S^r and S^c), each 2 n^2 nc flops; bytes: A once, R read, S written
-  L.n_sgemm += 2;
-  L.sgemm_flops += 4.0 * (double)H.n * (double)H.n * nc;
-  L.sgemm_bytes += 2.0 * ((double)H.n * (double)H.n * (H.dtype == HSS_F32 ? 4 : 8) +
-                          2.0 * (double)H.n * nc * 8);
+  // each product 2 n^2 nc flops; bytes: A once per product, R read, S written
+  for (const SampleReq& q : reqs) {
+    const Handle& H = *q.H;
+    const int nc = q.c1 - q.c0;
+    L.sgemm_flops += 4.0 * (double)H.n * (double)H.n * nc;
+    L.sgemm_bytes += 2.0 * ((double)H.n * (double)H.n * (H.dtype == HSS_F32 ? 4 : 8) +
+                            2.0 * (double)H.n * nc * 8);
+  }
   return HSS_OK;
 }
 
@@ -372,7 +422,7 @@ struct Item {
 // different matrices: every phase is one batched launch over all of them.
 // L (the lead handle) provides the stream, staging buffer, ID workspace and
 // rank readback; all handles of a batch share L's stream.
-hss_status process_items(Handle& L, std::vector<Item>& items, EventTimer& tm) {
+hss_status process_items(Handle& L, Arena& W, std::vector<Item>& items, EventTimer& tm) {
   if (items.empty()) return HSS_OK;
   const int ev_level = tm.begin();
   auto node = [](const Item& it) -> Node& { return it.H->nodes[it.t]; };
@@ -406,8 +456,8 @@ hss_status process_items(Handle& L, std::vector<Item>& items, EventTimer& tm) {
       v.mc = a.kc + b.kc;
       v.B12 = arena_alloc<double>(H, (size_t)a.kr * b.kc);
       v.B21 = arena_alloc<double>(H, (size_t)b.kr * a.kc);
-      v.Sr = arena_alloc<double>(H, (size_t)v.mr * H.ldg);
-      v.Sc = arena_alloc<double>(H, (size_t)v.mc * H.ldg);
+      v.Sr = work_alloc<double>(W, (size_t)v.mr * H.ldg);
+      v.Sc = work_alloc<double>(W, (size_t)v.mc * H.ldg);
       if (!v.B12 || !v.B21 || !v.Sr || !v.Sc) return fail(HSS_ERR_ALLOC, "inner node buffers");
       GatherDesc g{};
       g.A = it.A;
@@ -524,8 +574,8 @@ hss_status process_items(Handle& L, std::vector<Item>& items, EventTimer& tm) {
       }
       v.kr = kr;
       v.kc = kc;
-      v.Rr = arena_alloc<double>(H, (size_t)kc * H.ldg);
-      v.Rc = arena_alloc<double>(H, (size_t)kr * H.ldg);
+      v.Rr = work_alloc<double>(W, (size_t)kc * H.ldg);
+      v.Rc = work_alloc<double>(W, (size_t)kr * H.ldg);
       v.Ir = arena_alloc<int>(H, (size_t)kr);
       v.Ic = arena_alloc<int>(H, (size_t)kc);
       if (!v.Rr || !v.Rc || !v.Ir || !v.Ic) return fail(HSS_ERR_ALLOC, "node R / index buffers");
@@ -633,7 +683,10 @@ hss_status compress_batch(std::vector<Job>& jobs) {
   Handle& L = *jobs[0].H;
   EventTimer tm;
   tm.s = L.stream;
+  Arena W;  // compression-only buffers of the whole batch
+  W.chunk = (size_t)256 << 20;
   std::vector<GatherDesc> single;
+  std::vector<SampleReq> first;
   int maxh = 0;
   for (Job& j : jobs) {
     Handle& H = *j.H;
@@ -655,11 +708,11 @@ hss_status compress_batch(std::vector<Job>& jobs) {
     }
     const int dmax = H.opts.d_max;
     H.ldg = (long long)round_up((size_t)dmax, 8);
-    H.Rr = arena_alloc<double>(H, (size_t)n * H.ldg);
-    H.Rc = arena_alloc<double>(H, (size_t)n * H.ldg);
-    H.Sr = arena_alloc<double>(H, (size_t)n * H.ldg);
-    H.Sc = arena_alloc<double>(H, (size_t)n * H.ldg);
-    H.leaf_of = arena_alloc<int>(H, (size_t)n);
+    H.Rr = work_alloc<double>(W, (size_t)n * H.ldg);
+    H.Rc = work_alloc<double>(W, (size_t)n * H.ldg);
+    H.Sr = work_alloc<double>(W, (size_t)n * H.ldg);
+    H.Sc = work_alloc<double>(W, (size_t)n * H.ldg);
+    H.leaf_of = work_alloc<int>(W, (size_t)n);
     if (!H.Rr || !H.Rc || !H.Sr || !H.Sc || !H.leaf_of)
       return fail(HSS_ERR_ALLOC, "random matrices / samples (n x d_max doubles each)");
     const int nl = (int)H.leaves.size();
@@ -674,7 +727,7 @@ hss_status compress_batch(std::vector<Job>& jobs) {
     launch_leaf_of(nl, dlo, dhi, H.leaf_of, L.stream);
     HIPCHK(hipGetLastError());
     j.d = std::min(H.opts.d0, dmax);
-    CHK(sample_columns(L, H, j.A, j.lda, 0, j.d, tm));
+    first.push_back(SampleReq{&H, j.A, j.lda, 0, j.d});
     H.passes = 0;
     H.converged = true;
     j.ext.assign(nd.size(), 0);
@@ -683,6 +736,7 @@ hss_status compress_batch(std::vector<Job>& jobs) {
   if (!single.empty())
     HIPCHK(launch_gather(single[0].A, L.dtype, single[0].lda, single.data(), (int)single.size(),
                          L.staging, L.stream));
+  CHK(sample_batch(L, first, tm));
   int pass = 0;
   while (true) {
     std::vector<Job*> act;
@@ -720,8 +774,9 @@ hss_status compress_batch(std::vector<Job>& jobs) {
           items.push_back(Item{&H, j->A, j->lda, t, j->d, j->forced, af});
         }
       }
-      CHK(process_items(L, items, tm));
+      CHK(process_items(L, W, items, tm));
     }
+    std::vector<SampleReq> grow;
     for (Job* j : act) {
       Handle& H = *j->H;
       const std::vector<Node>& nd = H.nodes;
@@ -747,9 +802,10 @@ hss_status compress_batch(std::vector<Job>& jobs) {
         continue;
       }
       const int dn = std::min(j->d + H.opts.dd, H.opts.d_max);
-      CHK(sample_columns(L, H, j->A, j->lda, j->d, dn, tm));
+      grow.push_back(SampleReq{&H, j->A, j->lda, j->d, dn});
       j->d = dn;
     }
+    CHK(sample_batch(L, grow, tm));
     if (L.verbose && jobs.size() > 1) {
       int left = 0;
       for (Job& j : jobs) left += j.done ? 0 : 1;
@@ -796,6 +852,13 @@ hss_status compress_batch(std::vector<Job>& jobs) {
   tm.finish(acc);
   HIPCHK(hipStreamSynchronize(L.stream));
   L.staging.reset();
+  W.release();  // the handles keep only their generators
+  for (Job& j : jobs) {
+    Handle& H = *j.H;
+    H.Rr = H.Rc = H.Sr = H.Sc = nullptr;
+    H.leaf_of = nullptr;
+    for (Node& v : H.nodes) v.Sr = v.Sc = v.Rr = v.Rc = nullptr;
+  }
   const double total = now_ms() - t0;
   for (Job& j : jobs) {  // timings are those of the whole batch
     Handle& H = *j.H;
@@ -827,13 +890,10 @@ hss_status new_handle(hss_handle* out, long long n, hipStream_t s, hss_handle_s*
   if (!p) return fail(HSS_ERR_ALLOC, "handle");
   p->h.n = n;
   p->h.stream = s;
-  // device arena chunks sized to the matrix (a batch holds many small handles)
-  p->h.arena.chunk = std::min<size_t>((size_t)64 << 20, std::max<size_t>((size_t)1 << 20, (size_t)n * 4096));
-  // descriptor staging grows on demand (only the lead handle of a batch uses much)
-  if (p->h.staging.init((size_t)256 << 10, s) != hipSuccess) {
-    delete p;
-    return fail(HSS_ERR_ALLOC, "staging buffers");
-  }
+  // generator arena chunks sized to the matrix
+  p->h.gen->chunk = std::min<size_t>((size_t)64 << 20, std::max<size_t>((size_t)1 << 20, (size_t)n * 4096));
+  // descriptor staging is allocated on first use
+  p->h.staging.stream = s;
   *hp = p;
   (void)out;
   return HSS_OK;
@@ -843,7 +903,7 @@ void free_handle(hss_handle_s* p) {
   if (!p) return;
   Handle& H = p->h;
   if (H.stream) hipStreamSynchronize(H.stream);
-  H.arena.release();
+  H.gen.reset();  // frees the arena unless other handles of its batch still hold it
   H.work_id.release();
   H.work_sample.release();
   H.work_mv.release();
@@ -1131,6 +1191,8 @@ hss_status hss_compress_batched(int nmat, const void* const* A, int dtype, const
       H.dtype = dtype;
       H.opts = o;
       H.verbose = v && v[0] && v[0] != '0';
+      if (i == 0) H.gen->chunk = (size_t)64 << 20;
+      else H.gen = hs[0]->h.gen;  // one generator arena for the batch
       st = build_tree(H, n[i], trees ? &trees[i] : nullptr, o.leaf_size);
       jobs[i].H = &H;
       jobs[i].A = A[i];

@@ -2,6 +2,8 @@
 // pointers into the handle's arena), compression bookkeeping and workspaces.
 #pragma once
 
+#include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -18,8 +20,13 @@ struct Arena {
   size_t left = 0;
   size_t total = 0;
   size_t chunk = (size_t)64 << 20;  // minimum chunk size
+  std::mutex mu;                     // handles of one batch may allocate from several threads
   void* alloc(size_t bytes);
   void release();
+  Arena() = default;
+  Arena(const Arena&) = delete;
+  Arena& operator=(const Arena&) = delete;
+  ~Arena() { release(); }
 };
 
 // A growable device buffer reused between launches (freed and reallocated
@@ -72,7 +79,9 @@ struct Handle {
   int height = 0;                        // height of the root
   std::vector<std::vector<int>> levels;  // non-root nodes by height
   std::vector<int> leaves;               // leaves in index order
-  Arena arena;
+  // generators and factors (kept until the handle is destroyed; the handles
+  // of one batch share one arena, freed with the last of them)
+  std::shared_ptr<Arena> gen = std::make_shared<Arena>();
   Scratch work_id, work_sample, work_mv, work_misc;
   Staging staging;
   hipStream_t stream = nullptr;

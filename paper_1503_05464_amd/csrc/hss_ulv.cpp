@@ -176,9 +176,9 @@ hss_status factor_impl(Handle& H, hipStream_t s) {
   if (nd[0].leaf()) {
     const int n = (int)H.n;
     H.root_m = n;
-    H.root_lu = static_cast<double*>(H.arena.alloc((size_t)n * n * 8));
-    H.root_piv = static_cast<int*>(H.arena.alloc((size_t)n * 4));
-    H.root_info = static_cast<int*>(H.arena.alloc(4));
+    H.root_lu = static_cast<double*>(H.gen->alloc((size_t)n * n * 8));
+    H.root_piv = static_cast<int*>(H.gen->alloc((size_t)n * 4));
+    H.root_info = static_cast<int*>(H.gen->alloc(4));
     if (!H.root_lu || !H.root_piv || !H.root_info) return set_error(HSS_ERR_ALLOC, "root LU");
     HIPCHK(hipMemcpyAsync(H.root_lu, nd[0].D, (size_t)n * n * 8, hipMemcpyDeviceToDevice, s));
   } else {
@@ -190,8 +190,8 @@ hss_status factor_impl(Handle& H, hipStream_t s) {
         Node& v = nd[t];
         const int md = md_of(v), r = md - v.kr;
         const long long rows = (long long)r + v.kc + v.kr;
-        v.Z = static_cast<double*>(H.arena.alloc((size_t)std::max(1LL, rows * md) * 8));
-        v.tau = static_cast<double*>(H.arena.alloc((size_t)std::max(1, r) * 8));
+        v.Z = static_cast<double*>(H.gen->alloc((size_t)std::max(1LL, rows * md) * 8));
+        v.tau = static_cast<double*>(H.gen->alloc((size_t)std::max(1, r) * 8));
         if (!v.Z || !v.tau) return set_error(HSS_ERR_ALLOC, "ULV factors");
         if (!v.leaf()) {
           const Node& a = nd[v.left];
@@ -304,9 +304,9 @@ hss_status factor_impl(Handle& H, hipStream_t s) {
     Node& r = nd[0];
     const int m = nd[r.left].kr + nd[r.right].kr;
     H.root_m = m;
-    H.root_lu = static_cast<double*>(H.arena.alloc((size_t)std::max(1, m * m) * 8));
-    H.root_piv = static_cast<int*>(H.arena.alloc((size_t)std::max(1, m) * 4));
-    H.root_info = static_cast<int*>(H.arena.alloc(4));
+    H.root_lu = static_cast<double*>(H.gen->alloc((size_t)std::max(1, m * m) * 8));
+    H.root_piv = static_cast<int*>(H.gen->alloc((size_t)std::max(1, m) * 4));
+    H.root_info = static_cast<int*>(H.gen->alloc(4));
     if (!H.root_lu || !H.root_piv || !H.root_info) return set_error(HSS_ERR_ALLOC, "root LU");
     std::vector<GemmDesc> gd;
     merged_D(H, 0, H.root_lu, gd);

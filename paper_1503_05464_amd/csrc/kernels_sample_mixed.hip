@@ -27,6 +27,7 @@
 // all the product needs.  The output layout of both MFMAs (checked on the
 // device): lane l, register r -> row 4 (l / 16) + r, column l % 16.
 #include <cstdint>
+#include <vector>
 
 #include "hss_internal.h"
 
@@ -167,24 +168,14 @@ __device__ __forceinline__ void store_r(Smem<MODE>& sm, const double (&v)[8]) {
   }
 }
 
+// One 128 x 64 tile of S (rows i0.., columns c0..) over k in [kbeg, kend),
+// written to out (leading dimension ldo).
 template <int MODE, bool TRANS>
-__global__ __launch_bounds__(NT) void sample_mixed_kernel(
-    const float* __restrict__ A, long long lda, int n, const int* __restrict__ leaf_of,
-    const double* __restrict__ R, long long ldr, double* __restrict__ S, long long lds, int ncols,
-    int n_nt, int ksplit, int kchunk, double* __restrict__ work) {
-  __shared__ Smem<MODE> sm;
-
-  const int nblk = gridDim.x;
-  int L = blockIdx.x;
-  if ((nblk & 7) == 0) L = (blockIdx.x & 7) * (nblk >> 3) + (blockIdx.x >> 3);
-  const int nt = L % n_nt;
-  const int rest = L / n_nt;
-  const int ks = rest % ksplit;
-  const int mt = rest / ksplit;
-  const int i0 = mt * BM, c0 = nt * BN;
-  const int kbeg = ks * kchunk;
-  const int kend = min(n, kbeg + kchunk);
-
+__device__ __forceinline__ void sample_tile(Smem<MODE>& sm, const float* __restrict__ A,
+                                            long long lda, int n, const int* __restrict__ leaf_of,
+                                            const double* __restrict__ R, long long ldr, int ncols,
+                                            int i0, int c0, int kbeg, int kend,
+                                            double* __restrict__ out, long long ldo) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wm = wave >> 1, wn = wave & 1;
   const int lr = lane & 15, lk = (lane >> 4) * 8;
@@ -289,12 +280,6 @@ __global__ __launch_bounds__(NT) void sample_mixed_kernel(
     __syncthreads();
   }
 
-  double* out = S;
-  long long ldo = lds;
-  if (ksplit > 1) {
-    out = work + (long long)ks * n * ncols;
-    ldo = ncols;
-  }
 #pragma unroll
   for (int mb = 0; mb < 4; ++mb)
 #pragma unroll
@@ -306,6 +291,62 @@ __global__ __launch_bounds__(NT) void sample_mixed_kernel(
         if (i < n && c < ncols) out[(long long)i * ldo + c] = accd[mb][nb][r];
       }
     }
+}
+
+template <int MODE, bool TRANS>
+__global__ __launch_bounds__(NT) void sample_mixed_kernel(
+    const float* __restrict__ A, long long lda, int n, const int* __restrict__ leaf_of,
+    const double* __restrict__ R, long long ldr, double* __restrict__ S, long long lds, int ncols,
+    int n_nt, int ksplit, int kchunk, double* __restrict__ work) {
+  __shared__ Smem<MODE> sm;
+  // consecutive logical tiles share an XCD
+  const int nblk = gridDim.x;
+  int L = blockIdx.x;
+  if ((nblk & 7) == 0) L = (blockIdx.x & 7) * (nblk >> 3) + (blockIdx.x >> 3);
+  const int nt = L % n_nt;
+  const int rest = L / n_nt;
+  const int ks = rest % ksplit;
+  const int mt = rest / ksplit;
+  const int kbeg = ks * kchunk;
+  double* out = S;
+  long long ldo = lds;
+  if (ksplit > 1) {
+    out = work + (long long)ks * n * ncols;
+    ldo = ncols;
+  }
+  sample_tile<MODE, TRANS>(sm, A, lda, n, leaf_of, R, ldr, ncols, mt * BM, nt * BN, kbeg,
+                           min(n, kbeg + kchunk), out, ldo);
+}
+
+// Many matrices in one launch: descriptor q covers the tiles
+// [tile0, tile0 + n_mt * n_nt) of its product; no split of k.
+struct GroupDesc {
+  const float* A;
+  long long lda;
+  int n, ncols, n_nt;
+  const int* leaf_of;
+  const double* R;
+  long long ldr;
+  double* S;
+  long long lds;
+  long long tile0;
+};
+
+template <int MODE, bool TRANS>
+__global__ __launch_bounds__(NT) void sample_mixed_grouped_kernel(const GroupDesc* __restrict__ g,
+                                                                  int ng) {
+  __shared__ Smem<MODE> sm;
+  const long long b = blockIdx.x;
+  int lo = 0, hi = ng - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (g[mid].tile0 <= b) lo = mid;
+    else hi = mid - 1;
+  }
+  const GroupDesc d = g[lo];
+  const int t = (int)(b - d.tile0);
+  sample_tile<MODE, TRANS>(sm, d.A, d.lda, d.n, d.leaf_of, d.R, d.ldr, d.ncols, (t / d.n_nt) * BM,
+                           (t % d.n_nt) * BN, 0, d.n, d.S, d.lds);
 }
 
 __global__ void reduce_splits_mixed_kernel(const double* __restrict__ work, int ksplit, long long n,
@@ -393,6 +434,47 @@ void launch_sample_mixed(const float* A, long long n, long long lda, const int* 
     if (Sr) run<2, false>(A, lda, n, leaf_of, ncols, Rr, ldr, Sr, lds, work, s);
     if (Sc) run<2, true>(A, lda, n, leaf_of, ncols, Rc, ldr, Sc, lds, work, s);
   }
+}
+
+hipError_t launch_sample_mixed_grouped(const SampleJob* jobs, int njob, int mode, Staging& st,
+                                       hipStream_t s) {
+  if (njob <= 0) return hipSuccess;
+  for (int side = 0; side < 2; ++side) {
+    std::vector<GroupDesc> g;
+    long long tiles = 0;
+    for (int q = 0; q < njob; ++q) {
+      const SampleJob& j = jobs[q];
+      if (j.n <= 0 || j.ncols <= 0) continue;
+      GroupDesc d{};
+      d.A = j.A;
+      d.lda = j.lda;
+      d.n = (int)j.n;
+      d.ncols = j.ncols;
+      d.n_nt = (j.ncols + BN - 1) / BN;
+      d.leaf_of = j.leaf_of;
+      d.R = side == 0 ? j.Rr : j.Rc;
+      d.ldr = j.ldr;
+      d.S = side == 0 ? j.Sr : j.Sc;
+      d.lds = j.lds;
+      d.tile0 = tiles;
+      tiles += (long long)((j.n + BM - 1) / BM) * d.n_nt;
+      g.push_back(d);
+    }
+    if (g.empty()) return hipSuccess;
+    const GroupDesc* dg = static_cast<const GroupDesc*>(st.push(g.data(), g.size() * sizeof(GroupDesc)));
+    if (!dg) return hipErrorOutOfMemory;
+    const int ng = (int)g.size();
+    if (mode == 1) {
+      if (side == 0) hipLaunchKernelGGL((sample_mixed_grouped_kernel<1, false>), dim3((unsigned)tiles), dim3(NT), 0, s, dg, ng);
+      else hipLaunchKernelGGL((sample_mixed_grouped_kernel<1, true>), dim3((unsigned)tiles), dim3(NT), 0, s, dg, ng);
+    } else {
+      if (side == 0) hipLaunchKernelGGL((sample_mixed_grouped_kernel<2, false>), dim3((unsigned)tiles), dim3(NT), 0, s, dg, ng);
+      else hipLaunchKernelGGL((sample_mixed_grouped_kernel<2, true>), dim3((unsigned)tiles), dim3(NT), 0, s, dg, ng);
+    }
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 void launch_round_r(double* R, long long ld, long long n, int col0, int col1, int mode,

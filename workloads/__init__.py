@@ -268,7 +268,7 @@ CONFIGS = {
     # 512 independent planar 1/(4 pi r) matrices (frontal-matrix stand-ins),
     # N log-uniform in [256, 4096], FP32 storage, BF16x3 sampling
     "batched512": dict(count=512, n_lo=256, n_hi=4096, kind="laplace", leaf=64, rtol=1e-4,
-                       d0=64, dd=32, d_max=1024, storage="f32", sample_prec="bf16x3",
+                       d0=64, dd=32, d_max=1024, p_margin=32, storage="f32", sample_prec="bf16x3",
                        point_seed=5),
 }
 
