@@ -292,12 +292,119 @@ def run_batched(args) -> int:
     return 0
 
 
+def run_serve(args) -> int:
+    """The serving workload: requests of compress + ULV factor + solve arrive
+    as a Poisson process at 200 per second (seed 6).  Each request draws its
+    matrix from a pool of 16 pre-assembled matrices -- N log-uniform in
+    [512, 32768], the 2-D log kernel on a perturbed circle or the 3-D
+    Gaussian kernel (k-d ordered) with probability 1/2 each, FP32 storage --
+    and draws rtol in {1e-4, 1e-6} and nrhs in {1..64}; sampling is BF16x3.
+    The first 10 % of the requests are warm-up.  Reports p50/p99 latency from
+    submission to solution and the throughput; `value` is the p50 latency."""
+    import numpy as np
+    import torch
+
+    import paper_1503_05464_amd as P
+    import workloads as W
+
+    nreq = args.serve_requests
+    g = np.random.default_rng(6)
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    pool = []
+    sizes = np.floor(np.exp(g.uniform(np.log(512), np.log(32768), size=16))).astype(int)
+    kinds = g.integers(0, 2, size=16)
+    print(f"[bench] workload serve: assembling a pool of 16 matrices, N = {sorted(sizes.tolist())}",
+          file=sys.stderr, flush=True)
+    for q, (n, k) in enumerate(zip(sizes, kinds)):
+        if k == 0:
+            pts = W.circle_points(int(n), 600 + q)
+            pool.append(W.device_kernel_matrix("log", pts, torch.float32, dev))
+        else:
+            pts = W.cube_points(int(n), 600 + q)
+            pool.append(W.device_kernel_matrix("gauss", pts[W.kd_order(pts, 128)], torch.float32, dev))
+    pick = g.integers(0, 16, size=nreq)
+    rtols = g.choice([1e-4, 1e-6], size=nreq)
+    nrhs = g.integers(1, 65, size=nreq)
+    gaps = g.exponential(1.0 / 200.0, size=nreq)
+    rhs = [torch.from_numpy(W.normal_rhs(int(pool[q].shape[0]), int(k), 6000 + i)).to(dev)
+           for i, (q, k) in enumerate(zip(pick, nrhs))]
+    torch.cuda.synchronize()
+    srv = P.HSSServer(max_batch=32, workers=4)
+    kw0 = dict(d0=64, dd=32, d_max=1024, leaf_size=128, p_margin=32, sample_prec="bf16x3")
+    print(f"[bench] serving {nreq} requests at 200/s", file=sys.stderr, flush=True)
+    t_start = time.perf_counter()
+    t_next = t_start
+    tickets = []
+    for i in range(nreq):
+        t_next += gaps[i]
+        while time.perf_counter() < t_next:
+            time.sleep(max(0.0, min(0.001, t_next - time.perf_counter())))
+        tickets.append(srv.submit(pool[pick[i]], rhs[i], rtol=float(rtols[i]), **kw0))
+    infos = []
+    for i, t in enumerate(tickets):
+        infos.append(srv.wait(t)[1])
+        if (i + 1) % max(1, nreq // 10) == 0:
+            print(f"[bench] {i + 1} of {nreq} requests done", file=sys.stderr, flush=True)
+    t_end = time.perf_counter()
+    srv.close()
+    warm = nreq // 10
+    lat = np.array([x["t_done"] - x["t_submit"] for x in infos[warm:]])
+    bad = sum(1 for x in infos if x["status"] not in (P.HSS_OK, P.HSS_NOT_CONVERGED))
+    t_first = min(x["t_submit"] for x in infos[warm:])
+    t_last = max(x["t_done"] for x in infos[warm:])
+    thr = (nreq - warm) / max(1e-9, t_last - t_first)
+    # correctness spot check: the last request of each pool matrix solves its system
+    worst = 0.0
+    for q in sorted(set(pick.tolist()))[:4]:
+        i = int(np.flatnonzero(pick == q)[-1])
+        A = pool[q].double()
+        h = P.hss_compress(pool[q], rtol=float(rtols[i]), **kw0)
+        P.hss_factor(h)
+        x = P.hss_solve(h, rhs[i])
+        r = A @ x - rhs[i]
+        worst = max(worst, float(torch.linalg.norm(r) / torch.linalg.norm(rhs[i])))
+        del A
+    out = {
+        "metric": "HSS serving latency s (compress + ULV factor + solve per request), p50; p99 alongside",
+        "value": round(float(np.percentile(lat, 50)), 4),
+        "unit": "s",
+        "n_gpus": 1,
+        "steps": nreq - warm,
+        "warmup": warm,
+        "ms_per_step": round(1e3 / thr, 2),
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16x3 sampling, f64 ID and ULV",
+        "data": "synthetic",
+        "config": {
+            "workload": "serve: Poisson arrivals at 200/s (seed 6), pool of 16 FP32 matrices N log-uniform "
+                        "in [512, 32768] (log kernel on a circle or Gaussian kernel in 3-D), rtol in "
+                        "{1e-4, 1e-6}, nrhs in {1..64}, leaf 128, d0 64, dd 32, p_margin 32, BF16X3 sampling",
+            "requests": nreq, "workers": 4, "max_batch": 32, "hbm_budget": "80% of device memory",
+        },
+        "latency_s": {"p50": round(float(np.percentile(lat, 50)), 4), "p90": round(float(np.percentile(lat, 90)), 4),
+                      "p99": round(float(np.percentile(lat, 99)), 4), "max": round(float(lat.max()), 4)},
+        "throughput_req_s": round(thr, 2),
+        "offered_req_s": round(nreq / (t_end - t_start), 2),
+        "mean_batch": round(float(np.mean([x["batch_size"] for x in infos])), 2),
+        "failed": bad,
+        "spot_check_rel_residual": worst,
+        "roofline": None,
+        "cpu_baseline": None,
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="gauss65536", choices=sorted(WORKLOADS) + ["batched512"])
+    ap.add_argument("--workload", default="gauss65536", choices=sorted(WORKLOADS) + ["batched512", "serve"])
+    ap.add_argument("--serve-requests", type=int, default=400, help="requests of the serve workload")
     ap.add_argument("--rtol", type=float, default=None)
     ap.add_argument("--p-margin", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -312,6 +419,8 @@ def main() -> int:
         return 2
     if args.workload == "batched512":
         return run_batched(args)
+    if args.workload == "serve":
+        return run_serve(args)
 
     import numpy as np
     import torch

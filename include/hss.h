@@ -242,6 +242,70 @@ void hss_destroy(hss_handle h);
 const char* hss_last_error(void);
 
 /* ---------------------------------------------------------------------
+ * Serving: requests of compress (Alg. 1, adaptive sampling of Sec. 3.3) +
+ * ULV factorization (Alg. 3) + solve (Alg. 4) that arrive over time.
+ *
+ * Requests wait in arrival order.  Each worker thread of the server owns a
+ * HIP stream; a free worker admits the oldest waiting request and, behind
+ * it, the waiting requests with the same storage type and options, while
+ * their estimated device footprint (about 8 n d_max doubles of compression
+ * buffers plus the factors) fits the budget and the batch holds at most
+ * max_batch requests; it compresses them with one hss_compress_batched
+ * call, factors and solves each, then frees their footprint.  Requests that
+ * arrive meanwhile are admitted by the next free worker as memory frees up,
+ * so their work overlaps on the device with the batches already running.
+ * A request whose footprint alone exceeds the budget runs when nothing else
+ * is admitted.  Each result is computed exactly as the same calls made
+ * alone would compute it, up to the rounding of a batch's QRCP path choice.
+ * ------------------------------------------------------------------- */
+typedef struct hss_server_s* hss_server;
+
+typedef struct {
+  long long hbm_budget; /* bytes of device memory admitted requests may hold;
+                           0: 80 % of the device's memory */
+  int max_batch;        /* requests compressed together (default 32) */
+  int workers;          /* worker threads / streams, 1..16 (default 2) */
+} hss_server_opts;
+
+typedef struct {
+  int status;       /* HSS_OK, HSS_NOT_CONVERGED, or the error of the request */
+  int batch_size;   /* requests compressed in the same batch */
+  int d_final;      /* random vectors used */
+  int max_rank;     /* largest generator rank */
+  double t_submit;  /* seconds since the server started: submitted, */
+  double t_start;   /* admitted, */
+  double t_done;    /* solved (results in x) */
+} hss_request_info;
+
+/* Fills *o with hbm_budget 0 (80 % of device memory), max_batch 32,
+ * workers 2. */
+void hss_server_default_opts(hss_server_opts* o);
+
+/* Starts the worker threads.  opts NULL: defaults. */
+hss_status hss_server_create(const hss_server_opts* opts, hss_server* out);
+
+/*
+ * Queues one request: compress A (DEVICE n x n row-major, leading dimension
+ * lda, storage dtype; opts as in hss_compress, NULL: defaults, no user
+ * random matrices), factor, and solve A_HSS x = b for nrhs columns (b, x:
+ * DEVICE n x nrhs with leading dimensions ldb, ldx; nrhs may be 0).  A and b
+ * must stay valid and unchanged, and x untouched, until hss_server_wait on
+ * *ticket returns.  Returns at once.
+ */
+hss_status hss_server_submit(hss_server s, const void* A, int dtype, long long n, long long lda,
+                             const hss_opts* opts, int nrhs, const double* b, long long ldb,
+                             double* x, long long ldx, long long* ticket);
+
+/*
+ * Blocks until the request is done, fills *info (may be NULL) and forgets
+ * the ticket.  Returns the request's status.
+ */
+hss_status hss_server_wait(hss_server s, long long ticket, hss_request_info* info);
+
+/* Finishes every queued request, stops the workers and frees the server. */
+void hss_server_destroy(hss_server s);
+
+/* ---------------------------------------------------------------------
  * Building blocks of hss_compress, exported for parity tests.
  * ------------------------------------------------------------------- */
 

@@ -34,7 +34,18 @@ EXPORTED = [
     "hss_solve", "hss_stats",
     "hss_ranks", "hss_export_node", "hss_import", "hss_destroy", "hss_last_error",
     "hss_random_normal", "hss_sample", "hss_id_batched",
+    "hss_server_default_opts", "hss_server_create", "hss_server_submit", "hss_server_wait",
+    "hss_server_destroy",
 ]
+
+
+class hss_server_opts(C.Structure):
+    _fields_ = [("hbm_budget", C.c_longlong), ("max_batch", C.c_int), ("workers", C.c_int)]
+
+
+class hss_request_info(C.Structure):
+    _fields_ = [("status", C.c_int), ("batch_size", C.c_int), ("d_final", C.c_int), ("max_rank", C.c_int),
+                ("t_submit", C.c_double), ("t_start", C.c_double), ("t_done", C.c_double)]
 
 
 class HSSError(RuntimeError):
@@ -92,6 +103,14 @@ def lib() -> C.CDLL:
         L.hss_compress_batched.argtypes = [i, vp, i, vp, vp, C.POINTER(hss_tree), C.POINTER(hss_opts),
                                            vp, vp, vp]
         L.hss_matvec.argtypes = [vp, i, vp, ll, vp, ll, vp]
+        L.hss_server_default_opts.argtypes = [C.POINTER(hss_server_opts)]
+        L.hss_server_default_opts.restype = None
+        L.hss_server_create.argtypes = [C.POINTER(hss_server_opts), C.POINTER(vp)]
+        L.hss_server_submit.argtypes = [vp, vp, i, ll, ll, C.POINTER(hss_opts), i, vp, ll, vp, ll,
+                                        C.POINTER(C.c_longlong)]
+        L.hss_server_wait.argtypes = [vp, C.c_longlong, C.POINTER(hss_request_info)]
+        L.hss_server_destroy.argtypes = [vp]
+        L.hss_server_destroy.restype = None
         L.hss_factor.argtypes = [vp, vp]
         L.hss_solve.argtypes = [vp, i, vp, ll, vp, ll, vp]
         L.hss_stats.argtypes = [vp, C.POINTER(hss_stats_t)]
@@ -104,7 +123,8 @@ def lib() -> C.CDLL:
         L.hss_sample.argtypes = [vp, i, i, ll, ll, vp, i, vp, vp, ll, vp, vp, ll, vp]
         L.hss_id_batched.argtypes = [i, vp, vp, vp, vp, d, vp, vp, vp, vp]
         for f in EXPORTED:
-            if f not in ("hss_default_opts", "hss_destroy", "hss_last_error"):
+            if f not in ("hss_default_opts", "hss_destroy", "hss_last_error", "hss_server_default_opts",
+                         "hss_server_destroy"):
                 getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -405,3 +425,86 @@ def hss_id_batched(Ys, rtol: float, stream=None):
         kk, mm = int(k[q]), int(m[q])
         out.append((kk, perms[q].cpu().numpy(), es[q][: (mm - kk) * kk].reshape(mm - kk, kk).cpu().numpy()))
     return out
+
+
+class HSSServer:
+    """The serving loop of the C ABI (hss_server_*): requests of compress +
+    ULV factor + solve, admitted by a device-memory budget and batched with
+    the compatible requests waiting at the time, on several streams."""
+
+    def __init__(self, hbm_budget: int = 0, max_batch: int = 32, workers: int = 2):
+        o = hss_server_opts()
+        lib().hss_server_default_opts(C.byref(o))
+        o.hbm_budget, o.max_batch, o.workers = int(hbm_budget), int(max_batch), int(workers)
+        self._ptr = C.c_void_p()
+        _check(lib().hss_server_create(C.byref(o), C.byref(self._ptr)))
+        self._keep = {}
+
+    def submit(self, A, b, x=None, *, rtol=1e-6, d0=64, dd=32, d_max=4096, p_margin=10, seed=0,
+               leaf_size=64, sample_prec="f64") -> int:
+        """Queue A (square CUDA float32/float64) and right-hand sides b (CUDA
+        float64, n or n x nrhs); returns a ticket.  x (optional output,
+        same shape as b) is allocated when not given."""
+        import torch
+
+        dt = {torch.float64: HSS_F64, torch.float32: HSS_F32}.get(A.dtype)
+        if dt is None or A.dim() != 2 or A.shape[0] != A.shape[1] or A.stride(1) != 1 or not A.is_cuda:
+            raise ValueError("A must be a square CUDA float32/float64 matrix with unit column stride")
+        b2 = b.reshape(-1, 1) if b.dim() == 1 else b
+        if b2.dtype != torch.float64 or b2.stride(1) != 1 or b2.shape[0] != A.shape[0]:
+            raise ValueError("b must be float64, n x nrhs with unit column stride")
+        if x is None:
+            x = torch.empty_like(b)
+        x2 = x.reshape(-1, 1) if x.dim() == 1 else x
+        o = hss_default_opts()
+        o.rtol, o.d0, o.dd, o.d_max, o.p_margin = float(rtol), int(d0), int(dd), int(d_max), int(p_margin)
+        o.seed, o.leaf_size, o.sample_prec = int(seed), int(leaf_size), _PREC[sample_prec]
+        t = C.c_longlong()
+        torch.cuda.current_stream().synchronize()  # A and b are read from the server's streams
+        _check(lib().hss_server_submit(self._ptr, _ptr(A), dt, A.shape[0], A.stride(0), C.byref(o),
+                                       b2.shape[1], _ptr(b2), b2.stride(0), _ptr(x2), x2.stride(0),
+                                       C.byref(t)))
+        self._keep[t.value] = (A, b, x)
+        return t.value
+
+    def wait(self, ticket: int):
+        """Blocks until the request is solved; returns (x, info dict)."""
+        info = hss_request_info()
+        st = lib().hss_server_wait(self._ptr, int(ticket), C.byref(info))
+        A, b, x = self._keep.pop(ticket)
+        _check(st, (HSS_OK, HSS_NOT_CONVERGED))
+        return x, {f: getattr(info, f) for f, _ in hss_request_info._fields_}
+
+    def close(self):
+        if self._ptr:
+            lib().hss_server_destroy(self._ptr)
+            self._ptr = C.c_void_p()
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def hss_server_default_opts() -> hss_server_opts:
+    o = hss_server_opts()
+    lib().hss_server_default_opts(C.byref(o))
+    return o
+
+
+def hss_server_create(hbm_budget: int = 0, max_batch: int = 32, workers: int = 2) -> HSSServer:
+    return HSSServer(hbm_budget, max_batch, workers)
+
+
+def hss_server_submit(server: HSSServer, A, b, x=None, **kw) -> int:
+    return server.submit(A, b, x, **kw)
+
+
+def hss_server_wait(server: HSSServer, ticket: int):
+    return server.wait(ticket)
+
+
+def hss_server_destroy(server: HSSServer) -> None:
+    server.close()

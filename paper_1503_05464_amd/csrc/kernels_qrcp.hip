@@ -36,6 +36,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "hss_internal.h"
@@ -956,6 +957,12 @@ static hipError_t run_persistent(std::vector<DevProb>& h, const std::vector<int>
       return hipSuccess;
     }
   }
+  // one persistent grid on the device at a time: two of them started from
+  // different streams could each hold part of the device and wait for the
+  // rest (until the bounded wait gives up), so launch and completion happen
+  // under a process-wide lock
+  static std::mutex persist_mu;
+  std::lock_guard<std::mutex> lock(persist_mu);
   std::vector<int> done;
   size_t i0 = 0;
   while (i0 < cand.size()) {
