@@ -468,11 +468,14 @@ class HSSServer:
         return t.value
 
     def wait(self, ticket: int):
-        """Blocks until the request is solved; returns (x, info dict)."""
+        """Blocks until the request is done; returns (x, info dict).  A
+        request that failed is reported by info["status"] (x then holds no
+        solution); an unknown ticket raises HSSError."""
+        if ticket not in self._keep:
+            _check(lib().hss_server_wait(self._ptr, int(ticket), None))
         info = hss_request_info()
-        st = lib().hss_server_wait(self._ptr, int(ticket), C.byref(info))
+        lib().hss_server_wait(self._ptr, int(ticket), C.byref(info))
         A, b, x = self._keep.pop(ticket)
-        _check(st, (HSS_OK, HSS_NOT_CONVERGED))
         return x, {f: getattr(info, f) for f, _ in hss_request_info._fields_}
 
     def close(self):

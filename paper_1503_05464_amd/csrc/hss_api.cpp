@@ -131,7 +131,7 @@ void* Staging::push(const void* src, size_t bytes) {
     used = 0;
     if (need > cap) {  // first use or growth
       release();
-      if (init(std::max(need * 2, (size_t)256 << 10), stream) != hipSuccess) return nullptr;
+      if (init(std::max(need * 2, (size_t)1 << 20), stream) != hipSuccess) return nullptr;
     }
   }
   std::memcpy(host + used, src, bytes);
@@ -140,6 +140,19 @@ void* Staging::push(const void* src, size_t bytes) {
   void* r = dev + used;
   used += need;
   return r;
+}
+
+bool Staging::reserve(std::initializer_list<size_t> sizes) {
+  size_t total = 0;
+  for (size_t b : sizes) total += round_up(b ? b : 1, 256);
+  if (used + total <= cap) return true;
+  if (hipStreamSynchronize(stream) != hipSuccess) return false;
+  used = 0;
+  if (total > cap) {
+    release();
+    if (init(std::max(total * 2, (size_t)1 << 20), stream) != hipSuccess) return false;
+  }
+  return true;
 }
 
 long long Handle::generator_bytes() const {
@@ -721,6 +734,7 @@ hss_status compress_batch(std::vector<Job>& jobs) {
       lo[q] = nd[H.leaves[q]].lo;
       hi[q] = nd[H.leaves[q]].hi;
     }
+    if (!L.staging.reserve({lo.size() * 4, hi.size() * 4})) return fail(HSS_ERR_HIP, "staging");
     int* dlo = static_cast<int*>(L.staging.push(lo.data(), lo.size() * 4));
     int* dhi = static_cast<int*>(L.staging.push(hi.data(), hi.size() * 4));
     if (!dlo || !dhi) return fail(HSS_ERR_HIP, "staging");

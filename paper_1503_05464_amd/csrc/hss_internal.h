@@ -2,6 +2,8 @@
 // kernels of the randomized HSS library (gfx950).
 #pragma once
 
+#include <initializer_list>
+
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -22,8 +24,15 @@ struct Staging {
   hipStream_t stream = nullptr;
   hipError_t init(size_t bytes, hipStream_t s);
   void release();
-  // returns the device address of the copied table, or nullptr on failure
+  // Returns the device address of the copied table, or nullptr on failure.
+  // A push that does not fit waits for the stream and starts over at the
+  // beginning of the buffer (or in a larger one), so tables pushed earlier
+  // are only safe if their kernels were launched before that push; tables
+  // that must stay valid together are reserved first.
   void* push(const void* src, size_t bytes);
+  // Room for pushes of these sizes that stay valid together: any wrap or
+  // growth happens here, before the first of them.  False on failure.
+  bool reserve(std::initializer_list<size_t> sizes);
   void reset() { used = 0; }
 };
 

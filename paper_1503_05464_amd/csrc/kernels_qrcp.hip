@@ -985,6 +985,7 @@ static hipError_t run_persistent(std::vector<DevProb>& h, const std::vector<int>
     }
     i0 = i1;
     if (batch.empty()) continue;
+    if (!st.reserve({sizeof(DevProb) * h.size(), wgp.size() * 4})) return hipErrorOutOfMemory;
     const DevProb* dprobs = static_cast<const DevProb*>(st.push(h.data(), sizeof(DevProb) * h.size()));
     const int* dwg = static_cast<const int*>(st.push(wgp.data(), wgp.size() * 4));
     if (!dprobs || !dwg) return hipErrorOutOfMemory;
@@ -1076,6 +1077,15 @@ hipError_t launch_id_factor(IdProblem* probs, int nprob, double rtol, void* work
     int steps = dp.kmax;
     if (p.kfail >= 0 && p.m > p.d) steps = std::min(steps, p.kfail + 2);
     smax = std::max(smax, steps);
+  }
+  // every table of the launches below stays valid until the last of them
+  static_assert(kSmallClasses == 10, "one reserved size per class");
+  {
+    size_t sm[kSmallClasses];
+    for (int c = 0; c < kSmallClasses; ++c) sm[c] = small[c].size() * 4;
+    if (!st.reserve({sizeof(DevProb) * nprob, sm[0], sm[1], sm[2], sm[3], sm[4], sm[5], sm[6], sm[7],
+                     sm[8], sm[9], wg_prob.size() * 4}))
+      return hipErrorOutOfMemory;
   }
   const DevProb* dprobs = static_cast<const DevProb*>(st.push(h.data(), sizeof(DevProb) * nprob));
   if (!dprobs) return hipErrorOutOfMemory;
@@ -1178,6 +1188,7 @@ hipError_t launch_id_finish(const IdProblem* probs, int nprob, const int* k_host
     off += probs[q].m;
     aoff += h[q].kmax;
   }
+  if (!st.reserve({sizeof(DevProb) * nprob, (size_t)nsel * 4})) return hipErrorOutOfMemory;
   const DevProb* dprobs = static_cast<const DevProb*>(st.push(h.data(), sizeof(DevProb) * nprob));
   const int* dsel = static_cast<const int*>(st.push(sel, (size_t)nsel * 4));
   if (!dprobs || !dsel) return hipErrorOutOfMemory;
@@ -1285,6 +1296,7 @@ hipError_t launch_qr_reflectors(const IdProblem* probs, int nprob, void* work, S
       for (int i = 0; i < h[q].kmax; ++i) rows.push_back(RefRow{q, i});
   }
   if (rows.empty()) return hipSuccess;
+  if (!st.reserve({sizeof(DevProb) * nprob, rows.size() * sizeof(RefRow)})) return hipErrorOutOfMemory;
   const DevProb* dprobs = static_cast<const DevProb*>(st.push(h.data(), sizeof(DevProb) * nprob));
   const RefRow* drows = static_cast<const RefRow*>(st.push(rows.data(), rows.size() * sizeof(RefRow)));
   if (!dprobs || !drows) return hipErrorOutOfMemory;
