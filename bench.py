@@ -344,6 +344,7 @@ def run_serve(args) -> int:
         while time.perf_counter() < t_next:
             time.sleep(max(0.0, min(0.001, t_next - time.perf_counter())))
         tickets.append(srv.submit(pool[pick[i]], rhs[i], rtol=float(rtols[i]), **kw0))
+    t_submitted = time.perf_counter()
     infos = []
     for i, t in enumerate(tickets):
         infos.append(srv.wait(t)[1])
@@ -396,7 +397,7 @@ def run_serve(args) -> int:
         "latency_s": {"p50": round(float(np.percentile(lat, 50)), 4), "p90": round(float(np.percentile(lat, 90)), 4),
                       "p99": round(float(np.percentile(lat, 99)), 4), "max": round(float(lat.max()), 4)},
         "throughput_req_s": round(thr, 2),
-        "offered_req_s": round(nreq / (t_end - t_start), 2),
+        "offered_req_s": round(nreq / (t_submitted - t_start), 2),
         "mean_batch": round(float(np.mean([x["batch_size"] for x in infos])), 2),
         "failed": bad,
         "spot_check_backward_error": worst,

@@ -288,13 +288,14 @@ hss_status hss_server_create(const hss_server_opts* opts, hss_server* out);
  * Queues one request: compress A (DEVICE n x n row-major, leading dimension
  * lda, storage dtype; opts as in hss_compress, NULL: defaults, no user
  * random matrices), factor, and solve A_HSS x = b for nrhs columns (b, x:
- * DEVICE n x nrhs with leading dimensions ldb, ldx; nrhs may be 0).  A and b
- * must stay valid and unchanged, and x untouched, until hss_server_wait on
- * *ticket returns.  Returns at once.
+ * DEVICE n x nrhs with leading dimensions ldb, ldx; nrhs may be 0).  The
+ * server reads A and b after the work queued so far on `stream` (the
+ * stream that wrote them).  A and b must stay valid and unchanged, and x
+ * untouched, until hss_server_wait on *ticket returns.  Returns at once.
  */
 hss_status hss_server_submit(hss_server s, const void* A, int dtype, long long n, long long lda,
                              const hss_opts* opts, int nrhs, const double* b, long long ldb,
-                             double* x, long long ldx, long long* ticket);
+                             double* x, long long ldx, void* stream, long long* ticket);
 
 /*
  * Blocks until the request is done, fills *info (may be NULL) and forgets

@@ -106,7 +106,7 @@ def lib() -> C.CDLL:
         L.hss_server_default_opts.argtypes = [C.POINTER(hss_server_opts)]
         L.hss_server_default_opts.restype = None
         L.hss_server_create.argtypes = [C.POINTER(hss_server_opts), C.POINTER(vp)]
-        L.hss_server_submit.argtypes = [vp, vp, i, ll, ll, C.POINTER(hss_opts), i, vp, ll, vp, ll,
+        L.hss_server_submit.argtypes = [vp, vp, i, ll, ll, C.POINTER(hss_opts), i, vp, ll, vp, ll, vp,
                                         C.POINTER(C.c_longlong)]
         L.hss_server_wait.argtypes = [vp, C.c_longlong, C.POINTER(hss_request_info)]
         L.hss_server_destroy.argtypes = [vp]
@@ -460,10 +460,10 @@ class HSSServer:
         o.rtol, o.d0, o.dd, o.d_max, o.p_margin = float(rtol), int(d0), int(dd), int(d_max), int(p_margin)
         o.seed, o.leaf_size, o.sample_prec = int(seed), int(leaf_size), _PREC[sample_prec]
         t = C.c_longlong()
-        torch.cuda.current_stream().synchronize()  # A and b are read from the server's streams
+        # the server reads A and b after the work queued so far on the current stream
         _check(lib().hss_server_submit(self._ptr, _ptr(A), dt, A.shape[0], A.stride(0), C.byref(o),
                                        b2.shape[1], _ptr(b2), b2.stride(0), _ptr(x2), x2.stride(0),
-                                       C.byref(t)))
+                                       _stream(None), C.byref(t)))
         self._keep[t.value] = (A, b, x)
         return t.value
 

@@ -63,13 +63,42 @@ double now_ms() {
 // ---------------------------------------------------------------------------
 namespace hss {
 
+namespace {
+std::once_flag g_pool_once;
+}
+
+void* pool_alloc(size_t bytes, hipStream_t s) {
+  // keep up to a quarter of the device's memory cached in the pool between
+  // frees instead of returning it at every synchronization
+  std::call_once(g_pool_once, [] {
+    int dev = 0;
+    hipMemPool_t pool;
+    size_t fr = 0, tot = 0;
+    if (hipGetDevice(&dev) == hipSuccess && hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess &&
+        hipMemGetInfo(&fr, &tot) == hipSuccess) {
+      uint64_t thr = tot / 4;
+      hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
+    }
+  });
+  void* p = nullptr;
+  if (hipMallocAsync(&p, bytes, s) != hipSuccess) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  return p;
+}
+
+void pool_free(void* p, hipStream_t s) {
+  if (p) hipFreeAsync(p, s);
+}
+
 void* Arena::alloc(size_t bytes) {
   std::lock_guard<std::mutex> lock(mu);
   bytes = round_up(bytes ? bytes : 1, 256);
   if (bytes > left) {
     const size_t chunk = std::max(bytes, this->chunk);
-    void* p = nullptr;
-    if (hipMalloc(&p, chunk) != hipSuccess) return nullptr;
+    void* p = pool_alloc(chunk, stream);
+    if (!p) return nullptr;
     chunks.push_back(p);
     cur = static_cast<char*>(p);
     left = chunk;
@@ -82,43 +111,96 @@ void* Arena::alloc(size_t bytes) {
 }
 
 void Arena::release() {
-  for (void* p : chunks) hipFree(p);
+  for (void* p : chunks) pool_free(p, stream);
   chunks.clear();
   cur = nullptr;
   left = 0;
   total = 0;
 }
 
-void* Scratch::ensure(size_t bytes) {
+void* Scratch::ensure(size_t bytes, hipStream_t s) {
   bytes = round_up(bytes ? bytes : 1, 256);
-  if (bytes <= cap) return p;
+  if (bytes <= cap) {
+    if (s != last && p) {  // first use on another stream: wait for the previous one
+      hipEvent_t ev;
+      if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) == hipSuccess) {
+        hipEventRecord(ev, last);
+        hipStreamWaitEvent(s, ev, 0);
+        hipEventDestroy(ev);
+      }
+    }
+    last = s;
+    return p;
+  }
   const size_t want = std::max(bytes, cap * 3 / 2);
-  if (p) hipFree(p);
+  if (p) pool_free(p, last);
   p = nullptr;
   cap = 0;
-  if (hipMalloc(&p, want) != hipSuccess) return nullptr;
+  last = s;
+  p = pool_alloc(want, s);
+  if (!p) return nullptr;
   cap = want;
   return p;
 }
 
 void Scratch::release() {
-  if (p) hipFree(p);
+  pool_free(p, last);
   p = nullptr;
   cap = 0;
 }
 
+namespace {
+// Pinned host blocks of the staging buffers, kept for reuse (power-of-two
+// sizes), so that handles created and destroyed in a loop do not allocate
+// and free pinned memory each time.
+std::mutex g_pin_mu;
+std::vector<std::pair<size_t, char*>> g_pin_free;
+
+char* pinned_get(size_t bytes) {
+  {
+    std::lock_guard<std::mutex> lk(g_pin_mu);
+    for (size_t q = 0; q < g_pin_free.size(); ++q)
+      if (g_pin_free[q].first == bytes) {
+        char* p = g_pin_free[q].second;
+        g_pin_free.erase(g_pin_free.begin() + q);
+        return p;
+      }
+  }
+  char* p = nullptr;
+  if (hipHostMalloc(reinterpret_cast<void**>(&p), bytes, hipHostMallocDefault) != hipSuccess) return nullptr;
+  return p;
+}
+
+void pinned_put(char* p, size_t bytes) {
+  if (!p) return;
+  {
+    std::lock_guard<std::mutex> lk(g_pin_mu);
+    if (g_pin_free.size() < 64) {
+      g_pin_free.emplace_back(bytes, p);
+      return;
+    }
+  }
+  hipHostFree(p);
+}
+}  // namespace
+
 hipError_t Staging::init(size_t bytes, hipStream_t s) {
+  size_t b = (size_t)1 << 20;
+  while (b < bytes) b <<= 1;
   stream = s;
-  cap = bytes;
+  cap = b;
   used = 0;
-  hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&host), bytes, hipHostMallocDefault);
-  if (e != hipSuccess) return e;
-  return hipMalloc(reinterpret_cast<void**>(&dev), bytes);
+  host = pinned_get(b);
+  if (!host) return hipErrorOutOfMemory;
+  dev = static_cast<char*>(pool_alloc(b, s));
+  return dev ? hipSuccess : hipErrorOutOfMemory;
 }
 
 void Staging::release() {
-  if (host) hipHostFree(host);
-  if (dev) hipFree(dev);
+  // queued copies may still read the pinned block: it is reused only after them
+  if (host && stream_used) hipStreamSynchronize(stream);
+  pinned_put(host, cap);
+  pool_free(dev, stream);
   host = dev = nullptr;
   cap = used = 0;
 }
@@ -135,6 +217,7 @@ void* Staging::push(const void* src, size_t bytes) {
     }
   }
   std::memcpy(host + used, src, bytes);
+  stream_used = true;
   if (hipMemcpyAsync(dev + used, host + used, bytes, hipMemcpyHostToDevice, stream) != hipSuccess)
     return nullptr;
   void* r = dev + used;
@@ -375,7 +458,7 @@ hss_status sample_batch(Handle& L, const std::vector<SampleReq>& reqs, EventTime
                                                   : sample_mixed_workspace_doubles(H.n, nc);
       double* work = nullptr;
       if (wd > 0) {
-        work = static_cast<double*>(L.work_sample.ensure((size_t)wd * 8));
+        work = static_cast<double*>(L.work_sample.ensure((size_t)wd * 8, L.stream));
         if (!work) return fail(HSS_ERR_ALLOC, "sampling workspace");
       }
       if (prec == HSS_SAMPLE_F64)
@@ -560,7 +643,7 @@ hss_status process_items(Handle& L, Arena& W, std::vector<Item>& items, EventTim
       p.kfail = (it.forced || it.d - pm < 0) ? -1 : it.d - pm;
     }
     const size_t wb = id_workspace_bytes(pr.data(), np);
-    void* wk = L.work_id.ensure(wb);
+    void* wk = L.work_id.ensure(wb, L.stream);
     if (!wk) return fail(HSS_ERR_ALLOC, "ID workspace");
     if (L.k_host_cap < np) {
       if (L.k_host) hipHostFree(L.k_host);
@@ -698,6 +781,7 @@ hss_status compress_batch(std::vector<Job>& jobs) {
   tm.s = L.stream;
   Arena W;  // compression-only buffers of the whole batch
   W.chunk = (size_t)256 << 20;
+  W.stream = L.stream;
   std::vector<GatherDesc> single;
   std::vector<SampleReq> first;
   int maxh = 0;
@@ -904,6 +988,7 @@ hss_status new_handle(hss_handle* out, long long n, hipStream_t s, hss_handle_s*
   if (!p) return fail(HSS_ERR_ALLOC, "handle");
   p->h.n = n;
   p->h.stream = s;
+  p->h.gen->stream = s;
   // generator arena chunks sized to the matrix
   p->h.gen->chunk = std::min<size_t>((size_t)64 << 20, std::max<size_t>((size_t)1 << 20, (size_t)n * 4096));
   // descriptor staging is allocated on first use
@@ -963,7 +1048,7 @@ hss_status matvec_impl(Handle& H, int nrhs, const double* x, long long ldx, doub
     ow[t] = tot;
     tot += (long long)nd[t].mr * nrhs;
   }
-  double* ws = static_cast<double*>(H.work_mv.ensure((size_t)tot * 8 + 8));
+  double* ws = static_cast<double*>(H.work_mv.ensure((size_t)tot * 8 + 8, s));
   if (!ws) return fail(HSS_ERR_ALLOC, "matvec workspace");
   auto Y = [&](int t) { return ws + oy[t]; };
   auto Z = [&](int t) { return ws + oz[t]; };

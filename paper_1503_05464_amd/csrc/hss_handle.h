@@ -14,7 +14,14 @@ namespace hss {
 
 // Device memory owned by a handle: large chunks, bump-allocated, 256-byte
 // aligned, released together.
+// Device memory below comes from the device's stream-ordered pool
+// (hipMallocAsync / hipFreeAsync on the stream given), so allocating and
+// freeing never synchronizes the device or blocks other host threads.
+void* pool_alloc(size_t bytes, hipStream_t s);
+void pool_free(void* p, hipStream_t s);
+
 struct Arena {
+  hipStream_t stream = nullptr;  // stream of the allocations and of the release
   std::vector<void*> chunks;
   char* cur = nullptr;
   size_t left = 0;
@@ -30,11 +37,12 @@ struct Arena {
 };
 
 // A growable device buffer reused between launches (freed and reallocated
-// larger when needed; hipFree synchronises the device).
+// larger when needed).
 struct Scratch {
   void* p = nullptr;
   size_t cap = 0;
-  void* ensure(size_t bytes);
+  hipStream_t last = nullptr;  // stream of the latest use: the free is ordered after it
+  void* ensure(size_t bytes, hipStream_t s);
   void release();
 };
 

@@ -22,6 +22,7 @@ struct Staging {
   size_t cap = 0;
   size_t used = 0;
   hipStream_t stream = nullptr;
+  bool stream_used = false;  // copies were queued on `stream`
   hipError_t init(size_t bytes, hipStream_t s);
   void release();
   // Returns the device address of the copied table, or nullptr on failure.

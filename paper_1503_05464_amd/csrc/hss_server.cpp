@@ -40,6 +40,7 @@ struct Req {
   double* x = nullptr;
   long long ldx = 0;
   long long footprint = 0;
+  hipEvent_t ready = nullptr;  // recorded on the submitter's stream: A and b are written
   hss_request_info info{};
   bool done = false;
 };
@@ -116,6 +117,12 @@ struct hss_server_s {
 
   void run(const std::vector<Req*>& batch, hipStream_t s) {
     const int nb = (int)batch.size();
+    for (Req* r : batch)  // the inputs are read only after the submitter wrote them
+      if (r->ready) {
+        hipStreamWaitEvent(s, r->ready, 0);
+        hipEventDestroy(r->ready);
+        r->ready = nullptr;
+      }
     std::vector<const void*> As(nb);
     std::vector<long long> ns(nb), ldas(nb);
     for (int i = 0; i < nb; ++i) {
@@ -209,7 +216,7 @@ hss_status hss_server_create(const hss_server_opts* opts, hss_server* out) {
 
 hss_status hss_server_submit(hss_server sv, const void* A, int dtype, long long n, long long lda,
                              const hss_opts* opts, int nrhs, const double* b, long long ldb,
-                             double* x, long long ldx, long long* ticket) {
+                             double* x, long long ldx, void* stream, long long* ticket) {
   if (!sv || !ticket) return hss::set_error(HSS_ERR_ARG, "server or ticket is NULL");
   if (!A || n < 1 || lda < n || (dtype != HSS_F64 && dtype != HSS_F32))
     return hss::set_error(HSS_ERR_ARG, "A, n, lda or dtype invalid");
@@ -232,9 +239,17 @@ hss_status hss_server_submit(hss_server sv, const void* A, int dtype, long long 
   r->x = x;
   r->ldx = ldx;
   r->footprint = footprint_of(n, r->opts);
+  if (hipEventCreateWithFlags(&r->ready, hipEventDisableTiming) != hipSuccess ||
+      hipEventRecord(r->ready, static_cast<hipStream_t>(stream)) != hipSuccess) {
+    if (r->ready) hipEventDestroy(r->ready);
+    return hss::set_error(HSS_ERR_HIP, "event on the submitting stream");
+  }
   {
     std::lock_guard<std::mutex> lk(sv->mu);
-    if (sv->stop) return hss::set_error(HSS_ERR_STATE, "server is shutting down");
+    if (sv->stop) {
+      hipEventDestroy(r->ready);
+      return hss::set_error(HSS_ERR_STATE, "server is shutting down");
+    }
     r->id = sv->next_id++;
     r->info.t_submit = sv->now();
     r->info.status = HSS_OK;

@@ -201,7 +201,7 @@ hss_status factor_impl(Handle& H, hipStream_t s) {
       }
       double* scr = nullptr;
       if (scratch > 0) {
-        scr = static_cast<double*>(H.work_misc.ensure((size_t)scratch * 8));
+        scr = static_cast<double*>(H.work_misc.ensure((size_t)scratch * 8, s));
         if (!scr) return set_error(HSS_ERR_ALLOC, "ULV scratch");
         HIPCHK(hipMemsetAsync(scr, 0, (size_t)scratch * 8, s));
       }
@@ -291,7 +291,7 @@ hss_status factor_impl(Handle& H, hipStream_t s) {
       }
       if (!pr.empty()) {
         const size_t wb = id_workspace_bytes(pr.data(), (int)pr.size());
-        void* wk = H.work_id.ensure(wb);
+        void* wk = H.work_id.ensure(wb, s);
         if (!wk) return set_error(HSS_ERR_ALLOC, "QR workspace");
         std::vector<int> kh(pr.size() + 2);
         HIPCHK(launch_id_factor(pr.data(), (int)pr.size(), 0.0, wk, H.work_id.cap, kh.data(), H.staging, s));
@@ -365,7 +365,7 @@ hss_status solve_impl(Handle& H, int nrhs, const double* b, long long ldb, doubl
   }
   const long long oR = tot;
   tot += (long long)m0 * nrhs;
-  double* ws = static_cast<double*>(H.work_mv.ensure((size_t)tot * 8 + 8));
+  double* ws = static_cast<double*>(H.work_mv.ensure((size_t)tot * 8 + 8, s));
   if (!ws) return set_error(HSS_ERR_ALLOC, "solve workspace");
   double* RB = ws + oR;
   auto Bp = [&](int t) { return ws + oB[t]; };
