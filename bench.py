@@ -49,6 +49,29 @@ WORKLOADS = {
 }
 
 
+def measured_traffic(kernel_source: str, summary: str):
+    """HBM bytes per launch from a committed rocprofv3 --pmc summary, or None
+    when the summary is missing or was taken on another version of the
+    kernel's source (its sha256 prefix is recorded in the summary)."""
+    import hashlib
+
+    try:
+        text = open(os.path.join(ROOT, "profiles", summary)).read()
+        src = open(os.path.join(ROOT, "paper_1503_05464_amd", "csrc", kernel_source), "rb").read()
+    except OSError:
+        return None
+    want = None
+    traffic = None
+    for line in text.splitlines():
+        if line.startswith(f"{kernel_source} sha256 prefix:"):
+            want = line.split(":", 1)[1].strip()
+        if line.startswith("traffic_bytes_per_launch:"):
+            traffic = float(line.split(":", 1)[1].strip())
+    if want is None or traffic is None or hashlib.sha256(src).hexdigest()[:16] != want:
+        return None
+    return traffic
+
+
 def make_points(cfg):
     import workloads as W
 
@@ -496,7 +519,8 @@ def main() -> int:
         "peak": HBM_PEAK_GBS if hbm_bound else peak,
         "unit": "GB/s" if hbm_bound else "TFLOP/s",
         "frac": round(gbs / HBM_PEAK_GBS if hbm_bound else issued / peak, 4),
-        "traffic": None,
+        "traffic": (measured_traffic("kernels_sample.hip", "pmc_sample_kernel_gauss65536.txt")
+                    if args.sample_prec == "f64" and args.workload == "gauss65536" else None),
         "kernel": kname,
         "avg_launch_ms": round(t_gemm * 1e3 / max(1, launches), 4),
         "launches": launches,
