@@ -17,7 +17,8 @@
 // plain and the transposed product read MFMA operands conflict-free, and
 // only the global->LDS copy differs between them.  The next slice is
 // prefetched into registers while the current one is multiplied.  When the
-// tile count is too small to fill 256 CUs, K is split over workgroups and
+// tile count is too small to give every CU its four resident workgroups, K
+// is split over workgroups and
 // the partial sums are added in a fixed order by a second kernel
 // (deterministic, no atomics).  Consecutive tiles are mapped to the same XCD
 // so that the column tiles sharing an A slice meet in one L2.
@@ -293,7 +294,7 @@ Plan make_plan(long long n, int ncols, int bk) {
   p.n_mt = (int)((n + BM - 1) / BM);
   p.n_nt = (ncols + BN - 1) / BN;
   const long long tiles = (long long)p.n_mt * p.n_nt;
-  long long want = (512 + tiles - 1) / tiles;  // >= 2 workgroups per CU
+  long long want = (1024 + tiles - 1) / tiles;  // 4 workgroups per CU (the resident maximum)
   long long maxs = n / 1024;                   // keep >= 1024 k per split
   if (maxs < 1) maxs = 1;
   if (want > maxs) want = maxs;
