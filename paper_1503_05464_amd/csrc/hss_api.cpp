@@ -447,7 +447,10 @@ hss_status sample_batch(Handle& L, const std::vector<SampleReq>& reqs, EventTime
       j.lds = H.ldg;
       jobs.push_back(j);
     }
-    HIPCHK(launch_sample_mixed_grouped(jobs.data(), (int)jobs.size(), prec, L.staging, L.stream));
+    const long long wd = sample_mixed_grouped_workspace_doubles(jobs.data(), (int)jobs.size());
+    double* work = static_cast<double*>(L.work_sample.ensure((size_t)std::max(1LL, wd) * 8, L.stream));
+    if (!work) return fail(HSS_ERR_ALLOC, "sampling workspace");
+    HIPCHK(launch_sample_mixed_grouped(jobs.data(), (int)jobs.size(), prec, work, L.staging, L.stream));
     L.n_sgemm += 2;
   } else {
     for (const SampleReq& q : reqs) {
@@ -465,8 +468,9 @@ hss_status sample_batch(Handle& L, const std::vector<SampleReq>& reqs, EventTime
         launch_sample(q.A, H.dtype, H.n, q.lda, H.leaf_of, nc, H.Rr + c0, H.Rc + c0, H.ldg, H.Sr + c0,
                       H.Sc + c0, H.ldg, work, L.stream);
       else
-        launch_sample_mixed(static_cast<const float*>(q.A), H.n, q.lda, H.leaf_of, nc, prec, H.Rr + c0,
-                            H.Rc + c0, H.ldg, H.Sr + c0, H.Sc + c0, H.ldg, work, L.stream);
+        HIPCHK(launch_sample_mixed(static_cast<const float*>(q.A), H.n, q.lda, H.leaf_of, nc, prec,
+                                   H.Rr + c0, H.Rc + c0, H.ldg, H.Sr + c0, H.Sc + c0, H.ldg, work,
+                                   L.staging, L.stream));
       HIPCHK(hipGetLastError());
       L.n_sgemm += 2;
     }
@@ -1524,13 +1528,18 @@ hss_status hss_sample(const void* A, int dtype, int sample_prec, long long n, lo
                                                      : sample_mixed_workspace_doubles(n, ncols);
   double* work = nullptr;
   if (wd > 0) HIPCHK(hipMallocAsync(reinterpret_cast<void**>(&work), (size_t)wd * 8, s));
-  if (sample_prec == HSS_SAMPLE_F64)
+  Staging st;  // descriptor tables of the reduced-precision path
+  st.stream = s;
+  hipError_t e = hipSuccess;
+  if (sample_prec == HSS_SAMPLE_F64) {
     launch_sample(A, dtype, n, lda, leaf_of, ncols, Rr, Rc, ldr, Sr, Sc, lds, work, s);
-  else
-    launch_sample_mixed(static_cast<const float*>(A), n, lda, leaf_of, ncols, sample_prec, Rr, Rc,
-                        ldr, Sr, Sc, lds, work, s);
-  hipError_t e = hipGetLastError();
+    e = hipGetLastError();
+  } else {
+    e = launch_sample_mixed(static_cast<const float*>(A), n, lda, leaf_of, ncols, sample_prec, Rr, Rc,
+                            ldr, Sr, Sc, lds, work, st, s);
+  }
   if (work) hipFreeAsync(work, s);
+  st.release();
   HIPCHK(e);
   return HSS_OK;
 }

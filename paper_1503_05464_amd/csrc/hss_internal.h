@@ -56,9 +56,10 @@ long long sample_workspace_doubles(long long n, int ncols);
 // representable in the mode's precision.  FP32 accumulation over chunks of
 // 256 k, FP64 across chunks.
 long long sample_mixed_workspace_doubles(long long n, int ncols);
-void launch_sample_mixed(const float* A, long long n, long long lda, const int* leaf_of, int ncols,
-                         int mode, const double* Rr, const double* Rc, long long ldr, double* Sr,
-                         double* Sc, long long lds, double* work, hipStream_t s);
+hipError_t launch_sample_mixed(const float* A, long long n, long long lda, const int* leaf_of,
+                               int ncols, int mode, const double* Rr, const double* Rc,
+                               long long ldr, double* Sr, double* Sc, long long lds, double* work,
+                               Staging& st, hipStream_t s);
 // The sampling products of many matrices (one FP32 A each) in one launch per
 // side; all of one mode.  Rr/Rc/Sr/Sc point at the first column to form.
 struct SampleJob {
@@ -73,8 +74,9 @@ struct SampleJob {
   double* Sc;
   long long lds;
 };
-hipError_t launch_sample_mixed_grouped(const SampleJob* jobs, int njob, int mode, Staging& st,
-                                       hipStream_t s);
+long long sample_mixed_grouped_workspace_doubles(const SampleJob* jobs, int njob);
+hipError_t launch_sample_mixed_grouped(const SampleJob* jobs, int njob, int mode, double* work,
+                                       Staging& st, hipStream_t s);
 // R columns col0..col1-1 (rows 0..n-1, leading dimension ld, R points at row
 // 0 column 0) rounded to nearest even in place: mode 1 to FP32, mode 2 to
 // BF16; mode 0 leaves R unchanged.

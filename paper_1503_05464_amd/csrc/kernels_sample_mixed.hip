@@ -19,12 +19,18 @@
 // grows with the chunk length rather than with n.
 //
 // Tiling: a 256-thread workgroup computes a 128 x 64 tile of S, its four
-// wavefronts 64 x 32 each as 4 x 2 blocks of 16 x 16.  A and R pass through
-// LDS in k-slices of 32, both stored with k contiguous per row (A split into
-// its three BF16 planes on the way in), so that a lane reads its eight k
-// values for one MFMA operand in a single 16-byte access: lane l takes
+// wavefronts 64 x 32 each as 4 x 2 blocks of 16 x 16.  A passes through LDS
+// in k-slices of 32, stored with k contiguous per row (split into its three
+// BF16 planes on the way in), so that a lane reads its eight k values for
+// one MFMA operand in a single 16-byte access: lane l takes
 // k = 8 (l / 16) + e, e < 8, of row l % 16 -- the same k for A and R, which is
-// all the product needs.  The output layout of both MFMAs (checked on the
+// all the product needs.  A is written to LDS in packed pieces: in the plain
+// product a thread holds 16 consecutive k of one row; in the transposed
+// product it loads a 4 x 4 block of A so that it holds 4 consecutive k of
+// each of its 4 rows of the tile.  R comes from a transposed copy in the
+// products' precision (R^T: columns of R contiguous, zero-padded to whole
+// slices and tiles), made once per call, from which every wavefront loads
+// its operands directly.  The output layout of both MFMAs (checked on the
 // device): lane l, register r -> row 4 (l / 16) + r, column l % 16.
 #include <cstdint>
 #include <vector>
@@ -64,121 +70,174 @@ struct Smem;
 template <>
 struct alignas(16) Smem<1> {  // FP32
   float A[BM][AP1];
-  float B[BN][AP1];
 };
 template <>
 struct alignas(16) Smem<2> {  // BF16 x 3
   unsigned short A[3][BM][AP2];
-  unsigned short B[BN][AP2];
 };
 
-// this thread's 16 entries of the A slice: NN rows i, 16 consecutive k;
-// TN 16 consecutive i (columns of A) of one k
+template <int MODE>
+struct RtType;
+template <>
+struct RtType<1> {
+  typedef float T;
+};
+template <>
+struct RtType<2> {
+  typedef unsigned short T;
+};
+
+// This thread's 16 entries of the A slice.  NN: row i0 + tid/2, k = k0 +
+// 16 (tid % 2) + e.  TN (element (i, k) is A[k][i]): k = k0 + 4 (tid / 32) + q,
+// i = i0 + 4 (tid % 32) + e, stored in v[4 q + e].
 template <bool TRANS>
 __device__ __forceinline__ void load_a(float (&v)[16], const float* __restrict__ A, long long lda,
                                        int n, int i0, int k0, int kend,
                                        const int* __restrict__ leaf_of, bool vec_ok,
                                        bool need_mask) {
   const int tid = threadIdx.x;
-  int row, col, ie, ke;
   if (!TRANS) {
-    const int r = tid >> 1, kseg = (tid & 1) * 16;
-    row = i0 + r;
-    col = k0 + kseg;
-    ie = row;
-    ke = col;
+    const int row = i0 + (tid >> 1), col = k0 + (tid & 1) * 16;
+    if (row < n && col + 16 <= kend && vec_ok) {
+      const u32x4* p = reinterpret_cast<const u32x4*>(A + (long long)row * lda + col);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const u32x4 w = __builtin_nontemporal_load(p + q);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) v[4 * q + e] = __uint_as_float(w[e]);
+      }
+    } else {
+#pragma unroll
+      for (int e = 0; e < 16; ++e)
+        v[e] = (row < n && col + e < kend) ? A[(long long)row * lda + col + e] : 0.0f;
+    }
+    if (need_mask) {
+#pragma unroll
+      for (int e = 0; e < 16; ++e)
+        if (row < n && col + e < n && leaf_of[row] == leaf_of[col + e]) v[e] = 0.0f;
+    }
   } else {
-    const int kk = tid >> 3, iseg = (tid & 7) * 16;
-    row = k0 + kk;
-    col = i0 + iseg;
-    ie = col;
-    ke = row;
-  }
-  const bool full = !TRANS ? (row < n && col + 16 <= kend) : (row < kend && col + 16 <= n);
-  if (full && vec_ok) {
-    const u32x4* p = reinterpret_cast<const u32x4*>(A + (long long)row * lda + col);
+    const int kb = k0 + 4 * (tid >> 5), ib = i0 + 4 * (tid & 31);
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      const u32x4 w = __builtin_nontemporal_load(p + q);
+      const int k = kb + q;
+      if (k < kend && ib + 4 <= n && vec_ok) {
+        const u32x4 w = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(A + (long long)k * lda + ib));
 #pragma unroll
-      for (int e = 0; e < 4; ++e) v[4 * q + e] = __uint_as_float(w[e]);
+        for (int e = 0; e < 4; ++e) v[4 * q + e] = __uint_as_float(w[e]);
+      } else {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) v[4 * q + e] = (k < kend && ib + e < n) ? A[(long long)k * lda + ib + e] : 0.0f;
+      }
     }
-  } else {
+    if (need_mask) {
 #pragma unroll
-    for (int e = 0; e < 16; ++e) {
-      const bool ok = !TRANS ? (row < n && col + e < kend) : (row < kend && col + e < n);
-      v[e] = ok ? A[(long long)row * lda + col + e] : 0.0f;
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+          if (kb + q < n && ib + e < n && leaf_of[kb + q] == leaf_of[ib + e]) v[4 * q + e] = 0.0f;
     }
   }
-  if (need_mask) {
-#pragma unroll
-    for (int e = 0; e < 16; ++e) {
-      const int i = !TRANS ? ie : ie + e;
-      const int k = !TRANS ? ke + e : ke;
-      if (i < n && k < n && leaf_of[i] == leaf_of[k]) v[e] = 0.0f;
-    }
-  }
+}
+
+// three-term split of FP32 values into BF16: a = h1 + h2 + h3 exactly
+__device__ __forceinline__ void split3(float a, unsigned short& h1, unsigned short& h2,
+                                       unsigned short& h3) {
+  h1 = bf16_rn(a);
+  const float r1 = a - bf16_to_f(h1);
+  h2 = bf16_rn(r1);
+  h3 = bf16_rn(r1 - bf16_to_f(h2));
+}
+
+__device__ __forceinline__ unsigned int pack2(unsigned short lo, unsigned short hi) {
+  return (unsigned int)lo | ((unsigned int)hi << 16);
 }
 
 template <int MODE, bool TRANS>
 __device__ __forceinline__ void store_a(Smem<MODE>& sm, const float (&v)[16]) {
   const int tid = threadIdx.x;
-#pragma unroll
-  for (int e = 0; e < 16; ++e) {
-    int r, k;
-    if (!TRANS) {
-      r = tid >> 1;
-      k = (tid & 1) * 16 + e;
-    } else {
-      r = (tid & 7) * 16 + e;
-      k = tid >> 3;
-    }
+  if (!TRANS) {  // one row, 16 consecutive k
+    const int r = tid >> 1, kseg = (tid & 1) * 16;
     if constexpr (MODE == 1) {
-      sm.A[r][k] = v[e];
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        *reinterpret_cast<float4*>(&sm.A[r][kseg + 4 * j]) =
+            make_float4(v[4 * j], v[4 * j + 1], v[4 * j + 2], v[4 * j + 3]);
     } else {
-      const unsigned short h1 = bf16_rn(v[e]);
-      const float r1 = v[e] - bf16_to_f(h1);
-      const unsigned short h2 = bf16_rn(r1);
-      const float r2 = r1 - bf16_to_f(h2);
-      sm.A[0][r][k] = h1;
-      sm.A[1][r][k] = h2;
-      sm.A[2][r][k] = bf16_rn(r2);
+      unsigned short h[3][16];
+#pragma unroll
+      for (int e = 0; e < 16; ++e) split3(v[e], h[0][e], h[1][e], h[2][e]);
+#pragma unroll
+      for (int t = 0; t < 3; ++t)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          u32x4 w;
+#pragma unroll
+          for (int q = 0; q < 4; ++q) w[q] = pack2(h[t][8 * j + 2 * q], h[t][8 * j + 2 * q + 1]);
+          *reinterpret_cast<u32x4*>(&sm.A[t][r][kseg + 8 * j]) = w;
+        }
+    }
+  } else {  // 4 rows of the tile (columns of A), 4 consecutive k each
+    const int kq = 4 * (tid >> 5), rb = 4 * (tid & 31);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      if constexpr (MODE == 1) {
+        *reinterpret_cast<float4*>(&sm.A[rb + e][kq]) = make_float4(v[e], v[4 + e], v[8 + e], v[12 + e]);
+      } else {
+        unsigned short h[3][4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) split3(v[4 * q + e], h[0][q], h[1][q], h[2][q]);
+#pragma unroll
+        for (int t = 0; t < 3; ++t)
+          *reinterpret_cast<uint2*>(&sm.A[t][rb + e][kq]) = make_uint2(pack2(h[t][0], h[t][1]), pack2(h[t][2], h[t][3]));
+      }
     }
   }
 }
 
-// R slice: rows k0 .. k0+31, columns c0 .. c0+63; 8 values per thread
-__device__ __forceinline__ void load_r(double (&v)[8], const double* __restrict__ R, long long ldr,
-                                       int k0, int kend, int c0, int ncols) {
-  const int tid = threadIdx.x;
-  const int rr = tid >> 3, cc = (tid & 7) * 8;
-  const int k = k0 + rr, c = c0 + cc;
-#pragma unroll
-  for (int e = 0; e < 8; ++e) v[e] = (k < kend && c + e < ncols) ? R[(long long)k * ldr + c + e] : 0.0;
-}
+// R^T operands of a wavefront for one slice: column c (of R) and k = k0 + lk
+// + e, e < 8, for its two 16-column blocks
+template <int MODE>
+struct BFrag;
+template <>
+struct BFrag<1> {
+  float b[2][8];
+};
+template <>
+struct BFrag<2> {
+  bf16x8 b[2];
+};
 
 template <int MODE>
-__device__ __forceinline__ void store_r(Smem<MODE>& sm, const double (&v)[8]) {
-  const int tid = threadIdx.x;
-  const int rr = tid >> 3, cc = (tid & 7) * 8;
+__device__ __forceinline__ void load_b(BFrag<MODE>& f, const typename RtType<MODE>::T* __restrict__ Rt,
+                                       long long ldrt, int cbase, int k0, int lr, int lk) {
 #pragma unroll
-  for (int e = 0; e < 8; ++e) {
-    if constexpr (MODE == 1) sm.B[cc + e][rr] = (float)v[e];
-    else sm.B[cc + e][rr] = bf16_rn((float)v[e]);  // exact: R is BF16-representable
+  for (int nb = 0; nb < 2; ++nb) {
+    const typename RtType<MODE>::T* p = Rt + (long long)(cbase + nb * 16 + lr) * ldrt + k0 + lk;
+    if constexpr (MODE == 1) {
+      const float4 x = *reinterpret_cast<const float4*>(p);
+      const float4 y = *reinterpret_cast<const float4*>(p + 4);
+      f.b[nb][0] = x.x; f.b[nb][1] = x.y; f.b[nb][2] = x.z; f.b[nb][3] = x.w;
+      f.b[nb][4] = y.x; f.b[nb][5] = y.y; f.b[nb][6] = y.z; f.b[nb][7] = y.w;
+    } else {
+      f.b[nb] = *reinterpret_cast<const bf16x8*>(p);
+    }
   }
 }
 
 // One 128 x 64 tile of S (rows i0.., columns c0..) over k in [kbeg, kend),
-// written to out (leading dimension ldo).
+// written to out (leading dimension ldo).  Rt: R^T in the products'
+// precision, ldrt >= kend rounded up to BK, columns up to c0 + BN present.
 template <int MODE, bool TRANS>
 __device__ __forceinline__ void sample_tile(Smem<MODE>& sm, const float* __restrict__ A,
                                             long long lda, int n, const int* __restrict__ leaf_of,
-                                            const double* __restrict__ R, long long ldr, int ncols,
-                                            int i0, int c0, int kbeg, int kend,
-                                            double* __restrict__ out, long long ldo) {
+                                            const typename RtType<MODE>::T* __restrict__ Rt,
+                                            long long ldrt, int ncols, int i0, int c0, int kbeg,
+                                            int kend, double* __restrict__ out, long long ldo) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wm = wave >> 1, wn = wave & 1;
   const int lr = lane & 15, lk = (lane >> 4) * 8;
+  const int cbase = c0 + wn * 32;
 
   const bool vec_a = ((lda * 4) % 16 == 0) && ((reinterpret_cast<uintptr_t>(A) & 15) == 0);
   int li0 = 0, li1 = -1;
@@ -205,13 +264,12 @@ __device__ __forceinline__ void sample_tile(Smem<MODE>& sm, const float* __restr
     }
 
   float va[16];
-  double vr[8];
+  BFrag<MODE> fb, fn;
   int k0 = kbeg;
   if (k0 < kend) {
     load_a<TRANS>(va, A, lda, n, i0, k0, kend, leaf_of, vec_a, mask_for(k0));
-    load_r(vr, R, ldr, k0, kend, c0, ncols);
+    load_b<MODE>(fb, Rt, ldrt, cbase, k0, lr, lk);
     store_a<MODE, TRANS>(sm, va);
-    store_r<MODE>(sm, vr);
   }
   __syncthreads();
   int since = 0;  // k values accumulated in FP32 since the last carry
@@ -219,34 +277,21 @@ __device__ __forceinline__ void sample_tile(Smem<MODE>& sm, const float* __restr
     const int kn = k0 + BK;
     if (kn < kend) {
       load_a<TRANS>(va, A, lda, n, i0, kn, kend, leaf_of, vec_a, mask_for(kn));
-      load_r(vr, R, ldr, kn, kend, c0, ncols);
+      load_b<MODE>(fn, Rt, ldrt, cbase, kn, lr, lk);
     }
     if constexpr (MODE == 1) {
-      float a[4][8], b[2][8];
 #pragma unroll
       for (int mb = 0; mb < 4; ++mb) {
-        const float* p = &sm.A[wm * 64 + mb * 16 + lr][lk];
+        const float4 x = *reinterpret_cast<const float4*>(&sm.A[wm * 64 + mb * 16 + lr][lk]);
+        const float4 y = *reinterpret_cast<const float4*>(&sm.A[wm * 64 + mb * 16 + lr][lk + 4]);
+        const float a[8] = {x.x, x.y, x.z, x.w, y.x, y.y, y.z, y.w};
 #pragma unroll
-        for (int e = 0; e < 8; ++e) a[mb][e] = p[e];
-      }
-#pragma unroll
-      for (int nb = 0; nb < 2; ++nb) {
-        const float* p = &sm.B[wn * 32 + nb * 16 + lr][lk];
-#pragma unroll
-        for (int e = 0; e < 8; ++e) b[nb][e] = p[e];
-      }
-#pragma unroll
-      for (int e = 0; e < 8; ++e)
-#pragma unroll
-        for (int mb = 0; mb < 4; ++mb)
+        for (int e = 0; e < 8; ++e)
 #pragma unroll
           for (int nb = 0; nb < 2; ++nb)
-            acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[mb][e], b[nb][e], acc[mb][nb], 0, 0, 0);
+            acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[e], fb.b[nb][e], acc[mb][nb], 0, 0, 0);
+      }
     } else {
-      bf16x8 b[2];
-#pragma unroll
-      for (int nb = 0; nb < 2; ++nb)
-        b[nb] = *reinterpret_cast<const bf16x8*>(&sm.B[wn * 32 + nb * 16 + lr][lk]);
 #pragma unroll
       for (int t = 0; t < 3; ++t) {
         bf16x8 a[4];
@@ -257,7 +302,7 @@ __device__ __forceinline__ void sample_tile(Smem<MODE>& sm, const float* __restr
         for (int mb = 0; mb < 4; ++mb)
 #pragma unroll
           for (int nb = 0; nb < 2; ++nb)
-            acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[mb], b[nb], acc[mb][nb], 0, 0, 0);
+            acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[mb], fb.b[nb], acc[mb][nb], 0, 0, 0);
       }
     }
     since += BK;
@@ -275,7 +320,7 @@ __device__ __forceinline__ void sample_tile(Smem<MODE>& sm, const float* __restr
     __syncthreads();
     if (kn < kend) {
       store_a<MODE, TRANS>(sm, va);
-      store_r<MODE>(sm, vr);
+      fb = fn;
     }
     __syncthreads();
   }
@@ -284,7 +329,7 @@ __device__ __forceinline__ void sample_tile(Smem<MODE>& sm, const float* __restr
   for (int mb = 0; mb < 4; ++mb)
 #pragma unroll
     for (int nb = 0; nb < 2; ++nb) {
-      const int c = c0 + wn * 32 + nb * 16 + lr;
+      const int c = cbase + nb * 16 + lr;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int i = i0 + wm * 64 + mb * 16 + 4 * (lane >> 4) + r;
@@ -296,8 +341,8 @@ __device__ __forceinline__ void sample_tile(Smem<MODE>& sm, const float* __restr
 template <int MODE, bool TRANS>
 __global__ __launch_bounds__(NT) void sample_mixed_kernel(
     const float* __restrict__ A, long long lda, int n, const int* __restrict__ leaf_of,
-    const double* __restrict__ R, long long ldr, double* __restrict__ S, long long lds, int ncols,
-    int n_nt, int ksplit, int kchunk, double* __restrict__ work) {
+    const typename RtType<MODE>::T* __restrict__ Rt, long long ldrt, double* __restrict__ S,
+    long long lds, int ncols, int n_nt, int ksplit, int kchunk, double* __restrict__ work) {
   __shared__ Smem<MODE> sm;
   // consecutive logical tiles share an XCD
   const int nblk = gridDim.x;
@@ -314,7 +359,7 @@ __global__ __launch_bounds__(NT) void sample_mixed_kernel(
     out = work + (long long)ks * n * ncols;
     ldo = ncols;
   }
-  sample_tile<MODE, TRANS>(sm, A, lda, n, leaf_of, R, ldr, ncols, mt * BM, nt * BN, kbeg,
+  sample_tile<MODE, TRANS>(sm, A, lda, n, leaf_of, Rt, ldrt, ncols, mt * BM, nt * BN, kbeg,
                            min(n, kbeg + kchunk), out, ldo);
 }
 
@@ -325,8 +370,8 @@ struct GroupDesc {
   long long lda;
   int n, ncols, n_nt;
   const int* leaf_of;
-  const double* R;
-  long long ldr;
+  const void* Rt;
+  long long ldrt;
   double* S;
   long long lds;
   long long tile0;
@@ -345,8 +390,9 @@ __global__ __launch_bounds__(NT) void sample_mixed_grouped_kernel(const GroupDes
   }
   const GroupDesc d = g[lo];
   const int t = (int)(b - d.tile0);
-  sample_tile<MODE, TRANS>(sm, d.A, d.lda, d.n, d.leaf_of, d.R, d.ldr, d.ncols, (t / d.n_nt) * BM,
-                           (t % d.n_nt) * BN, 0, d.n, d.S, d.lds);
+  sample_tile<MODE, TRANS>(sm, d.A, d.lda, d.n, d.leaf_of,
+                           static_cast<const typename RtType<MODE>::T*>(d.Rt), d.ldrt, d.ncols,
+                           (t / d.n_nt) * BM, (t % d.n_nt) * BN, 0, d.n, d.S, d.lds);
 }
 
 __global__ void reduce_splits_mixed_kernel(const double* __restrict__ work, int ksplit, long long n,
@@ -359,6 +405,57 @@ __global__ void reduce_splits_mixed_kernel(const double* __restrict__ work, int 
   double s = 0.0;
   for (int q = 0; q < ksplit; ++q) s += work[(long long)q * total + idx];
   S[i * lds + c] = s;
+}
+
+// R^T in the products' precision: Rt[c][k] = R[k][c] for c < ncols, k < n,
+// zero in the padding (columns up to whole tiles, k up to whole slices).
+// R already holds values representable in that precision.
+struct PrepDesc {
+  const double* R;
+  long long ldr;
+  int n, ncols, cpad;
+  long long ldrt;
+  void* Rt;
+  long long e0;  // first element of this descriptor in the launch
+};
+
+template <int MODE>
+__global__ void prep_rt_kernel(const PrepDesc* __restrict__ g, int ng, long long total) {
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= total) return;
+  int lo = 0, hi = ng - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (g[mid].e0 <= e) lo = mid;
+    else hi = mid - 1;
+  }
+  const PrepDesc d = g[lo];
+  const long long x = e - d.e0;
+  const int c = (int)(x / d.ldrt);
+  const long long k = x % d.ldrt;
+  const double v = (c < d.ncols && k < d.n) ? d.R[k * d.ldr + c] : 0.0;
+  if constexpr (MODE == 1) static_cast<float*>(d.Rt)[x] = (float)v;
+  else static_cast<unsigned short*>(d.Rt)[x] = bf16_rn((float)v);
+}
+
+long long rt_ld(long long n) { return (n + BK - 1) / BK * BK; }
+int rt_cols(int ncols) { return (ncols + BN - 1) / BN * BN; }
+// doubles of workspace for one R^T copy (4-byte elements: enough for both modes)
+long long rt_doubles(long long n, int ncols) { return (rt_ld(n) * rt_cols(ncols) * 4 + 7) / 8; }
+
+hipError_t prep_rt(std::vector<PrepDesc>& g, int mode, Staging& st, hipStream_t s) {
+  if (g.empty()) return hipSuccess;
+  long long total = 0;
+  for (PrepDesc& d : g) {
+    d.e0 = total;
+    total += (long long)d.cpad * d.ldrt;
+  }
+  const PrepDesc* dg = static_cast<const PrepDesc*>(st.push(g.data(), g.size() * sizeof(PrepDesc)));
+  if (!dg) return hipErrorOutOfMemory;
+  const dim3 grid((unsigned)((total + 255) / 256));
+  if (mode == 1) hipLaunchKernelGGL(prep_rt_kernel<1>, grid, dim3(256), 0, s, dg, (int)g.size(), total);
+  else hipLaunchKernelGGL(prep_rt_kernel<2>, grid, dim3(256), 0, s, dg, (int)g.size(), total);
+  return hipGetLastError();
 }
 
 // R rounded in place to the precision of the products: FP32 (mode 1) or
@@ -403,12 +500,13 @@ Plan make_plan(long long n, int ncols) {
 }
 
 template <int MODE, bool TRANS>
-void run(const float* A, long long lda, long long n, const int* leaf_of, int ncols, const double* R,
-         long long ldr, double* S, long long lds, double* work, hipStream_t s) {
+void run(const float* A, long long lda, long long n, const int* leaf_of, int ncols, const void* Rt,
+         double* S, long long lds, double* work, hipStream_t s) {
   Plan p = make_plan(n, ncols);
   const long long nblocks = (long long)p.n_mt * p.n_nt * p.ksplit;
   hipLaunchKernelGGL((sample_mixed_kernel<MODE, TRANS>), dim3((unsigned)nblocks), dim3(NT), 0, s, A,
-                     lda, (int)n, leaf_of, R, ldr, S, lds, ncols, p.n_nt, p.ksplit, p.kchunk, work);
+                     lda, (int)n, leaf_of, static_cast<const typename RtType<MODE>::T*>(Rt), rt_ld(n),
+                     S, lds, ncols, p.n_nt, p.ksplit, p.kchunk, work);
   if (p.ksplit > 1) {
     const long long total = n * ncols;
     hipLaunchKernelGGL(reduce_splits_mixed_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256),
@@ -420,25 +518,59 @@ void run(const float* A, long long lda, long long n, const int* leaf_of, int nco
 
 long long sample_mixed_workspace_doubles(long long n, int ncols) {
   Plan p = make_plan(n, ncols);
-  return p.ksplit > 1 ? (long long)p.ksplit * n * ncols : 0;
+  return 2 * rt_doubles(n, ncols) + (p.ksplit > 1 ? (long long)p.ksplit * n * ncols : 0);
 }
 
-void launch_sample_mixed(const float* A, long long n, long long lda, const int* leaf_of, int ncols,
-                         int mode, const double* Rr, const double* Rc, long long ldr, double* Sr,
-                         double* Sc, long long lds, double* work, hipStream_t s) {
-  if (n <= 0 || ncols <= 0) return;
+hipError_t launch_sample_mixed(const float* A, long long n, long long lda, const int* leaf_of,
+                               int ncols, int mode, const double* Rr, const double* Rc,
+                               long long ldr, double* Sr, double* Sc, long long lds, double* work,
+                               Staging& st, hipStream_t s) {
+  if (n <= 0 || ncols <= 0) return hipSuccess;
+  // work: [R^T of R^r | R^T of R^c | split-k partials]
+  double* rt_r = work;
+  double* rt_c = work + rt_doubles(n, ncols);
+  double* part = work + 2 * rt_doubles(n, ncols);
+  std::vector<PrepDesc> g;
+  if (Sr) g.push_back(PrepDesc{Rr, ldr, (int)n, ncols, rt_cols(ncols), rt_ld(n), rt_r, 0});
+  if (Sc) g.push_back(PrepDesc{Rc, ldr, (int)n, ncols, rt_cols(ncols), rt_ld(n), rt_c, 0});
+  hipError_t e = prep_rt(g, mode, st, s);
+  if (e != hipSuccess) return e;
   if (mode == 1) {
-    if (Sr) run<1, false>(A, lda, n, leaf_of, ncols, Rr, ldr, Sr, lds, work, s);
-    if (Sc) run<1, true>(A, lda, n, leaf_of, ncols, Rc, ldr, Sc, lds, work, s);
+    if (Sr) run<1, false>(A, lda, n, leaf_of, ncols, rt_r, Sr, lds, part, s);
+    if (Sc) run<1, true>(A, lda, n, leaf_of, ncols, rt_c, Sc, lds, part, s);
   } else {
-    if (Sr) run<2, false>(A, lda, n, leaf_of, ncols, Rr, ldr, Sr, lds, work, s);
-    if (Sc) run<2, true>(A, lda, n, leaf_of, ncols, Rc, ldr, Sc, lds, work, s);
+    if (Sr) run<2, false>(A, lda, n, leaf_of, ncols, rt_r, Sr, lds, part, s);
+    if (Sc) run<2, true>(A, lda, n, leaf_of, ncols, rt_c, Sc, lds, part, s);
   }
+  return hipGetLastError();
 }
 
-hipError_t launch_sample_mixed_grouped(const SampleJob* jobs, int njob, int mode, Staging& st,
-                                       hipStream_t s) {
+long long sample_mixed_grouped_workspace_doubles(const SampleJob* jobs, int njob) {
+  long long t = 0;
+  for (int q = 0; q < njob; ++q)
+    if (jobs[q].n > 0 && jobs[q].ncols > 0) t += 2 * rt_doubles(jobs[q].n, jobs[q].ncols);
+  return t;
+}
+
+hipError_t launch_sample_mixed_grouped(const SampleJob* jobs, int njob, int mode, double* work,
+                                       Staging& st, hipStream_t s) {
   if (njob <= 0) return hipSuccess;
+  // the R^T copies of every job and side, then one launch per side
+  std::vector<PrepDesc> pd;
+  std::vector<double*> rts(2 * (size_t)njob, nullptr);
+  long long off = 0;
+  for (int q = 0; q < njob; ++q) {
+    const SampleJob& j = jobs[q];
+    if (j.n <= 0 || j.ncols <= 0) continue;
+    for (int side = 0; side < 2; ++side) {
+      rts[2 * q + side] = work + off;
+      pd.push_back(PrepDesc{side == 0 ? j.Rr : j.Rc, j.ldr, (int)j.n, j.ncols, rt_cols(j.ncols),
+                            rt_ld(j.n), work + off, 0});
+      off += rt_doubles(j.n, j.ncols);
+    }
+  }
+  hipError_t e = prep_rt(pd, mode, st, s);
+  if (e != hipSuccess) return e;
   for (int side = 0; side < 2; ++side) {
     std::vector<GroupDesc> g;
     long long tiles = 0;
@@ -452,8 +584,8 @@ hipError_t launch_sample_mixed_grouped(const SampleJob* jobs, int njob, int mode
       d.ncols = j.ncols;
       d.n_nt = (j.ncols + BN - 1) / BN;
       d.leaf_of = j.leaf_of;
-      d.R = side == 0 ? j.Rr : j.Rc;
-      d.ldr = j.ldr;
+      d.Rt = rts[2 * q + side];
+      d.ldrt = rt_ld(j.n);
       d.S = side == 0 ? j.Sr : j.Sc;
       d.lds = j.lds;
       d.tile0 = tiles;
@@ -471,7 +603,7 @@ hipError_t launch_sample_mixed_grouped(const SampleJob* jobs, int njob, int mode
       if (side == 0) hipLaunchKernelGGL((sample_mixed_grouped_kernel<2, false>), dim3((unsigned)tiles), dim3(NT), 0, s, dg, ng);
       else hipLaunchKernelGGL((sample_mixed_grouped_kernel<2, true>), dim3((unsigned)tiles), dim3(NT), 0, s, dg, ng);
     }
-    const hipError_t e = hipGetLastError();
+    e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
