@@ -68,14 +68,20 @@ struct Work {
   int* ndone;    // 1
   double* cand_v;  // 2 * tg: per-workgroup pivot candidates (step parity)
   int* cand_i;     // 2 * tg
-  double* cbuf;    // 2 * tg * ldcb: candidate columns (persistent path)
-  long long ldcb;  // max d
+  double* cbuf;    // 2 * min(tg, kCandSlots) * ldcb: candidate columns (persistent path)
+  long long ldcb;  // max d rounded up to a multiple of 512 (a whole column of registers)
+  long long nslots;  // min(tg, kCandSlots): workgroups a persistent launch may have
   int* stamp;      // 2 * tg: step stamp of each published candidate (persistent path)
   int* err;        // 1: a wait for a candidate timed out (persistent path)
   double* W;     // sum(m * d)
 };
 
 size_t al(size_t b) { return (b + 255) / 256 * 256; }
+
+// persistent path: at most this many workgroups per launch (candidate
+// column slots per step parity), and the stride of a published column
+constexpr long long kCandSlots = 2048;
+long long ldcb_of(long long dmax) { return (dmax + 511) / 512 * 512; }
 
 // pivot steps a problem can take
 int kmax_of(const IdProblem& p) {
@@ -110,8 +116,9 @@ void carve(const IdProblem* probs, int nprob, void* base, Work& w, long long& tm
   w.ndone = reinterpret_cast<int*>(take(4));
   w.cand_v = reinterpret_cast<double*>(take(2 * tg * 8));
   w.cand_i = reinterpret_cast<int*>(take(2 * tg * 4));
-  w.ldcb = dm;
-  w.cbuf = reinterpret_cast<double*>(take(2 * tg * dm * 8));
+  w.ldcb = ldcb_of(dm);
+  w.nslots = std::min(tg, kCandSlots);
+  w.cbuf = reinterpret_cast<double*>(take(2 * w.nslots * w.ldcb * 8));
   w.stamp = reinterpret_cast<int*>(take(2 * tg * 4));
   w.err = reinterpret_cast<int*>(take(4));
   w.W = reinterpret_cast<double*>(take(tw * 8));
@@ -506,13 +513,16 @@ __global__ __launch_bounds__(ST) void id_step_kernel(const DevProb* __restrict__
 //
 // Workgroup g of a problem owns columns g*PW*C .. (g+1)*PW*C-1, C per
 // wavefront, and keeps them in registers for the whole factorization (lane l
-// holds rows l, l+64, ..., T per column).  After each step the workgroup
-// publishes its best remaining column -- norm, index and values -- in a slot
-// of its own (double-buffered by step parity) and then stamps the slot with
-// the step number.  Every workgroup of the problem waits for the G stamps of
-// the step, reduces the same candidates the same way, reads the winner's
-// published values as the reflector and updates its own columns.  Per step,
-// global memory carries only the candidates and one column per workgroup.
+// holds rows l, l+64, ..., T per column; rows d..64T-1 are zero and stay
+// zero, so no row needs a bounds test inside the step loop).  Two
+// wavefronts share each SIMD and every value lives in architectural
+// registers.  After each step the workgroup publishes its best remaining
+// column -- norm, index and values -- in a slot of its own (double-buffered
+// by step parity) and then stamps the slot with the step number.  Every
+// workgroup of the problem waits for the G stamps of the step, reduces the
+// same candidates the same way, reads the winner's published values as the
+// reflector and updates its own columns.  Per step, global memory carries
+// only the candidates and one column per workgroup.
 //
 // Published data is written and read with device-scope (coherent) accesses;
 // a workgroup stamps its slot only after its data stores have completed.  No
@@ -521,7 +531,7 @@ __global__ __launch_bounds__(ST) void id_step_kernel(const DevProb* __restrict__
 // does every workgroup that sees the flag; the factorization is then
 // reported as failed and nothing is written back.
 // ---------------------------------------------------------------------------
-constexpr int PW = 4;        // wavefronts per persistent workgroup
+constexpr int PW = 8;        // wavefronts per persistent workgroup (two per SIMD)
 constexpr int PT = PW * 64;  // threads per persistent workgroup
 constexpr int kSpinLimit = 1 << 22;
 
@@ -534,10 +544,19 @@ __device__ __forceinline__ V ld_dev(const V* p) {
   return __hip_atomic_load(const_cast<V*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// The step loop is written for the register allocator: slices are skipped
+// in groups of PG (a handful of uniform branches per step, the finished
+// rows of a processed group see u = 0), at most PG reflector values are
+// read from LDS ahead of their use, and the published column's addresses are
+// formed inside the loop.  Each wavefront keeps only its best remaining
+// column's norm, not one per column.
+constexpr int PG = 4;
+
 template <int T, int C>
 __global__ __launch_bounds__(PT) void qrcp_persist_kernel(const DevProb* __restrict__ probs,
                                                          const int* __restrict__ wg_prob,
                                                          double rtol, Work w) {
+  static_assert(T % PW == 0 && T % PG == 0, "slices are staged T / PW per thread, skipped PG at a time");
   __shared__ double u[T * 64];
   __shared__ double rv[PW];
   __shared__ int ri[PW];
@@ -547,44 +566,40 @@ __global__ __launch_bounds__(PT) void qrcp_persist_kernel(const DevProb* __restr
 
   const int q = wg_prob[blockIdx.x];
   const DevProb dp = probs[q];
-  const IdProblem& P = dp.p;
-  const int m = P.m, d = P.d;
-  const int g = blockIdx.x - dp.g0;
+  const int m = dp.p.m, d = dp.p.d;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const bool leader = (g == 0 && tid == 0);
+  const bool leader = (blockIdx.x == dp.g0 && tid == 0);
   constexpr int CPG = PW * C;  // columns per workgroup
-  const int jb = g * CPG + wave * C;
+  const int jb = (blockIdx.x - dp.g0) * CPG + wave * C;
   int* __restrict__ step = w.step + dp.off;
   const long long ldcb = w.ldcb;
   const long long nslot = gridDim.x;
 
   double y[C][T];
-  double nv[C];
+  double bv = -1.0;  // this wavefront's best remaining column: norm, index
+  int bi = INT_MAX;
   unsigned sel = 0;  // columns of this wavefront already chosen as pivots
 #pragma unroll
   for (int c = 0; c < C; ++c) {
     const int j = jb + c;
+    // a lane's base address and constant strides: no per-row offsets to keep
+    const double* __restrict__ src = dp.p.Y + (long long)min(j, m - 1) * dp.p.ldy + lane;
     double s = 0.0;
 #pragma unroll
     for (int t = 0; t < T; ++t) {
-      const int r = lane + 64 * t;
-      const double v = (j < m && r < d) ? P.Y[(long long)j * P.ldy + r] : 0.0;
+      const double v = (j < m && lane < d - 64 * t) ? src[64 * t] : 0.0;
       y[c][t] = v;
       s = fma(v, v, s);
     }
-    nv[c] = (j < m) ? sqrt(wave_sum(s)) : -1.0;
+    if (j < m) better(bv, bi, sqrt(wave_sum(s)), j);
     if (j < m && lane == 0) step[j] = -1;
     asm volatile("" ::: "memory");  // one column's loads in flight at a time
   }
   if (tid == 0) s_ok = 1;
 
-  // publish this workgroup's best column for step i (norm, index, rows >= i)
-  auto publish = [&](int i) {
-    double bv = -1.0;
-    int bi = INT_MAX;
-#pragma unroll
-    for (int c = 0; c < C; ++c)
-      if (!((sel >> c) & 1u) && jb + c < m) better(bv, bi, nv[c], jb + c);
+  // publish this workgroup's best column for step i: norm, index, and the
+  // row slices from i / 64 on (the reader masks rows below i)
+  auto publish = [&](int i) __attribute__((always_inline)) {  // y must stay in registers
     if (lane == 0) {
       rv[wave] = bv;
       ri[wave] = bi;
@@ -599,26 +614,31 @@ __global__ __launch_bounds__(PT) void qrcp_persist_kernel(const DevProb* __restr
       st_dev(w.cand_v + slot, v);
       st_dev(w.cand_i + slot, ix);
     }
-    double* dst = w.cbuf + slot * ldcb;
+    if (ix >= jb && ix < jb + C) {  // uniform: the owning wavefront writes
+      double* dst = w.cbuf + slot * ldcb + lane;
+      asm volatile("" : "+v"(dst));  // addresses formed here, not hoisted out of the step loop
+      const int ti = i >> 6;
 #pragma unroll
-    for (int c = 0; c < C; ++c)
-      if (jb + c == ix) {
+      for (int c = 0; c < C; ++c) {
+        if (ix != jb + c) continue;
 #pragma unroll
-        for (int t = 0; t < T; ++t) {
-          const int r = lane + 64 * t;
-          if (r >= i && r < d) st_dev(dst + r, y[c][t]);
+        for (int g = 0; g < T / PG; ++g) {
+          if (PG * g + PG <= ti) continue;
+#pragma unroll
+          for (int tt = 0; tt < PG; ++tt) st_dev(dst + 64 * (PG * g + tt), y[c][PG * g + tt]);
         }
       }
+    }
     __builtin_amdgcn_s_waitcnt(0);  // this thread's stores have completed
     __syncthreads();                // ... and every other thread's
     if (tid == 0) st_dev(w.stamp + slot, i + 1);
   };
 
   // wait for the problem's G candidates of step i; false on a timeout
-  auto gather = [&](int i) -> bool {
+  auto gather = [&](int i) __attribute__((always_inline)) -> bool {
     const long long base = (long long)(i & 1) * nslot + dp.g0;
-    double bv = -1.0;
-    int bi = INT_MAX;
+    double gv = -1.0;
+    int gi = INT_MAX;
     bool ok = true;
     for (int t = tid; t < dp.G && ok; t += PT) {
       int spins = 0;
@@ -636,14 +656,15 @@ __global__ __launch_bounds__(PT) void qrcp_persist_kernel(const DevProb* __restr
         }
         __builtin_amdgcn_s_sleep(1);
       }
-      if (ok) better(bv, bi, ld_dev(w.cand_v + base + t), ld_dev(w.cand_i + base + t));
+      if (ok) better(gv, gi, ld_dev(w.cand_v + base + t), ld_dev(w.cand_i + base + t));
     }
     if (!ok) s_ok = 0;
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) better(bv, bi, __shfl_xor(bv, o, 64), __shfl_xor(bi, o, 64));
+    for (int o = 32; o > 0; o >>= 1) better(gv, gi, __shfl_xor(gv, o, 64), __shfl_xor(gi, o, 64));
+    // rv / ri: every thread read them in publish before its closing barrier
     if (lane == 0) {
-      rv[wave] = bv;
-      ri[wave] = bi;
+      rv[wave] = gv;
+      ri[wave] = gi;
     }
     __syncthreads();
     if (tid == 0) {
@@ -666,15 +687,16 @@ __global__ __launch_bounds__(PT) void qrcp_persist_kernel(const DevProb* __restr
     const int p = s_p;
     if (i == 0) nu0 = best;
     if (best <= 0.0 || best <= rtol * nu0) break;
-    if (P.kfail >= 0 && i > P.kfail && m > d) break;
+    if (dp.p.kfail >= 0 && i > dp.p.kfail && m > d) break;
     const int gp = p / CPG;  // the workgroup that published column p
     const double* xp = w.cbuf + ((long long)(i & 1) * nslot + dp.g0 + gp) * ldcb;
-    // the winner's rows i..d-1 into LDS, all loads in flight together
+    // the winner's rows i..d-1 into LDS (zero elsewhere), loads in flight together
 #pragma unroll
     for (int t = 0; t < T / PW; ++t) {
       const int r = tid + PT * t;
-      const double v = ld_dev(xp + min(max(r, i), d - 1));  // in bounds, unconditional
-      u[r] = (r >= i && r < d) ? v : 0.0;
+      const bool in = r >= i && r < d;
+      const double v = ld_dev(xp + (in ? r : i));
+      u[r] = in ? v : 0.0;
     }
     __syncthreads();
     const double x0 = u[i];
@@ -699,42 +721,61 @@ __global__ __launch_bounds__(PT) void qrcp_persist_kernel(const DevProb* __restr
       w.piv[dp.aoff + i] = p;
     }
     __syncthreads();
-    // rows below i are finished: slices t < i/64 are skipped (uniform
-    // branch).  The C columns go through each phase together, so their
-    // dependency chains and reductions overlap.
+    // rows below i are finished: groups of slices below i/64 are skipped,
+    // and u is zero on the finished rows of the groups that run.  The C
+    // columns go through each phase together, so their dependency chains
+    // and reductions overlap.
     const int ti = i >> 6;
-    double f[C], s2[C];
+    double f[C];
 #pragma unroll
     for (int c = 0; c < C; ++c) f[c] = 0.0;
 #pragma unroll
-    for (int t = 0; t < T; ++t) {
-      if (t < ti) continue;
-      const double ut = u[lane + 64 * t];
+    for (int g = 0; g < T / PG; ++g) {
+      if (PG * g + PG <= ti) continue;
+      __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-      for (int c = 0; c < C; ++c) f[c] = fma(ut, y[c][t], f[c]);
+      for (int tt = 0; tt < PG; ++tt) {
+        const int t = PG * g + tt;
+        const double ut = u[lane + 64 * t];
+#pragma unroll
+        for (int c = 0; c < C; ++c) f[c] = fma(ut, y[c][t], f[c]);
+      }
     }
     wave_sum_n<C>(f);
+    asm volatile("" ::: "memory");  // u is read again below rather than kept in registers
 #pragma unroll
     for (int c = 0; c < C; ++c) {
       const bool live = !((sel >> c) & 1u) && jb + c < m;  // pivots stay as they are
       f[c] = live ? tau * f[c] : 0.0;
-      s2[c] = 0.0;
     }
+    // norms of the rows below i: slice i/64 counts the lanes past i only
+    double s2[C];
 #pragma unroll
-    for (int t = 0; t < T; ++t) {
-      if (t < ti) continue;
-      const double ut = u[lane + 64 * t];
-      const bool below = t > ti || lane > (i & 63);
+    for (int c = 0; c < C; ++c) s2[c] = 0.0;
+    const double keep = lane > (i & 63) ? 1.0 : 0.0;
 #pragma unroll
-      for (int c = 0; c < C; ++c) {
-        const double v = fma(-f[c], ut, y[c][t]);
-        y[c][t] = v;
-        if (below) s2[c] = fma(v, v, s2[c]);
+    for (int g = 0; g < T / PG; ++g) {
+      if (PG * g + PG <= ti) continue;
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int tt = 0; tt < PG; ++tt) {
+        const int t = PG * g + tt;
+        const double ut = u[lane + 64 * t];
+        const double wt = t > ti ? 1.0 : (t == ti ? keep : 0.0);
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+          const double v = fma(-f[c], ut, y[c][t]);
+          y[c][t] = v;
+          s2[c] = fma(v * wt, v, s2[c]);
+        }
       }
     }
     wave_sum_n<C>(s2);
+    bv = -1.0;
+    bi = INT_MAX;
 #pragma unroll
-    for (int c = 0; c < C; ++c) nv[c] = sqrt(s2[c]);
+    for (int c = 0; c < C; ++c)
+      if (!((sel >> c) & 1u) && jb + c < m) better(bv, bi, sqrt(s2[c]), jb + c);
     k = i + 1;
     if (i + 1 < dp.kmax) publish(i + 1);
   }
@@ -743,11 +784,10 @@ __global__ __launch_bounds__(PT) void qrcp_persist_kernel(const DevProb* __restr
   for (int c = 0; c < C; ++c) {
     const int j = jb + c;
     if (j >= m) continue;
+    double* __restrict__ out = dp.p.W + (long long)j * dp.p.ldw + lane;
 #pragma unroll
-    for (int t = 0; t < T; ++t) {
-      const int r = lane + 64 * t;
-      if (r < d) P.W[(long long)j * P.ldw + r] = y[c][t];
-    }
+    for (int t = 0; t < T; ++t)
+      if (lane < d - 64 * t) out[64 * t] = y[c][t];
     asm volatile("" ::: "memory");
   }
 }
@@ -849,8 +889,8 @@ size_t id_workspace_bytes(const IdProblem* probs, int nprob) {
     if (!probs[q].W) tw += (long long)probs[q].m * probs[q].d;
   }
   return al(2 * tm * 8) + al(tm * 4) + al(tk * 8) + al(tk * 4) + 3 * al((size_t)nprob * 8) +
-         al(4) + al(2 * tg * 8) + al(2 * tg * 4) + al(2 * tg * dm * 8) + al(2 * tg * 4) +
-         al(4) + al(tw * 8) + 4096;
+         al(4) + al(2 * tg * 8) + al(2 * tg * 4) + al(2 * std::min(tg, kCandSlots) * ldcb_of(dm) * 8) +
+         al(2 * tg * 4) + al(4) + al(tw * 8) + 4096;
 }
 
 // Register-resident classes (wavefronts, columns per wavefront, rows per
@@ -873,19 +913,22 @@ struct PVariant {
   const void* fn;
 };
 static const PVariant kPVariants[] = {
-    {8, 20, reinterpret_cast<const void*>(&qrcp_persist_kernel<8, 20>)},
-    {16, 12, reinterpret_cast<const void*>(&qrcp_persist_kernel<16, 12>)},
-    {24, 8, reinterpret_cast<const void*>(&qrcp_persist_kernel<24, 8>)},
-    {32, 6, reinterpret_cast<const void*>(&qrcp_persist_kernel<32, 6>)},
-    {40, 4, reinterpret_cast<const void*>(&qrcp_persist_kernel<40, 4>)},
+    {8, 8, reinterpret_cast<const void*>(&qrcp_persist_kernel<8, 8>)},
+    {16, 5, reinterpret_cast<const void*>(&qrcp_persist_kernel<16, 5>)},
+    {24, 4, reinterpret_cast<const void*>(&qrcp_persist_kernel<24, 4>)},
+    {32, 3, reinterpret_cast<const void*>(&qrcp_persist_kernel<32, 3>)},
+    {40, 2, reinterpret_cast<const void*>(&qrcp_persist_kernel<40, 2>)},
 };
 
 // cost model constants (measured on gfx950): time per pivot step of a
-// persistent launch, the floor of one step-path launch, and the HBM rate the
-// step path reaches
-constexpr double kPersistStepUs = 16.0;
+// persistent launch, a base plus a term that grows with the workgroups of its
+// widest problem (each one publishes a candidate every step: 7.5 us at 4,
+// 10.7 us at 167); the floor of one step-path launch, and the rate at which
+// the step path moves the active rows
+constexpr double kPersistStepUs = 7.3;
+constexpr double kPersistStepUsPerWg = 0.02;
 constexpr double kStepFloorUs = 25.0;
-constexpr double kStepBytesPerS = 4.5e12;
+constexpr double kStepBytesPerS = 3.0e12;
 
 static int resident_workgroups(const void* fn) {
   int dev = 0, cus = 0, per = 0;
@@ -926,14 +969,14 @@ static hipError_t run_persistent(std::vector<DevProb>& h, const std::vector<int>
   while (kPVariants[v].T * 64 < dmax) ++v;
   const PVariant& pv = kPVariants[v];
   const int cpg = PW * pv.C;
-  const int maxwg = resident_workgroups(pv.fn);
+  const int maxwg = (int)std::min<long long>(resident_workgroups(pv.fn), w.nslots);
   if (!force_pers) {
     // persistent: launches run one after another, each ~kPersistStepUs per
     // step; step path: one launch per step for the whole batch, bound by
     // the larger of the launch floor and the traffic (read + write of the
     // active rows)
     double t_pers = 0.0, bytes = 0.0;
-    int smax = 0, nwg = 0, lsteps = 0;
+    int smax = 0, nwg = 0, lsteps = 0, lg = 0;
     for (int q : cand) {
       const IdProblem& p = h[q].p;
       int steps = h[q].kmax;
@@ -943,15 +986,24 @@ static hipError_t run_persistent(std::vector<DevProb>& h, const std::vector<int>
       const int G = (p.m + cpg - 1) / cpg;
       if (G > maxwg) continue;
       if (nwg + G > maxwg) {
-        t_pers += lsteps * kPersistStepUs;
+        t_pers += lsteps * (kPersistStepUs + kPersistStepUsPerWg * lg);
         nwg = 0;
         lsteps = 0;
+        lg = 0;
       }
       nwg += G;
       lsteps = std::max(lsteps, steps);
+      lg = std::max(lg, G);
     }
-    t_pers += lsteps * kPersistStepUs;
+    t_pers += lsteps * (kPersistStepUs + kPersistStepUsPerWg * lg);
     const double t_step = smax * std::max(kStepFloorUs, bytes * 1e6 / kStepBytesPerS);
+    const char* vb = std::getenv("HSS_VERBOSE");
+    if (vb && vb[0] >= '2') {
+      long long sm = 0;
+      for (int q : cand) sm += h[q].p.m;
+      std::fprintf(stderr, "[hss-id] cost: %zu problems, sum m %lld, max d %d, <= %d steps, %d x %d columns resident: "
+                   "persistent %.0f us, step %.0f us\n", cand.size(), sm, dmax, smax, maxwg, cpg, t_pers, t_step);
+    }
     if (maxwg <= 0 || t_pers >= t_step) {
       rest.insert(rest.end(), cand.begin(), cand.end());
       return hipSuccess;
