@@ -71,7 +71,9 @@ struct Work {
   double* cbuf;    // 2 * min(tg, kCandSlots) * ldcb: candidate columns (persistent path)
   long long ldcb;  // max d rounded up to a multiple of 512 (a whole column of registers)
   long long nslots;  // min(tg, kCandSlots): workgroups a persistent launch may have
-  int* stamp;      // 2 * tg: step stamp of each published candidate (persistent path)
+  long long krec;    // max kmax: steps a persistent launch may publish
+  unsigned long long* rec;  // 2 * nslots * kmax: one published candidate record per
+                            // workgroup and step, zeroed before each persistent launch
   int* err;        // 1: a wait for a candidate timed out (persistent path)
   double* W;     // sum(m * d)
 };
@@ -80,7 +82,7 @@ size_t al(size_t b) { return (b + 255) / 256 * 256; }
 
 // persistent path: at most this many workgroups per launch (candidate
 // column slots per step parity), and the stride of a published column
-constexpr long long kCandSlots = 2048;
+constexpr long long kCandSlots = 1024;
 long long ldcb_of(long long dmax) { return (dmax + 511) / 512 * 512; }
 
 // pivot steps a problem can take
@@ -92,11 +94,12 @@ int kmax_of(const IdProblem& p) {
 void carve(const IdProblem* probs, int nprob, void* base, Work& w, long long& tm, long long& tk,
            long long& tw) {
   tm = tk = tw = 0;
-  long long tg = 0, dm = 1;
+  long long tg = 0, dm = 1, km = 1;
   for (int q = 0; q < nprob; ++q) {
     tg += (probs[q].m + SW - 1) / SW;
     tm += probs[q].m;
     tk += kmax_of(probs[q]);
+    km = std::max<long long>(km, kmax_of(probs[q]));
     dm = std::max<long long>(dm, probs[q].d);
     if (!probs[q].W) tw += (long long)probs[q].m * probs[q].d;
   }
@@ -119,7 +122,8 @@ void carve(const IdProblem* probs, int nprob, void* base, Work& w, long long& tm
   w.ldcb = ldcb_of(dm);
   w.nslots = std::min(tg, kCandSlots);
   w.cbuf = reinterpret_cast<double*>(take(2 * w.nslots * w.ldcb * 8));
-  w.stamp = reinterpret_cast<int*>(take(2 * tg * 4));
+  w.krec = km;
+  w.rec = reinterpret_cast<unsigned long long*>(take(2 * w.nslots * km * 8));
   w.err = reinterpret_cast<int*>(take(4));
   w.W = reinterpret_cast<double*>(take(tw * 8));
 }
@@ -517,23 +521,28 @@ __global__ __launch_bounds__(ST) void id_step_kernel(const DevProb* __restrict__
 // zero, so no row needs a bounds test inside the step loop).  Two
 // wavefronts share each SIMD and every value lives in architectural
 // registers.  After each step the workgroup publishes its best remaining
-// column -- norm, index and values -- in a slot of its own (double-buffered
-// by step parity) and then stamps the slot with the step number.  Every
-// workgroup of the problem waits for the G stamps of the step, reduces the
-// same candidates the same way, reads the winner's published values as the
-// reflector and updates its own columns.  Per step, global memory carries
-// only the candidates and one column per workgroup.
+// column: the values go to a column slot of its own (double-buffered by step
+// parity), then norm and index go to a 16-byte record of its own for that
+// step.  Every workgroup of the problem waits for the G records of the step,
+// reduces the same candidates the same way, reads the winner's published
+// values as the reflector and updates its own columns.  Per step, global
+// memory carries only the candidates and one column per workgroup.
 //
-// Published data is written and read with device-scope (coherent) accesses;
-// a workgroup stamps its slot only after its data stores have completed.  No
-// read-modify-write atomics are used.  The wait for a stamp is bounded: a
-// workgroup that waits too long raises the error flag and leaves, and so
-// does every workgroup that sees the flag; the factorization is then
-// reported as failed and nothing is written back.
+// A record is two 64-bit words, each written and read whole (aligned 64-bit
+// device-scope accesses), in memory zeroed before the launch and written once
+// per launch: the norm with its sign bit flipped (never zero: norms are +0 or
+// more, or -1 for no candidate) and (step + 1) << 32 | index.  A reader takes
+// a record once both words are non-zero and the step matches, so one poll
+// returns the candidate.  A workgroup writes its record only after its column
+// stores have completed.  No read-modify-write atomics are used.  The wait
+// for a record is bounded: a workgroup that waits too long raises the error
+// flag and leaves, and so does every workgroup that sees the flag; the
+// factorization is then reported as failed and nothing is written back.
 // ---------------------------------------------------------------------------
 constexpr int PW = 8;        // wavefronts per persistent workgroup (two per SIMD)
 constexpr int PT = PW * 64;  // threads per persistent workgroup
 constexpr int kSpinLimit = 1 << 22;
+constexpr unsigned long long kSignBit = 1ull << 63;
 
 template <typename V>
 __device__ __forceinline__ void st_dev(V* p, V v) {
@@ -610,10 +619,6 @@ __global__ __launch_bounds__(PT) void qrcp_persist_kernel(const DevProb* __restr
 #pragma unroll
     for (int t = 1; t < PW; ++t) better(v, ix, rv[t], ri[t]);
     const long long slot = (long long)(i & 1) * nslot + blockIdx.x;
-    if (tid == 0) {
-      st_dev(w.cand_v + slot, v);
-      st_dev(w.cand_i + slot, ix);
-    }
     if (ix >= jb && ix < jb + C) {  // uniform: the owning wavefront writes
       double* dst = w.cbuf + slot * ldcb + lane;
       asm volatile("" : "+v"(dst));  // addresses formed here, not hoisted out of the step loop
@@ -631,18 +636,27 @@ __global__ __launch_bounds__(PT) void qrcp_persist_kernel(const DevProb* __restr
     }
     __builtin_amdgcn_s_waitcnt(0);  // this thread's stores have completed
     __syncthreads();                // ... and every other thread's
-    if (tid == 0) st_dev(w.stamp + slot, i + 1);
+    if (tid == 0) {
+      unsigned long long* r = w.rec + 2 * ((long long)i * nslot + blockIdx.x);
+      st_dev(r, (unsigned long long)__double_as_longlong(v) ^ kSignBit);
+      st_dev(r + 1, ((unsigned long long)(i + 1) << 32) | (unsigned)ix);
+    }
   };
 
   // wait for the problem's G candidates of step i; false on a timeout
   auto gather = [&](int i) __attribute__((always_inline)) -> bool {
-    const long long base = (long long)(i & 1) * nslot + dp.g0;
+    const unsigned long long* recs = w.rec + 2 * ((long long)i * nslot + dp.g0);
+    const unsigned long long want = (unsigned long long)(i + 1);
     double gv = -1.0;
     int gi = INT_MAX;
     bool ok = true;
     for (int t = tid; t < dp.G && ok; t += PT) {
       int spins = 0;
-      while (ld_dev(w.stamp + base + t) != i + 1) {
+      unsigned long long a, b;
+      while (true) {
+        a = ld_dev(recs + 2 * t);
+        b = ld_dev(recs + 2 * t + 1);
+        if (a != 0 && (b >> 32) == want) break;
         if ((++spins & 63) == 0) {
           if (ld_dev(w.err)) {
             ok = false;
@@ -656,7 +670,7 @@ __global__ __launch_bounds__(PT) void qrcp_persist_kernel(const DevProb* __restr
         }
         __builtin_amdgcn_s_sleep(1);
       }
-      if (ok) better(gv, gi, ld_dev(w.cand_v + base + t), ld_dev(w.cand_i + base + t));
+      if (ok) better(gv, gi, __longlong_as_double((long long)(a ^ kSignBit)), (int)(unsigned)b);
     }
     if (!ok) s_ok = 0;
 #pragma unroll
@@ -880,17 +894,19 @@ __global__ __launch_bounds__(NT) void trsm_diag_kernel(const DiagDesc* __restric
 }  // namespace
 
 size_t id_workspace_bytes(const IdProblem* probs, int nprob) {
-  long long tm = 0, tk = 0, tw = 0, tg = 0, dm = 1;
+  long long tm = 0, tk = 0, tw = 0, tg = 0, dm = 1, km = 1;
   for (int q = 0; q < nprob; ++q) {
     tg += (probs[q].m + SW - 1) / SW;
     tm += probs[q].m;
     tk += kmax_of(probs[q]);
+    km = std::max<long long>(km, kmax_of(probs[q]));
     dm = std::max<long long>(dm, probs[q].d);
     if (!probs[q].W) tw += (long long)probs[q].m * probs[q].d;
   }
+  const long long ns = std::min(tg, kCandSlots);
   return al(2 * tm * 8) + al(tm * 4) + al(tk * 8) + al(tk * 4) + 3 * al((size_t)nprob * 8) +
-         al(4) + al(2 * tg * 8) + al(2 * tg * 4) + al(2 * std::min(tg, kCandSlots) * ldcb_of(dm) * 8) +
-         al(2 * tg * 4) + al(4) + al(tw * 8) + 4096;
+         al(4) + al(2 * tg * 8) + al(2 * tg * 4) + al(2 * ns * ldcb_of(dm) * 8) + al(2 * ns * km * 8) +
+         al(4) + al(tw * 8) + 4096;
 }
 
 // Register-resident classes (wavefronts, columns per wavefront, rows per
@@ -1041,7 +1057,9 @@ static hipError_t run_persistent(std::vector<DevProb>& h, const std::vector<int>
     const DevProb* dprobs = static_cast<const DevProb*>(st.push(h.data(), sizeof(DevProb) * h.size()));
     const int* dwg = static_cast<const int*>(st.push(wgp.data(), wgp.size() * 4));
     if (!dprobs || !dwg) return hipErrorOutOfMemory;
-    hipError_t e = hipMemsetAsync(w.stamp, 0, 2 * (size_t)nwg * 4, s);
+    int kb = 1;  // the launch's records: steps 0..kb-1 of nwg workgroups, zeroed
+    for (int q : batch) kb = std::max(kb, h[q].kmax);
+    hipError_t e = hipMemsetAsync(w.rec, 0, (size_t)kb * nwg * 16, s);
     if (e == hipSuccess && done.empty()) e = hipMemsetAsync(w.err, 0, 4, s);
     if (e != hipSuccess) return e;
     Work wa = w;
