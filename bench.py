@@ -224,7 +224,12 @@ def run_batched(args) -> int:
               file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    stats = [step() for _ in range(args.steps)]
+    stats = []
+    for k in range(args.steps):
+        tk = time.perf_counter()
+        stats.append(step())
+        print(f"[bench] step {k}: {1e3 * (time.perf_counter() - tk):.1f} ms (compression "
+              f"{stats[-1][0]['t_total_ms']:.1f} ms)", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     ms = (time.perf_counter() - t0) * 1e3 / max(1, args.steps)
     sts = [s[0] for s in stats]

@@ -13,7 +13,9 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 #include "hss_handle.h"
@@ -64,32 +66,103 @@ double now_ms() {
 namespace hss {
 
 namespace {
-std::once_flag g_pool_once;
+// Freed device blocks of 1 MB and more are kept for reuse, by size class (four
+// classes per power of two), up to a quarter of the device's memory: the
+// runtime pool returns freed memory to the system at synchronizations, and
+// mapping it again can take seconds when a step frees and allocates tens of
+// GB (batched compressions).  A reused block is ordered after its last use
+// by an event recorded when it was freed.
+struct CachedBlock {
+  void* p;
+  hipEvent_t ev;  // recorded on the freeing stream
+};
+std::mutex g_dev_mu;
+std::unordered_map<size_t, std::vector<CachedBlock>> g_dev_free;  // by class
+std::unordered_map<void*, size_t> g_dev_live;                     // class of cached-size blocks
+size_t g_dev_cached = 0;
+size_t g_dev_cap = 0;
+std::once_flag g_dev_once;
+
+constexpr size_t kCacheMin = (size_t)1 << 20;
+
+size_t size_class(size_t b) {
+  if (b < kCacheMin) return 0;
+  size_t top = kCacheMin;
+  while (top * 2 <= b) top *= 2;
+  const size_t step = top / 4;
+  return (b + step - 1) / step * step;
 }
 
-void* pool_alloc(size_t bytes, hipStream_t s) {
-  // keep up to a quarter of the device's memory cached in the pool between
-  // frees instead of returning it at every synchronization
-  std::call_once(g_pool_once, [] {
-    int dev = 0;
-    hipMemPool_t pool;
-    size_t fr = 0, tot = 0;
-    if (hipGetDevice(&dev) == hipSuccess && hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess &&
-        hipMemGetInfo(&fr, &tot) == hipSuccess) {
-      uint64_t thr = tot / 4;
-      hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
+// frees every cached block, each after its last use, on stream s (lock held)
+void trim_cache(hipStream_t s) {
+  for (auto& kv : g_dev_free)
+    for (CachedBlock& c : kv.second) {
+      hipStreamWaitEvent(s, c.ev, 0);
+      hipEventDestroy(c.ev);
+      hipFreeAsync(c.p, s);
     }
+  g_dev_free.clear();
+  g_dev_cached = 0;
+}
+}  // namespace
+
+void* pool_alloc(size_t bytes, hipStream_t s) {
+  std::call_once(g_dev_once, [] {
+    size_t fr = 0, tot = 0;
+    if (hipMemGetInfo(&fr, &tot) == hipSuccess) g_dev_cap = tot / 4;
   });
+  const size_t cls = size_class(bytes);
   void* p = nullptr;
-  if (hipMallocAsync(&p, bytes, s) != hipSuccess) {
-    (void)hipGetLastError();
-    return nullptr;
+  if (cls == 0) {
+    if (hipMallocAsync(&p, bytes, s) != hipSuccess) {
+      (void)hipGetLastError();
+      return nullptr;
+    }
+    return p;
   }
+  std::lock_guard<std::mutex> lk(g_dev_mu);
+  auto it = g_dev_free.find(cls);
+  if (it != g_dev_free.end() && !it->second.empty()) {
+    CachedBlock c = it->second.back();
+    it->second.pop_back();
+    g_dev_cached -= cls;
+    hipStreamWaitEvent(s, c.ev, 0);
+    hipEventDestroy(c.ev);
+    g_dev_live[c.p] = cls;
+    return c.p;
+  }
+  if (hipMallocAsync(&p, cls, s) != hipSuccess) {
+    (void)hipGetLastError();
+    if (g_dev_cached == 0) return nullptr;
+    trim_cache(s);  // cached blocks of other classes go back, then try again
+    if (hipMallocAsync(&p, cls, s) != hipSuccess) {
+      (void)hipGetLastError();
+      return nullptr;
+    }
+  }
+  g_dev_live[p] = cls;
   return p;
 }
 
 void pool_free(void* p, hipStream_t s) {
-  if (p) hipFreeAsync(p, s);
+  if (!p) return;
+  std::lock_guard<std::mutex> lk(g_dev_mu);
+  auto it = g_dev_live.find(p);
+  if (it == g_dev_live.end()) {  // below the cached sizes
+    hipFreeAsync(p, s);
+    return;
+  }
+  const size_t cls = it->second;
+  g_dev_live.erase(it);
+  hipEvent_t ev = nullptr;
+  if (g_dev_cached + cls > g_dev_cap || hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess ||
+      hipEventRecord(ev, s) != hipSuccess) {
+    if (ev) hipEventDestroy(ev);
+    hipFreeAsync(p, s);
+    return;
+  }
+  g_dev_free[cls].push_back(CachedBlock{p, ev});
+  g_dev_cached += cls;
 }
 
 void* Arena::alloc(size_t bytes) {
@@ -155,6 +228,8 @@ namespace {
 // and free pinned memory each time.
 std::mutex g_pin_mu;
 std::vector<std::pair<size_t, char*>> g_pin_free;
+size_t g_pin_bytes = 0;
+constexpr size_t kPinKeep = (size_t)1 << 30;
 
 char* pinned_get(size_t bytes) {
   {
@@ -163,6 +238,7 @@ char* pinned_get(size_t bytes) {
       if (g_pin_free[q].first == bytes) {
         char* p = g_pin_free[q].second;
         g_pin_free.erase(g_pin_free.begin() + q);
+        g_pin_bytes -= bytes;
         return p;
       }
   }
@@ -175,8 +251,9 @@ void pinned_put(char* p, size_t bytes) {
   if (!p) return;
   {
     std::lock_guard<std::mutex> lk(g_pin_mu);
-    if (g_pin_free.size() < 64) {
+    if (g_pin_bytes + bytes <= kPinKeep) {  // every handle of a large batch holds one
       g_pin_free.emplace_back(bytes, p);
+      g_pin_bytes += bytes;
       return;
     }
   }
