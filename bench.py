@@ -322,7 +322,7 @@ def run_batched(args) -> int:
 
 def run_serve(args) -> int:
     """The serving workload: requests of compress + ULV factor + solve arrive
-    as a Poisson process at 200 per second (seed 6).  Each request draws its
+    as a Poisson process at --serve-rate per second (default 200, seed 6).  Each request draws its
     matrix from a pool of 16 pre-assembled matrices -- N log-uniform in
     [512, 32768], the 2-D log kernel on a perturbed circle or the 3-D
     Gaussian kernel (k-d ordered) with probability 1/2 each, FP32 storage --
@@ -354,7 +354,8 @@ def run_serve(args) -> int:
     pick = g.integers(0, 16, size=nreq)
     rtols = g.choice([1e-4, 1e-6], size=nreq)
     nrhs = g.integers(1, 65, size=nreq)
-    gaps = g.exponential(1.0 / 200.0, size=nreq)
+    rate = float(args.serve_rate)
+    gaps = g.exponential(1.0 / rate, size=nreq)
     rhs = [torch.from_numpy(W.normal_rhs(int(pool[q].shape[0]), int(k), 6000 + i)).to(dev)
            for i, (q, k) in enumerate(zip(pick, nrhs))]
     torch.cuda.synchronize()
@@ -363,7 +364,7 @@ def run_serve(args) -> int:
     budget = int(0.5 * torch.cuda.mem_get_info()[1])
     srv = P.HSSServer(hbm_budget=budget, max_batch=32, workers=4)
     kw0 = dict(d0=64, dd=32, d_max=1024, leaf_size=128, p_margin=32, sample_prec="bf16x3")
-    print(f"[bench] serving {nreq} requests at 200/s", file=sys.stderr, flush=True)
+    print(f"[bench] serving {nreq} requests at {rate:g}/s", file=sys.stderr, flush=True)
     t_start = time.perf_counter()
     t_next = t_start
     tickets = []
@@ -417,7 +418,7 @@ def run_serve(args) -> int:
         "dtype": "bf16x3 sampling, f64 ID and ULV",
         "data": "synthetic",
         "config": {
-            "workload": "serve: Poisson arrivals at 200/s (seed 6), pool of 16 FP32 matrices N log-uniform "
+            "workload": f"serve: Poisson arrivals at {rate:g}/s (seed 6), pool of 16 FP32 matrices N log-uniform "
                         "in [512, 32768] (log kernel on a circle or Gaussian kernel in 3-D), rtol in "
                         "{1e-4, 1e-6}, nrhs in {1..64}, leaf 128, d0 64, dd 32, p_margin 32, BF16X3 sampling",
             "requests": nreq, "workers": 4, "max_batch": 32, "hbm_budget": "50% of device memory",
@@ -443,6 +444,7 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="gauss65536", choices=sorted(WORKLOADS) + ["batched512", "serve"])
     ap.add_argument("--serve-requests", type=int, default=400, help="requests of the serve workload")
+    ap.add_argument("--serve-rate", type=float, default=200.0, help="Poisson arrival rate of the serve workload")
     ap.add_argument("--rtol", type=float, default=None)
     ap.add_argument("--p-margin", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
