@@ -164,6 +164,24 @@ hss_status hss_compress_batched(int nmat, const void* const* A, int dtype, const
 hss_status hss_matvec(hss_handle h, int nrhs, const double* x, long long ldx,
                       double* b, long long ldb, void* stream);
 
+/*
+ * b[i] = A_HSS[i] x[i] (Alg. 2) for nmat compressed handles at once, each
+ * as hss_matvec computes it: every phase of Alg. 2 (the upward sweep of one
+ * height, the downward sweep of one height, the leaves) is one batched
+ * launch over all matrices, heights counted from the leaves.
+ *  h        nmat distinct compressed handles (matrices of any sizes).
+ *  x[i]     DEVICE n_i x nrhs, leading dimension ldx[i] >= nrhs.
+ *  b[i]     DEVICE n_i x nrhs, leading dimension ldb[i] >= nrhs; must not
+ *           overlap x[i].
+ *  h, x, b, ldx, ldb are host arrays of nmat entries.
+ * Uses h[0]'s workspace: not concurrently with another call on h[0].
+ * Returns HSS_OK, HSS_ERR_STATE (a handle not compressed) or HSS_ERR_ARG;
+ * nothing is computed on an error.  Host-synchronous; all work on `stream`.
+ */
+hss_status hss_matvec_batched(int nmat, const hss_handle* h, int nrhs, const double* const* x,
+                              const long long* ldx, double* const* b, const long long* ldb,
+                              void* stream);
+
 /* ULV-like factorization of the HSS form (Alg. 3); root LU with partial
  * pivoting.  Host-synchronous. */
 hss_status hss_factor(hss_handle h, void* stream);

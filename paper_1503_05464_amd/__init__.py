@@ -30,7 +30,8 @@ HSS_SAMPLE_BF16X3 = 2
 _PREC = {"f64": HSS_SAMPLE_F64, "f32": HSS_SAMPLE_F32, "bf16x3": HSS_SAMPLE_BF16X3}
 
 EXPORTED = [
-    "hss_default_opts", "hss_compress", "hss_compress_batched", "hss_matvec", "hss_factor",
+    "hss_default_opts", "hss_compress", "hss_compress_batched", "hss_matvec", "hss_matvec_batched",
+    "hss_factor",
     "hss_solve", "hss_stats",
     "hss_ranks", "hss_export_node", "hss_import", "hss_destroy", "hss_last_error",
     "hss_random_normal", "hss_sample", "hss_id_batched",
@@ -103,6 +104,7 @@ def lib() -> C.CDLL:
         L.hss_compress_batched.argtypes = [i, vp, i, vp, vp, C.POINTER(hss_tree), C.POINTER(hss_opts),
                                            vp, vp, vp]
         L.hss_matvec.argtypes = [vp, i, vp, ll, vp, ll, vp]
+        L.hss_matvec_batched.argtypes = [i, vp, i, vp, vp, vp, vp, vp]
         L.hss_server_default_opts.argtypes = [C.POINTER(hss_server_opts)]
         L.hss_server_default_opts.restype = None
         L.hss_server_create.argtypes = [C.POINTER(hss_server_opts), C.POINTER(vp)]
@@ -276,6 +278,32 @@ def hss_matvec(h: HSSHandle, x, b=None, stream=None):
     _check(lib().hss_matvec(h.ptr, x2.shape[1], _ptr(x2), x2.stride(0), _ptr(b2), b2.stride(0),
                             _stream(stream)))
     return b2.reshape(-1) if vec else b2
+
+
+def hss_matvec_batched(hs, xs, bs=None, stream=None):
+    """b[i] = A_HSS[i] x[i] for several handles in one call (every phase of
+    the matvec is one launch over all of them).  xs: CUDA float64 tensors,
+    n_i x nrhs (the same nrhs for all) with unit column stride."""
+    import torch
+
+    if len(hs) != len(xs):
+        raise ValueError("one x per handle")
+    if not hs:
+        return []
+    nrhs = xs[0].shape[1]
+    for h, x in zip(hs, xs):
+        if x.dim() != 2 or x.dtype != torch.float64 or x.stride(1) != 1 or x.shape[0] != h.n or x.shape[1] != nrhs:
+            raise ValueError("each x must be float64, n_i x nrhs with unit column stride")
+    if bs is None:
+        bs = [torch.empty_like(x, memory_format=torch.contiguous_format) for x in xs]
+    hp = np.array([h.ptr.value if hasattr(h.ptr, "value") else h.ptr for h in hs], dtype=np.uint64)
+    xp = np.array([x.data_ptr() for x in xs], dtype=np.uint64)
+    bp = np.array([b.data_ptr() for b in bs], dtype=np.uint64)
+    ldx = np.array([x.stride(0) for x in xs], dtype=np.int64)
+    ldb = np.array([b.stride(0) for b in bs], dtype=np.int64)
+    _check(lib().hss_matvec_batched(len(hs), _np_ptr(hp), nrhs, _np_ptr(xp), _np_ptr(ldx), _np_ptr(bp),
+                                    _np_ptr(ldb), _stream(stream)))
+    return bs
 
 
 def hss_factor(h: HSSHandle, stream=None) -> None:

@@ -1100,173 +1100,227 @@ void free_handle(hss_handle_s* p) {
 // ---------------------------------------------------------------------------
 namespace hss {
 
-hss_status matvec_impl(Handle& H, int nrhs, const double* x, long long ldx, double* b,
-                       long long ldb, hipStream_t s) {
-  std::vector<Node>& nd = H.nodes;
-  H.staging.stream = s;
-  if (nd[0].leaf()) {
-    GemmDesc g{};
-    g.M = g.K = (int)H.n;
-    g.N = nrhs;
-    g.A = nd[0].D;
-    g.lda = H.n;
-    g.B = Seg{x, nullptr, ldx, INT_MAX, nullptr};
-    g.D = SegOut{b, nullptr, ldb, INT_MAX, nullptr};
-    g.alpha = 1.0;
-    HIPCHK(launch_gemm_batched(&g, 1, H.staging, s));
-    HIPCHK(hipStreamSynchronize(s));
-    H.staging.reset();
-    return HSS_OK;
-  }
-  // workspace: y (kc), z (kr), w (mr) per node, nrhs columns each
-  std::vector<long long> oy(nd.size()), oz(nd.size()), ow(nd.size());
+// One matvec b = A_HSS x of a batch (Alg. 2).
+struct MvJob {
+  Handle* H;
+  int nrhs;
+  const double* x;
+  long long ldx;
+  double* b;
+  long long ldb;
+};
+
+// Alg. 2 for several handles at once: every phase (upward sweep of a height,
+// downward sweep of a height, leaves) is one batched GEMM launch over all of
+// them, heights aligned from the leaves.  Workspace and descriptor staging
+// come from the lead handle L.  Host-synchronous at the end (the descriptor
+// tables live in the staging area until their copies ran).
+hss_status matvec_many(Handle& L, std::vector<MvJob>& jobs, hipStream_t s) {
+  L.staging.stream = s;
+  // workspace: y (kc), z (kr), w (mr) per node and job, nrhs columns each
+  std::vector<std::vector<long long>> oy(jobs.size()), oz(jobs.size()), ow(jobs.size());
   long long tot = 0;
-  for (size_t t = 0; t < nd.size(); ++t) {
-    oy[t] = tot;
-    tot += (long long)nd[t].kc * nrhs;
-    oz[t] = tot;
-    tot += (long long)nd[t].kr * nrhs;
-    ow[t] = tot;
-    tot += (long long)nd[t].mr * nrhs;
-  }
-  double* ws = static_cast<double*>(H.work_mv.ensure((size_t)tot * 8 + 8, s));
-  if (!ws) return fail(HSS_ERR_ALLOC, "matvec workspace");
-  auto Y = [&](int t) { return ws + oy[t]; };
-  auto Z = [&](int t) { return ws + oz[t]; };
-  auto Wv = [&](int t) { return ws + ow[t]; };
-  std::vector<GemmDesc> gd;
-  // upward: y_tau = V^T x_in
-  for (int h = 0; h < H.height; ++h) {
-    gd.clear();
-    for (int t : H.levels[h]) {
-      const Node& v = nd[t];
-      Seg src{};
-      if (v.leaf()) {
-        src = Seg{x + (long long)v.lo * ldx, nullptr, ldx, INT_MAX, nullptr};
-      } else {
-        src = Seg{Y(v.left), Y(v.right), nrhs, nd[v.left].kc, nullptr};
-      }
-      GemmDesc g{};
-      g.M = v.kc;
-      g.N = nrhs;
-      g.K = v.mc - v.kc;
-      g.A = v.Ec;
-      g.lda = v.kc;
-      g.transA = 1;
-      g.B = src;
-      g.B.map = v.perm_c + v.kc;
-      g.C = src;
-      g.C.map = v.perm_c;
-      g.D = SegOut{Y(t), nullptr, nrhs, INT_MAX, nullptr};
-      g.alpha = g.beta = 1.0;
-      gd.push_back(g);
+  int maxh = 0;
+  for (size_t j = 0; j < jobs.size(); ++j) {
+    const std::vector<Node>& nd = jobs[j].H->nodes;
+    const int nrhs = jobs[j].nrhs;
+    oy[j].resize(nd.size());
+    oz[j].resize(nd.size());
+    ow[j].resize(nd.size());
+    for (size_t t = 0; t < nd.size(); ++t) {
+      oy[j][t] = tot;
+      tot += (long long)nd[t].kc * nrhs;
+      oz[j][t] = tot;
+      tot += (long long)nd[t].kr * nrhs;
+      ow[j][t] = tot;
+      tot += (long long)nd[t].mr * nrhs;
     }
-    HIPCHK(launch_gemm_batched(gd.data(), (int)gd.size(), H.staging, s));
+    if (!nd[0].leaf()) maxh = std::max(maxh, jobs[j].H->height);
   }
-  // downward: w_tau = U_tau z_tau, then z_a = B_ab y_b + w_tau(top), z_b = B_ba y_a + w_tau(bottom)
-  for (int h = H.height; h >= 1; --h) {
-    std::vector<int> inner;
-    if (h == H.height) inner.push_back(0);
-    else
-      for (int t : H.levels[h]) inner.push_back(t);
+  double* ws = static_cast<double*>(L.work_mv.ensure((size_t)tot * 8 + 8, s));
+  if (!ws) return fail(HSS_ERR_ALLOC, "matvec workspace");
+  std::vector<GemmDesc> gd;
+  auto flush = [&]() -> hipError_t {
+    hipError_t e = gd.empty() ? hipSuccess : launch_gemm_batched(gd.data(), (int)gd.size(), L.staging, s);
     gd.clear();
-    for (int t : inner) {
-      if (t == 0) continue;
-      const Node& v = nd[t];
-      GemmDesc g{};  // rows J: w[J[a]] = z[a]
+    return e;
+  };
+  // upward: y_tau = V^T x_in
+  for (int h = 0; h < maxh; ++h) {
+    for (size_t j = 0; j < jobs.size(); ++j) {
+      const MvJob& J = jobs[j];
+      const Handle& H = *J.H;
+      const std::vector<Node>& nd = H.nodes;
+      if (nd[0].leaf() || h >= H.height) continue;
+      const int nrhs = J.nrhs;
+      for (int t : H.levels[h]) {
+        const Node& v = nd[t];
+        Seg src{};
+        if (v.leaf()) {
+          src = Seg{J.x + (long long)v.lo * J.ldx, nullptr, J.ldx, INT_MAX, nullptr};
+        } else {
+          src = Seg{ws + oy[j][v.left], ws + oy[j][v.right], nrhs, nd[v.left].kc, nullptr};
+        }
+        GemmDesc g{};
+        g.M = v.kc;
+        g.N = nrhs;
+        g.K = v.mc - v.kc;
+        g.A = v.Ec;
+        g.lda = v.kc;
+        g.transA = 1;
+        g.B = src;
+        g.B.map = v.perm_c + v.kc;
+        g.C = src;
+        g.C.map = v.perm_c;
+        g.D = SegOut{ws + oy[j][t], nullptr, nrhs, INT_MAX, nullptr};
+        g.alpha = g.beta = 1.0;
+        gd.push_back(g);
+      }
+    }
+    HIPCHK(flush());
+  }
+  // downward: w_tau = U_tau z_tau, then z_a = B_ab y_b + w_tau(top),
+  // z_b = B_ba y_a + w_tau(bottom); a handle's root is at its own height
+  for (int h = maxh; h >= 1; --h) {
+    auto inner_of = [&](const Handle& H) {
+      std::vector<int> inner;
+      if (h == H.height) inner.push_back(0);
+      else if (h < H.height)
+        for (int t : H.levels[h]) inner.push_back(t);
+      return inner;
+    };
+    for (size_t j = 0; j < jobs.size(); ++j) {
+      const Handle& H = *jobs[j].H;
+      if (H.nodes[0].leaf()) continue;
+      const int nrhs = jobs[j].nrhs;
+      for (int t : inner_of(H)) {
+        if (t == 0) continue;
+        const Node& v = H.nodes[t];
+        GemmDesc g{};  // rows J: w[J[a]] = z[a]
+        g.M = v.kr;
+        g.N = nrhs;
+        g.K = 0;
+        g.C = Seg{ws + oz[j][t], nullptr, nrhs, INT_MAX, nullptr};
+        g.D = SegOut{ws + ow[j][t], nullptr, nrhs, INT_MAX, v.perm_r};
+        g.alpha = 1.0;
+        g.beta = 1.0;
+        gd.push_back(g);
+        GemmDesc e{};  // other rows: w[rest[i]] = (E z)[i]
+        e.M = v.mr - v.kr;
+        e.N = nrhs;
+        e.K = v.kr;
+        e.A = v.Er;
+        e.lda = v.kr;
+        e.B = Seg{ws + oz[j][t], nullptr, nrhs, INT_MAX, nullptr};
+        e.D = SegOut{ws + ow[j][t], nullptr, nrhs, INT_MAX, v.perm_r + v.kr};
+        e.alpha = 1.0;
+        gd.push_back(e);
+      }
+    }
+    HIPCHK(flush());
+    for (size_t j = 0; j < jobs.size(); ++j) {
+      const Handle& H = *jobs[j].H;
+      if (H.nodes[0].leaf()) continue;
+      const int nrhs = jobs[j].nrhs;
+      for (int t : inner_of(H)) {
+        const Node& v = H.nodes[t];
+        const Node& a = H.nodes[v.left];
+        const Node& c = H.nodes[v.right];
+        GemmDesc g{};
+        g.N = nrhs;
+        g.alpha = 1.0;
+        g.beta = (t == 0) ? 0.0 : 1.0;
+        // z_a = B_ab y_b (+ w top)
+        g.M = a.kr;
+        g.K = c.kc;
+        g.A = v.B12;
+        g.lda = c.kc;
+        g.B = Seg{ws + oy[j][v.right], nullptr, nrhs, INT_MAX, nullptr};
+        g.C = Seg{ws + ow[j][t], nullptr, nrhs, INT_MAX, nullptr};
+        g.D = SegOut{ws + oz[j][v.left], nullptr, nrhs, INT_MAX, nullptr};
+        gd.push_back(g);
+        // z_b = B_ba y_a (+ w bottom)
+        g.M = c.kr;
+        g.K = a.kc;
+        g.A = v.B21;
+        g.lda = a.kc;
+        g.B = Seg{ws + oy[j][v.left], nullptr, nrhs, INT_MAX, nullptr};
+        g.C = Seg{ws + ow[j][t] + (long long)a.kr * nrhs, nullptr, nrhs, INT_MAX, nullptr};
+        g.D = SegOut{ws + oz[j][v.right], nullptr, nrhs, INT_MAX, nullptr};
+        gd.push_back(g);
+      }
+    }
+    HIPCHK(flush());
+  }
+  // leaves: w = U z, then b(I) = w + D x(I); a single-leaf matrix is b = D x
+  for (size_t j = 0; j < jobs.size(); ++j) {
+    const Handle& H = *jobs[j].H;
+    if (H.nodes[0].leaf()) continue;
+    const int nrhs = jobs[j].nrhs;
+    for (int t : H.leaves) {
+      const Node& v = H.nodes[t];
+      GemmDesc g{};
       g.M = v.kr;
       g.N = nrhs;
       g.K = 0;
-      g.C = Seg{Z(t), nullptr, nrhs, INT_MAX, nullptr};
-      g.D = SegOut{Wv(t), nullptr, nrhs, INT_MAX, v.perm_r};
-      g.alpha = 1.0;
-      g.beta = 1.0;
+      g.C = Seg{ws + oz[j][t], nullptr, nrhs, INT_MAX, nullptr};
+      g.D = SegOut{ws + ow[j][t], nullptr, nrhs, INT_MAX, v.perm_r};
+      g.alpha = g.beta = 1.0;
       gd.push_back(g);
-      GemmDesc e{};  // other rows: w[rest[i]] = (E z)[i]
+      GemmDesc e{};
       e.M = v.mr - v.kr;
       e.N = nrhs;
       e.K = v.kr;
       e.A = v.Er;
       e.lda = v.kr;
-      e.B = Seg{Z(t), nullptr, nrhs, INT_MAX, nullptr};
-      e.D = SegOut{Wv(t), nullptr, nrhs, INT_MAX, v.perm_r + v.kr};
+      e.B = Seg{ws + oz[j][t], nullptr, nrhs, INT_MAX, nullptr};
+      e.D = SegOut{ws + ow[j][t], nullptr, nrhs, INT_MAX, v.perm_r + v.kr};
       e.alpha = 1.0;
       gd.push_back(e);
     }
-    HIPCHK(launch_gemm_batched(gd.data(), (int)gd.size(), H.staging, s));
-    gd.clear();
-    for (int t : inner) {
-      const Node& v = nd[t];
-      const Node& a = nd[v.left];
-      const Node& c = nd[v.right];
+  }
+  HIPCHK(flush());
+  for (size_t j = 0; j < jobs.size(); ++j) {
+    const MvJob& J = jobs[j];
+    const Handle& H = *J.H;
+    const std::vector<Node>& nd = H.nodes;
+    if (nd[0].leaf()) {
       GemmDesc g{};
-      g.N = nrhs;
+      g.M = g.K = (int)H.n;
+      g.N = J.nrhs;
+      g.A = nd[0].D;
+      g.lda = H.n;
+      g.B = Seg{J.x, nullptr, J.ldx, INT_MAX, nullptr};
+      g.D = SegOut{J.b, nullptr, J.ldb, INT_MAX, nullptr};
       g.alpha = 1.0;
-      g.beta = (t == 0) ? 0.0 : 1.0;
-      // z_a = B_ab y_b (+ w top)
-      g.M = a.kr;
-      g.K = c.kc;
-      g.A = v.B12;
-      g.lda = c.kc;
-      g.B = Seg{Y(v.right), nullptr, nrhs, INT_MAX, nullptr};
-      g.C = Seg{Wv(t), nullptr, nrhs, INT_MAX, nullptr};
-      g.D = SegOut{Z(v.left), nullptr, nrhs, INT_MAX, nullptr};
       gd.push_back(g);
-      // z_b = B_ba y_a (+ w bottom)
-      g.M = c.kr;
-      g.K = a.kc;
-      g.A = v.B21;
-      g.lda = a.kc;
-      g.B = Seg{Y(v.left), nullptr, nrhs, INT_MAX, nullptr};
-      g.C = Seg{Wv(t) + (long long)a.kr * nrhs, nullptr, nrhs, INT_MAX, nullptr};
-      g.D = SegOut{Z(v.right), nullptr, nrhs, INT_MAX, nullptr};
+      continue;
+    }
+    for (int t : H.leaves) {
+      const Node& v = nd[t];
+      GemmDesc g{};
+      g.M = g.K = v.size();
+      g.N = J.nrhs;
+      g.A = v.D;
+      g.lda = v.size();
+      g.B = Seg{J.x + (long long)v.lo * J.ldx, nullptr, J.ldx, INT_MAX, nullptr};
+      g.C = Seg{ws + ow[j][t], nullptr, J.nrhs, INT_MAX, nullptr};
+      g.D = SegOut{J.b + (long long)v.lo * J.ldb, nullptr, J.ldb, INT_MAX, nullptr};
+      g.alpha = g.beta = 1.0;
       gd.push_back(g);
     }
-    HIPCHK(launch_gemm_batched(gd.data(), (int)gd.size(), H.staging, s));
   }
-  // leaves: b(I) = U z + D x(I)
-  gd.clear();
-  for (int t : H.leaves) {
-    const Node& v = nd[t];
-    GemmDesc g{};
-    g.M = v.kr;
-    g.N = nrhs;
-    g.K = 0;
-    g.C = Seg{Z(t), nullptr, nrhs, INT_MAX, nullptr};
-    g.D = SegOut{Wv(t), nullptr, nrhs, INT_MAX, v.perm_r};
-    g.alpha = g.beta = 1.0;
-    gd.push_back(g);
-    GemmDesc e{};
-    e.M = v.mr - v.kr;
-    e.N = nrhs;
-    e.K = v.kr;
-    e.A = v.Er;
-    e.lda = v.kr;
-    e.B = Seg{Z(t), nullptr, nrhs, INT_MAX, nullptr};
-    e.D = SegOut{Wv(t), nullptr, nrhs, INT_MAX, v.perm_r + v.kr};
-    e.alpha = 1.0;
-    gd.push_back(e);
-  }
-  HIPCHK(launch_gemm_batched(gd.data(), (int)gd.size(), H.staging, s));
-  gd.clear();
-  for (int t : H.leaves) {
-    const Node& v = nd[t];
-    GemmDesc g{};
-    g.M = g.K = v.size();
-    g.N = nrhs;
-    g.A = v.D;
-    g.lda = v.size();
-    g.B = Seg{x + (long long)v.lo * ldx, nullptr, ldx, INT_MAX, nullptr};
-    g.C = Seg{Wv(t), nullptr, nrhs, INT_MAX, nullptr};
-    g.D = SegOut{b + (long long)v.lo * ldb, nullptr, ldb, INT_MAX, nullptr};
-    g.alpha = g.beta = 1.0;
-    gd.push_back(g);
-  }
-  HIPCHK(launch_gemm_batched(gd.data(), (int)gd.size(), H.staging, s));
+  HIPCHK(flush());
   // the descriptor tables live in the staging area until the copies ran
   HIPCHK(hipStreamSynchronize(s));
-  H.staging.reset();
+  L.staging.reset();
   return HSS_OK;
+}
+
+hss_status matvec_impl(Handle& H, int nrhs, const double* x, long long ldx, double* b,
+                       long long ldb, hipStream_t s) {
+  std::vector<MvJob> jobs{MvJob{&H, nrhs, x, ldx, b, ldb}};
+  return matvec_many(H, jobs, s);
 }
 
 }  // namespace hss
@@ -1411,6 +1465,33 @@ hss_status hss_matvec(hss_handle h, int nrhs, const double* x, long long ldx, do
   const long long xe = ((H.n - 1) * ldx + nrhs) * 8, be = ((H.n - 1) * ldb + nrhs) * 8;
   if (xb < bb + be && bb < xb + xe) return fail(HSS_ERR_ARG, "x and b overlap");
   return matvec_impl(h->h, nrhs, x, ldx, b, ldb, static_cast<hipStream_t>(stream));
+}
+
+hss_status hss_matvec_batched(int nmat, const hss_handle* h, int nrhs, const double* const* x,
+                              const long long* ldx, double* const* b, const long long* ldb,
+                              void* stream) {
+  g_err.clear();
+  if (nmat < 0 || (nmat > 0 && (!h || !x || !ldx || !b || !ldb)))
+    return fail(HSS_ERR_ARG, "batch arguments");
+  if (nrhs < 0) return fail(HSS_ERR_ARG, "nrhs");
+  if (nmat == 0 || nrhs == 0) return HSS_OK;
+  std::vector<MvJob> jobs;
+  jobs.reserve(nmat);
+  for (int i = 0; i < nmat; ++i) {
+    const std::string tag = "matrix " + std::to_string(i) + ": ";
+    if (!h[i] || !h[i]->h.compressed) return fail(HSS_ERR_STATE, tag + "handle not compressed");
+    if (ldx[i] < nrhs || ldb[i] < nrhs) return fail(HSS_ERR_ARG, tag + "ldx / ldb");
+    if (!x[i] || !b[i]) return fail(HSS_ERR_ARG, tag + "x or b is NULL");
+    const long long n = h[i]->h.n;
+    const char* xb = reinterpret_cast<const char*>(x[i]);
+    const char* bb = reinterpret_cast<const char*>(b[i]);
+    const long long xe = ((n - 1) * ldx[i] + nrhs) * 8, be = ((n - 1) * ldb[i] + nrhs) * 8;
+    if (xb < bb + be && bb < xb + xe) return fail(HSS_ERR_ARG, tag + "x and b overlap");
+    for (int q = 0; q < i; ++q)
+      if (h[q] == h[i]) return fail(HSS_ERR_ARG, tag + "handle appears twice");
+    jobs.push_back(MvJob{&h[i]->h, nrhs, x[i], ldx[i], b[i], ldb[i]});
+  }
+  return matvec_many(h[0]->h, jobs, static_cast<hipStream_t>(stream));
 }
 
 hss_status hss_stats(hss_handle h, hss_stats_t* st) {

@@ -70,3 +70,32 @@ def test_batched_argument_errors():
         P.hss_compress_batched([A], sample_prec="bf16x3")
     assert e.value.status == P.HSS_ERR_ARG
     assert P.hss_compress_batched([]) == []
+
+
+def test_matvec_batched_equals_single():
+    """hss_matvec_batched over matrices of different heights (a single leaf
+    among them) gives exactly hss_matvec's result for each: every GEMM
+    descriptor is computed the same way whatever else is in the launch."""
+    As = _matrices(9, 40, 2000, 5, torch.float64, 64)
+    hs = P.hss_compress_batched(As, rtol=1e-8, d0=32, dd=16, leaf_size=64)
+    heights = {P.hss_stats(h)["height"] for h in hs}
+    assert len(heights) > 2
+    for nrhs in (1, 3):
+        xs = [torch.from_numpy(np.random.default_rng(int(a.shape[0]) + nrhs).uniform(-1, 1, (a.shape[0], nrhs))).cuda()
+              for a in As]
+        print(f"matvec batched: {len(hs)} matrices, nrhs {nrhs}, heights {sorted(heights)}", flush=True)
+        bs = P.hss_matvec_batched(hs, xs)
+        for h, x, b in zip(hs, xs, bs):
+            assert torch.equal(b, P.hss_matvec(h, x))
+
+
+def test_matvec_batched_argument_errors():
+    As = _matrices(2, 100, 300, 8, torch.float64, 64)
+    hs = P.hss_compress_batched(As, rtol=1e-8, leaf_size=64)
+    xs = [torch.ones((a.shape[0], 1), dtype=torch.float64, device="cuda") for a in As]
+    with pytest.raises(P.HSSError) as e:
+        P.hss_matvec_batched([hs[0], hs[0]], [xs[0], xs[0]])
+    assert e.value.status == P.HSS_ERR_ARG
+    with pytest.raises(ValueError):
+        P.hss_matvec_batched(hs, [xs[0], torch.ones((As[1].shape[0], 2), dtype=torch.float64, device="cuda")])
+    assert P.hss_matvec_batched([], []) == []
