@@ -135,6 +135,126 @@ hss_status tri_solve_batch(const std::vector<TriJob>& jobs, bool lower, bool uni
   return HSS_OK;
 }
 
+// v <- H_0 H_1 ... H_{r-1} v for every descriptor (H_i = I - tau_i u_i u_i^T,
+// u_i in row i of Z), in the compact WY form: the reflectors in blocks of 64,
+// H_{i0} ... H_{i0+kb-1} = I - Y_b T_b Y_b^T, applied from the last block as
+// W = Y_b^T v, W = T_b W, v = v - Y_b W.  Y_b is zero above its block's first
+// row, so every product starts there.  Every step is a batched GEMM over all
+// descriptors, so a large problem spreads over the device.
+hss_status apply_q_blocked(Handle& H, const std::vector<ReflDesc>& rd, hipStream_t s) {
+  if (rd.empty()) return HSS_OK;
+  for (const ReflDesc& d : rd)
+    if (!d.transpose) return set_error(HSS_ERR_ARG, "apply_q_blocked: only the H_0 ... H_{r-1} v form");
+  const size_t np = rd.size();
+  std::vector<long long> oy(np), ow1(np), ow2(np);
+  std::vector<int> nb(np), ob(np);
+  long long tot = 0;
+  int nbtot = 0, nbmax = 0, rmax = 0, mmax = 0;
+  for (size_t p = 0; p < np; ++p) {
+    const ReflDesc& d = rd[p];
+    oy[p] = tot;
+    tot += (long long)d.m * d.r;
+    ow1[p] = tot;
+    tot += 64LL * d.nrhs;
+    ow2[p] = tot;
+    tot += 64LL * d.nrhs;
+    nb[p] = (d.r + 63) / 64;
+    ob[p] = nbtot;
+    nbtot += nb[p];
+    nbmax = std::max(nbmax, nb[p]);
+    rmax = std::max(rmax, d.r);
+    mmax = std::max(mmax, d.m);
+  }
+  const long long og = tot;
+  tot += (long long)nbtot * 64 * 64;
+  const long long ot = tot;
+  tot += (long long)nbtot * 64 * 64;
+  double* ws = static_cast<double*>(H.work_misc.ensure((size_t)tot * 8 + 8, s));
+  if (!ws) return set_error(HSS_ERR_ALLOC, "reflector workspace");
+  auto Y = [&](size_t p) { return ws + oy[p]; };
+  auto Gb = [&](size_t p, int b) { return ws + og + (long long)(ob[p] + b) * 64 * 64; };
+  auto Tb = [&](size_t p, int b) { return ws + ot + (long long)(ob[p] + b) * 64 * 64; };
+  std::vector<ReflYDesc> yd(np);
+  for (size_t p = 0; p < np; ++p) yd[p] = ReflYDesc{rd[p].Z, rd[p].ldz, Y(p), rd[p].r, rd[p].m};
+  HIPCHK(launch_refl_y(yd.data(), (int)np, rmax, mmax, H.staging, s));
+  // G_b = Y_b^T Y_b, then T_b
+  std::vector<GemmDesc> gd;
+  std::vector<LarftDesc> ld;
+  for (size_t p = 0; p < np; ++p) {
+    const ReflDesc& d = rd[p];
+    for (int b = 0; b < nb[p]; ++b) {
+      const int i0 = 64 * b, kb = std::min(64, d.r - i0);
+      const double* yb = Y(p) + (long long)i0 * d.r + i0;
+      GemmDesc g{};
+      g.M = g.N = kb;
+      g.K = d.m - i0;
+      g.A = yb;
+      g.lda = d.r;
+      g.transA = 1;
+      g.B = seg(yb, d.r);
+      g.D = out(Gb(p, b), 64);
+      g.alpha = 1.0;
+      g.beta = 0.0;
+      gd.push_back(g);
+      ld.push_back(LarftDesc{Gb(p, b), d.tau + i0, Tb(p, b), kb});
+    }
+  }
+  HIPCHK(launch_gemm_batched(gd.data(), (int)gd.size(), H.staging, s));
+  HIPCHK(launch_larft(ld.data(), (int)ld.size(), H.staging, s));
+  for (int step = 0; step < nbmax; ++step) {
+    std::vector<GemmDesc> g1, g2, g3;
+    for (size_t p = 0; p < np; ++p) {
+      if (step >= nb[p]) continue;
+      const ReflDesc& d = rd[p];
+      const int b = nb[p] - 1 - step;
+      const int i0 = 64 * b, kb = std::min(64, d.r - i0);
+      const double* yb = Y(p) + (long long)i0 * d.r + i0;
+      double* vb = d.V + (long long)i0 * d.ldv;
+      double* w1 = ws + ow1[p];
+      double* w2 = ws + ow2[p];
+      GemmDesc g{};  // W1 = Y_b^T v
+      g.M = kb;
+      g.N = d.nrhs;
+      g.K = d.m - i0;
+      g.A = yb;
+      g.lda = d.r;
+      g.transA = 1;
+      g.B = seg(vb, d.ldv);
+      g.D = out(w1, d.nrhs);
+      g.alpha = 1.0;
+      g.beta = 0.0;
+      g1.push_back(g);
+      GemmDesc t{};  // W2 = T_b W1
+      t.M = kb;
+      t.N = d.nrhs;
+      t.K = kb;
+      t.A = Tb(p, b);
+      t.lda = 64;
+      t.B = seg(w1, d.nrhs);
+      t.D = out(w2, d.nrhs);
+      t.alpha = 1.0;
+      t.beta = 0.0;
+      g2.push_back(t);
+      GemmDesc u{};  // v = v - Y_b W2
+      u.M = d.m - i0;
+      u.N = d.nrhs;
+      u.K = kb;
+      u.A = yb;
+      u.lda = d.r;
+      u.B = seg(w2, d.nrhs);
+      u.C = seg(vb, d.ldv);
+      u.D = out(vb, d.ldv);
+      u.alpha = -1.0;
+      u.beta = 1.0;
+      g3.push_back(u);
+    }
+    HIPCHK(launch_gemm_batched(g1.data(), (int)g1.size(), H.staging, s));
+    HIPCHK(launch_gemm_batched(g2.data(), (int)g2.size(), H.staging, s));
+    HIPCHK(launch_gemm_batched(g3.data(), (int)g3.size(), H.staging, s));
+  }
+  return HSS_OK;
+}
+
 // The 4 blocks of D_tau for inner node t into Dm (ld md).
 void merged_D(const Handle& H, int t, double* Dm, std::vector<GemmDesc>& gd) {
   const Node& v = H.nodes[t];
@@ -550,7 +670,7 @@ hss_status solve_impl(Handle& H, int nrhs, const double* b, long long ldb, doubl
         }
       }
       HIPCHK(launch_gemm_batched(gd.data(), (int)gd.size(), H.staging, s));
-      HIPCHK(launch_reflect(rd.data(), (int)rd.size(), H.staging, s));
+      CHK(apply_q_blocked(H, rd, s));
     }
   }
   HIPCHK(hipStreamSynchronize(s));

@@ -22,7 +22,7 @@ struct TriDesc {     // X <- T^{-1} X on one diagonal block (nb <= 64)
   int lower, unit;
 };
 
-struct ReflDesc {    // V <- Q^T V or Q V, reflectors in rows of Z
+struct ReflDesc {    // V <- H_0 ... H_{r-1} V (transpose = 1), reflectors in rows of Z
   const double* Z;
   long long ldz;
   const double* tau;
@@ -33,9 +33,26 @@ struct ReflDesc {    // V <- Q^T V or Q V, reflectors in rows of Z
   int transpose;
 };
 
+// Blocked application of reflectors (compact WY form): the reflector
+// vectors as columns of a dense Y, and the triangular factor of each block
+// of 64 of them.
+struct ReflYDesc {   // Y[q][i] = u_i[q] (m x r, ld r) from the rows of Z
+  const double* Z;
+  long long ldz;
+  double* Y;
+  int r, m;
+};
+struct LarftDesc {   // T (kb x kb, ld 64) of reflectors i0..i0+kb-1 from G = Y_b^T Y_b (ld 64)
+  const double* G;
+  const double* tau;  // tau of the block's first reflector
+  double* T;
+  int kb;
+};
+hipError_t launch_refl_y(const ReflYDesc* d, int nd, int rmax, int mmax, Staging& st, hipStream_t s);
+hipError_t launch_larft(const LarftDesc* d, int nd, Staging& st, hipStream_t s);
+
 hipError_t launch_vt_leaf(const VtLeafDesc* d, int nd, int kmax, Staging& st, hipStream_t s);
 hipError_t launch_tri_block(const TriDesc* d, int nd, Staging& st, hipStream_t s);
-hipError_t launch_reflect(const ReflDesc* d, int nd, Staging& st, hipStream_t s);
 hipError_t launch_lu_panel(double* A, long long ld, int n, int j0, int nb, int* piv, int* info,
                            hipStream_t s);
 hipError_t launch_lu_swap(double* A, long long ld, int ncols, const int* piv, int j0, int nb,

@@ -1,6 +1,7 @@
 // Kernels of the ULV-like factorization (Alg. 3) and solve (Alg. 4): the
 // generators' V^T at the leaves, 64-wide triangular block solves with many
-// right-hand sides, application of the LQ reflectors, and the partial-pivoting
+// right-hand sides, the dense reflector matrix and block triangular factors
+// of the compact WY form of the LQ reflectors, and the partial-pivoting
 // LU of the root block (panel factorization and row interchanges; the
 // trailing updates run on the batched GEMM).
 #include <climits>
@@ -72,31 +73,52 @@ __global__ __launch_bounds__(NT) void tri_block_kernel(const TriDesc* __restrict
   }
 }
 
-// v <- H_0 H_1 ... H_{r-1} v (transpose = 1, i.e. Q^T v) or
-// v <- H_{r-1} ... H_0 v (transpose = 0, Q v) with H_i = I - tau_i u_i u_i^T,
-// u_i = (1, Z[i][i+1..m-1]).  One workgroup per problem; every wavefront
-// handles right-hand-side columns.
-__global__ __launch_bounds__(NT) void reflect_kernel(const ReflDesc* __restrict__ d) {
-  const ReflDesc g = d[blockIdx.x];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  for (int col = wave; col < g.nrhs; col += NT / 64) {
-    for (int s = 0; s < g.r; ++s) {
-      const int i = g.transpose ? g.r - 1 - s : s;
-      const double* u = g.Z + (long long)i * g.ldz;
-      double dot = 0.0;
-      for (int q = i + lane; q < g.m; q += 64) {
-        const double ui = (q == i) ? 1.0 : u[q];
-        dot = fma(ui, g.V[(long long)q * g.ldv + col], dot);
-      }
-#pragma unroll
-      for (int o = 32; o > 0; o >>= 1) dot += __shfl_xor(dot, o, 64);
-      const double f = g.tau[i] * dot;
-      for (int q = i + lane; q < g.m; q += 64) {
-        const double ui = (q == i) ? 1.0 : u[q];
-        g.V[(long long)q * g.ldv + col] = fma(-f, ui, g.V[(long long)q * g.ldv + col]);
-      }
-    }
+// Y = [u_0 .. u_{r-1}] (m x r, row-major, ld r) with u_i = (0.., 1, Z[i][i+1..m-1]):
+// 64 x 64 tiles transposed through LDS, so both Z rows and Y rows are read
+// and written contiguously.  grid: (ceil(m/64) * ceil(rmax/64), problems).
+__global__ __launch_bounds__(NT) void refl_y_kernel(const ReflYDesc* __restrict__ d) {
+  __shared__ double tile[64][65];
+  const ReflYDesc g = d[blockIdx.y];
+  const int tq = (g.m + 63) / 64, ti = (g.r + 63) / 64;
+  if ((int)blockIdx.x >= tq * ti) return;
+  const int q0 = (blockIdx.x % tq) * 64, i0 = (blockIdx.x / tq) * 64;
+  // read: rows i of Z (reflector i), columns q
+  for (int e = threadIdx.x; e < 64 * 64; e += NT) {
+    const int il = e / 64, ql = e % 64;
+    const int i = i0 + il, q = q0 + ql;
+    double v = 0.0;
+    if (i < g.r && q < g.m) v = (q < i) ? 0.0 : (q == i ? 1.0 : g.Z[(long long)i * g.ldz + q]);
+    tile[il][ql] = v;
   }
+  __syncthreads();
+  for (int e = threadIdx.x; e < 64 * 64; e += NT) {
+    const int ql = e / 64, il = e % 64;
+    const int i = i0 + il, q = q0 + ql;
+    if (i < g.r && q < g.m) g.Y[(long long)q * g.r + i] = tile[il][ql];
+  }
+}
+
+// Forward triangular factor of a block of kb reflectors, H_0 ... H_{kb-1} =
+// I - Y T Y^T: T[j][j] = tau_j, T[0:j, j] = -tau_j T[0:j, 0:j] G[0:j, j] with
+// G = Y^T Y.  One workgroup of 64 threads per block; thread l owns row l.
+__global__ __launch_bounds__(64) void larft_kernel(const LarftDesc* __restrict__ d) {
+  __shared__ double T[64][65];
+  const LarftDesc g = d[blockIdx.x];
+  const int l = threadIdx.x;
+  for (int c = 0; c < 64; ++c) T[l][c] = 0.0;
+  __syncthreads();
+  for (int j = 0; j < g.kb; ++j) {
+    const double tj = g.tau[j];
+    double s = 0.0;
+    if (l < j)
+      for (int p = l; p < j; ++p) s = fma(T[l][p], g.G[(long long)p * 64 + j], s);
+    __syncthreads();
+    if (l < j) T[l][j] = -tj * s;
+    if (l == j) T[j][j] = tj;
+    __syncthreads();
+  }
+  if (l < g.kb)
+    for (int c = 0; c < g.kb; ++c) g.T[(long long)l * 64 + c] = T[l][c];
 }
 
 // Unblocked partial-pivoting LU of the panel A[j0:n, j0:j0+nb] (row-major,
@@ -206,11 +228,20 @@ hipError_t launch_tri_block(const TriDesc* d, int nd, Staging& st, hipStream_t s
   return hipGetLastError();
 }
 
-hipError_t launch_reflect(const ReflDesc* d, int nd, Staging& st, hipStream_t s) {
-  if (nd <= 0) return hipSuccess;
-  const ReflDesc* dd = static_cast<const ReflDesc*>(st.push(d, sizeof(ReflDesc) * nd));
+hipError_t launch_refl_y(const ReflYDesc* d, int nd, int rmax, int mmax, Staging& st, hipStream_t s) {
+  if (nd <= 0 || rmax <= 0 || mmax <= 0) return hipSuccess;
+  const ReflYDesc* dd = static_cast<const ReflYDesc*>(st.push(d, sizeof(ReflYDesc) * nd));
   if (!dd) return hipErrorOutOfMemory;
-  hipLaunchKernelGGL(reflect_kernel, dim3(nd), dim3(NT), 0, s, dd);
+  const int tiles = ((mmax + 63) / 64) * ((rmax + 63) / 64);
+  hipLaunchKernelGGL(refl_y_kernel, dim3(tiles, nd), dim3(NT), 0, s, dd);
+  return hipGetLastError();
+}
+
+hipError_t launch_larft(const LarftDesc* d, int nd, Staging& st, hipStream_t s) {
+  if (nd <= 0) return hipSuccess;
+  const LarftDesc* dd = static_cast<const LarftDesc*>(st.push(d, sizeof(LarftDesc) * nd));
+  if (!dd) return hipErrorOutOfMemory;
+  hipLaunchKernelGGL(larft_kernel, dim3(nd), dim3(64), 0, s, dd);
   return hipGetLastError();
 }
 
