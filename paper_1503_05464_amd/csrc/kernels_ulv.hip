@@ -192,6 +192,177 @@ __global__ __launch_bounds__(1024) void lu_panel_kernel(double* __restrict__ A, 
   }
 }
 
+// The same panel factorization with the panel's rows split over the 1024
+// threads (thread t owns rows j0 + t + 1024 k, k < R) and the columns taken
+// eight at a time: a sub-panel of 8 columns lives in registers while its
+// pivots are chosen (largest magnitude, lowest row on ties), its rows are
+// interchanged (through LDS, and in global memory for the panel's other
+// columns) and its multipliers are applied; then the panel's columns to the
+// right get the 8 rows of U (a unit-lower solve) and the rank-8 update of
+// the rows below, with the multipliers still in registers.
+constexpr int LW = 8;  // sub-panel width
+
+template <int R>
+__global__ __launch_bounds__(1024) void lu_panel_reg_kernel(double* __restrict__ A, long long ld, int n,
+                                                           int j0, int nb, int* __restrict__ piv,
+                                                           int* __restrict__ info) {
+  __shared__ double rv[16];
+  __shared__ int ri[16];
+  __shared__ int s_p;
+  __shared__ double xr[2][LW];
+  __shared__ double ub[LW][64];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int j1 = j0 + nb;
+  for (int c0 = j0; c0 < j1; c0 += LW) {
+    const int w = min(LW, j1 - c0);
+    double a[R][LW];
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+      const int r = j0 + tid + 1024 * k;
+#pragma unroll
+      for (int q = 0; q < LW; ++q) a[k][q] = (r >= c0 && r < n && q < w) ? A[(long long)r * ld + c0 + q] : 0.0;
+    }
+    for (int cc = 0; cc < w; ++cc) {
+      const int col = c0 + cc;
+      double bv = -1.0;
+      int bi = INT_MAX;
+#pragma unroll
+      for (int k = 0; k < R; ++k) {
+        const int r = j0 + tid + 1024 * k;
+        double x = 0.0;
+#pragma unroll
+        for (int q = 0; q < LW; ++q)
+          if (q == cc) x = a[k][q];
+        if (r >= col && r < n && fabs(x) > bv) {
+          bv = fabs(x);
+          bi = r;
+        }
+      }
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) {
+        const double ov = __shfl_xor(bv, o, 64);
+        const int oi = __shfl_xor(bi, o, 64);
+        if (ov > bv || (ov == bv && oi < bi)) {
+          bv = ov;
+          bi = oi;
+        }
+      }
+      if (lane == 0) {
+        rv[wave] = bv;
+        ri[wave] = bi;
+      }
+      __syncthreads();
+      if (tid == 0) {
+        double v = rv[0];
+        int ix = ri[0];
+        for (int q = 1; q < 16; ++q)
+          if (rv[q] > v || (rv[q] == v && ri[q] < ix)) {
+            v = rv[q];
+            ix = ri[q];
+          }
+        s_p = ix;
+        piv[col] = ix;
+        if (!(v > 0.0) && *info == 0) *info = col + 1;
+      }
+      __syncthreads();
+      const int p = s_p;
+      // rows col and p: exchange the sub-panel part through LDS
+      const int oc = col - j0, op = p - j0;
+      const bool own_c = (oc & 1023) == tid, own_p = (op & 1023) == tid;
+      if (own_c || own_p) {
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+          if (own_c && (oc >> 10) == k)
+#pragma unroll
+            for (int q = 0; q < LW; ++q) xr[0][q] = a[k][q];
+          if (own_p && (op >> 10) == k)
+#pragma unroll
+            for (int q = 0; q < LW; ++q) xr[1][q] = a[k][q];
+        }
+      }
+      // ... and the panel's other columns in global memory
+      if (p != col && tid < nb) {
+        const int q = j0 + tid;
+        if (q < c0 || q >= c0 + w) {
+          const double t = A[(long long)col * ld + q];
+          A[(long long)col * ld + q] = A[(long long)p * ld + q];
+          A[(long long)p * ld + q] = t;
+        }
+      }
+      __syncthreads();
+      if (p != col && (own_c || own_p)) {
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+          if (own_c && (oc >> 10) == k)
+#pragma unroll
+            for (int q = 0; q < LW; ++q) a[k][q] = xr[1][q];
+          if (own_p && (op >> 10) == k)
+#pragma unroll
+            for (int q = 0; q < LW; ++q) a[k][q] = xr[0][q];
+        }
+      }
+      // the pivot row (after the interchange) is xr[1]
+      const double d = xr[1][cc];
+      const double inv = (d != 0.0) ? 1.0 / d : 0.0;
+#pragma unroll
+      for (int k = 0; k < R; ++k) {
+        const int r = j0 + tid + 1024 * k;
+        if (r > col && r < n) {
+          double l = 0.0;
+#pragma unroll
+          for (int q = 0; q < LW; ++q)
+            if (q == cc) l = a[k][q] * inv;
+#pragma unroll
+          for (int q = 0; q < LW; ++q) {
+            if (q == cc) a[k][q] = l;
+            else if (q > cc) a[k][q] = fma(-l, xr[1][q], a[k][q]);
+          }
+        }
+      }
+      __syncthreads();  // xr is rewritten by the next column
+    }
+    // the sub-panel back to global memory
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+      const int r = j0 + tid + 1024 * k;
+      if (r >= c0 && r < n)
+#pragma unroll
+        for (int q = 0; q < LW; ++q)
+          if (q < w) A[(long long)r * ld + c0 + q] = a[k][q];
+    }
+    const int q0 = c0 + w, nr = j1 - q0;  // the panel's columns to the right
+    if (nr <= 0) break;
+    __syncthreads();
+    // U rows c0..c0+w-1 of those columns: unit-lower solve with L11, one column per thread
+    if (tid < nr) {
+      const int q = q0 + tid;
+      for (int i = 0; i < w; ++i) {
+        double x = A[(long long)(c0 + i) * ld + q];
+        for (int k = 0; k < i; ++k) x = fma(-A[(long long)(c0 + i) * ld + c0 + k], ub[k][tid], x);
+        A[(long long)(c0 + i) * ld + q] = x;
+        ub[i][tid] = x;  // this thread's column: read back by it only until the barrier
+      }
+    }
+    __syncthreads();
+    // rows below: A[r][q] -= L[r][c0..c0+w) U[c0..c0+w)[q]
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+      const int r = j0 + tid + 1024 * k;
+      if (r >= q0 && r < n) {
+        double* ar = A + (long long)r * ld;
+        for (int t = 0; t < nr; ++t) {
+          double x = ar[q0 + t];
+#pragma unroll
+          for (int i = 0; i < LW; ++i)
+            if (i < w) x = fma(-a[k][i], ub[i][t], x);
+          ar[q0 + t] = x;
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
 // Row interchanges of the panel's pivots applied to the columns outside
 // [j0, j0+nb) (or to a right-hand side with cols = its width, c_skip0 = 0,
 // c_skip1 = 0).  Sequential over the pivots, parallel over columns.
@@ -247,7 +418,15 @@ hipError_t launch_larft(const LarftDesc* d, int nd, Staging& st, hipStream_t s) 
 
 hipError_t launch_lu_panel(double* A, long long ld, int n, int j0, int nb, int* piv, int* info,
                            hipStream_t s) {
-  hipLaunchKernelGGL(lu_panel_kernel, dim3(1), dim3(1024), 0, s, A, ld, n, j0, nb, piv, info);
+  const int rows = n - j0;
+  if (nb > 64 || rows > 4096)
+    hipLaunchKernelGGL(lu_panel_kernel, dim3(1), dim3(1024), 0, s, A, ld, n, j0, nb, piv, info);
+  else if (rows > 2048)
+    hipLaunchKernelGGL(lu_panel_reg_kernel<4>, dim3(1), dim3(1024), 0, s, A, ld, n, j0, nb, piv, info);
+  else if (rows > 1024)
+    hipLaunchKernelGGL(lu_panel_reg_kernel<2>, dim3(1), dim3(1024), 0, s, A, ld, n, j0, nb, piv, info);
+  else
+    hipLaunchKernelGGL(lu_panel_reg_kernel<1>, dim3(1), dim3(1024), 0, s, A, ld, n, j0, nb, piv, info);
   return hipGetLastError();
 }
 

@@ -106,3 +106,23 @@ def test_compress_factor_solve_circle16384():
         v = v / torch.linalg.norm(v)
     anorm = float(torch.linalg.norm(A @ v))
     assert float(torch.linalg.norm(r)) / (anorm * float(torch.linalg.norm(x))) <= 10 * cfg["rtol"]
+
+
+@pytest.mark.parametrize("n", [1500, 3000])
+def test_large_root_lu(n):
+    """A matrix without low-rank structure (random plus a diagonal shift):
+    the off-diagonal ranks are full, so the root block has about n rows and
+    its partial-pivoting LU takes the register panel kernel with one, two
+    and four rows per thread (panels of more than 1024 and 2048 rows).  The
+    solve must reproduce x with the accuracy of a dense LU."""
+    g = np.random.default_rng(n)
+    A = torch.from_numpy(g.standard_normal((n, n)) / np.sqrt(n) + 3.0 * np.eye(n)).cuda()
+    print(f"large root LU: n={n}", flush=True)
+    h = P.hss_compress(A, rtol=1e-13, d0=n // 2 + 128, dd=64, d_max=n + 256, leaf_size=n // 4, p_margin=16)
+    st = P.hss_stats(h)
+    assert st["converged"]
+    P.hss_factor(h)
+    xs = torch.from_numpy(g.uniform(-1, 1, (n, 3))).cuda()
+    b = A @ xs
+    x = P.hss_solve(h, b)
+    assert float(torch.linalg.norm(x - xs) / torch.linalg.norm(xs)) < 1e-9
