@@ -29,18 +29,23 @@ __global__ __launch_bounds__(NT) void vt_leaf_kernel(const VtLeafDesc* __restric
 
 // One diagonal block of a triangular solve, in place on X (nb rows, nrhs
 // columns): lower: X = T^{-1} X with T lower triangular (unit diagonal if
-// unit); upper: likewise with T upper triangular.  One workgroup per problem;
-// each thread owns right-hand-side columns.
+// unit); upper: likewise with T upper triangular.  One workgroup per problem
+// and block of NT right-hand-side columns (grid y); each thread owns one
+// column.
 __global__ __launch_bounds__(NT) void tri_block_kernel(const TriDesc* __restrict__ d) {
   __shared__ double T[64][65];
   const TriDesc g = d[blockIdx.x];
   const int nb = g.nb;
+  const int cbeg = blockIdx.y * NT;
+  if (cbeg >= g.nrhs) return;
   for (int e = threadIdx.x; e < nb * nb; e += NT) {
     const int r = e / nb, c = e % nb;
     T[r][c] = g.T[(long long)r * g.ldt + c];
   }
   __syncthreads();
-  for (int col = threadIdx.x; col < g.nrhs; col += NT) {
+  {
+    const int col = cbeg + threadIdx.x;
+    if (col >= g.nrhs) return;
     double x[64];
 #pragma unroll
     for (int r = 0; r < 64; ++r) x[r] = (r < nb) ? g.X[(long long)r * g.ldx + col] : 0.0;
@@ -393,9 +398,11 @@ hipError_t launch_vt_leaf(const VtLeafDesc* d, int nd, int kmax, Staging& st, hi
 
 hipError_t launch_tri_block(const TriDesc* d, int nd, Staging& st, hipStream_t s) {
   if (nd <= 0) return hipSuccess;
+  int cmax = 1;
+  for (int i = 0; i < nd; ++i) cmax = d[i].nrhs > cmax ? d[i].nrhs : cmax;
   const TriDesc* dd = static_cast<const TriDesc*>(st.push(d, sizeof(TriDesc) * nd));
   if (!dd) return hipErrorOutOfMemory;
-  hipLaunchKernelGGL(tri_block_kernel, dim3(nd), dim3(NT), 0, s, dd);
+  hipLaunchKernelGGL(tri_block_kernel, dim3(nd, (cmax + NT - 1) / NT), dim3(NT), 0, s, dd);
   return hipGetLastError();
 }
 
