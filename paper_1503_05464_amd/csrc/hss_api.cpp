@@ -71,17 +71,23 @@ namespace {
 // runtime pool returns freed memory to the system at synchronizations, and
 // mapping it again can take seconds when a step frees and allocates tens of
 // GB (batched compressions).  A reused block is ordered after its last use
-// by an event recorded when it was freed.
+// by an event recorded when it was freed.  Blocks are kept per device.
 struct CachedBlock {
   void* p;
   hipEvent_t ev;  // recorded on the freeing stream
 };
+struct LiveBlock {
+  size_t cls;
+  int dev;
+};
 std::mutex g_dev_mu;
-std::unordered_map<size_t, std::vector<CachedBlock>> g_dev_free;  // by class
-std::unordered_map<void*, size_t> g_dev_live;                     // class of cached-size blocks
+std::unordered_map<unsigned long long, std::vector<CachedBlock>> g_dev_free;  // by (class, device)
+std::unordered_map<void*, LiveBlock> g_dev_live;  // cached-size blocks in use
 size_t g_dev_cached = 0;
 size_t g_dev_cap = 0;
 std::once_flag g_dev_once;
+
+unsigned long long cache_key(size_t cls, int dev) { return ((unsigned long long)cls << 8) | (unsigned)(dev & 255); }
 
 constexpr size_t kCacheMin = (size_t)1 << 20;
 
@@ -93,16 +99,23 @@ size_t size_class(size_t b) {
   return (b + step - 1) / step * step;
 }
 
-// frees every cached block, each after its last use, on stream s (lock held)
-void trim_cache(hipStream_t s) {
-  for (auto& kv : g_dev_free)
-    for (CachedBlock& c : kv.second) {
+// frees every cached block of device dev, each after its last use, on
+// stream s of that device (lock held)
+void trim_cache(int dev, hipStream_t s) {
+  for (auto it = g_dev_free.begin(); it != g_dev_free.end();) {
+    if ((int)(it->first & 255) != (dev & 255)) {
+      ++it;
+      continue;
+    }
+    const size_t cls = (size_t)(it->first >> 8);
+    for (CachedBlock& c : it->second) {
       hipStreamWaitEvent(s, c.ev, 0);
       hipEventDestroy(c.ev);
       hipFreeAsync(c.p, s);
+      g_dev_cached -= cls;
     }
-  g_dev_free.clear();
-  g_dev_cached = 0;
+    it = g_dev_free.erase(it);
+  }
 }
 }  // namespace
 
@@ -120,27 +133,28 @@ void* pool_alloc(size_t bytes, hipStream_t s) {
     }
     return p;
   }
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return nullptr;
   std::lock_guard<std::mutex> lk(g_dev_mu);
-  auto it = g_dev_free.find(cls);
+  auto it = g_dev_free.find(cache_key(cls, dev));
   if (it != g_dev_free.end() && !it->second.empty()) {
     CachedBlock c = it->second.back();
     it->second.pop_back();
     g_dev_cached -= cls;
     hipStreamWaitEvent(s, c.ev, 0);
     hipEventDestroy(c.ev);
-    g_dev_live[c.p] = cls;
+    g_dev_live[c.p] = LiveBlock{cls, dev};
     return c.p;
   }
   if (hipMallocAsync(&p, cls, s) != hipSuccess) {
     (void)hipGetLastError();
-    if (g_dev_cached == 0) return nullptr;
-    trim_cache(s);  // cached blocks of other classes go back, then try again
+    trim_cache(dev, s);  // cached blocks of other classes go back, then try again
     if (hipMallocAsync(&p, cls, s) != hipSuccess) {
       (void)hipGetLastError();
       return nullptr;
     }
   }
-  g_dev_live[p] = cls;
+  g_dev_live[p] = LiveBlock{cls, dev};
   return p;
 }
 
@@ -152,17 +166,17 @@ void pool_free(void* p, hipStream_t s) {
     hipFreeAsync(p, s);
     return;
   }
-  const size_t cls = it->second;
+  const LiveBlock lb = it->second;
   g_dev_live.erase(it);
   hipEvent_t ev = nullptr;
-  if (g_dev_cached + cls > g_dev_cap || hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess ||
+  if (g_dev_cached + lb.cls > g_dev_cap || hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess ||
       hipEventRecord(ev, s) != hipSuccess) {
     if (ev) hipEventDestroy(ev);
     hipFreeAsync(p, s);
     return;
   }
-  g_dev_free[cls].push_back(CachedBlock{p, ev});
-  g_dev_cached += cls;
+  g_dev_free[cache_key(lb.cls, lb.dev)].push_back(CachedBlock{p, ev});
+  g_dev_cached += lb.cls;
 }
 
 void* Arena::alloc(size_t bytes) {
