@@ -565,7 +565,8 @@ template <int T, int C>
 __global__ __launch_bounds__(PT) void qrcp_persist_kernel(const DevProb* __restrict__ probs,
                                                          const int* __restrict__ wg_prob,
                                                          double rtol, Work w) {
-  static_assert(T % PW == 0 && T % PG == 0, "slices are staged T / PW per thread, skipped PG at a time");
+  static_assert(T % PG == 0, "slices are skipped PG at a time");
+  constexpr int SU = (T * 64 + PT - 1) / PT;  // reflector rows staged per thread
   __shared__ double u[T * 64];
   __shared__ double rv[PW];
   __shared__ int ri[PW];
@@ -706,8 +707,9 @@ __global__ __launch_bounds__(PT) void qrcp_persist_kernel(const DevProb* __restr
     const double* xp = w.cbuf + ((long long)(i & 1) * nslot + dp.g0 + gp) * ldcb;
     // the winner's rows i..d-1 into LDS (zero elsewhere), loads in flight together
 #pragma unroll
-    for (int t = 0; t < T / PW; ++t) {
+    for (int t = 0; t < SU; ++t) {
       const int r = tid + PT * t;
+      if (r >= T * 64) break;
       const bool in = r >= i && r < d;
       const double v = ld_dev(xp + (in ? r : i));
       u[r] = in ? v : 0.0;
@@ -720,8 +722,9 @@ __global__ __launch_bounds__(PT) void qrcp_persist_kernel(const DevProb* __restr
     const double inv_v0 = 1.0 / v0;
     __syncthreads();  // x0 read before row i is rewritten
 #pragma unroll
-    for (int t = 0; t < T / PW; ++t) {
+    for (int t = 0; t < SU; ++t) {
       const int r = tid + PT * t;
+      if (r >= T * 64) break;
       u[r] = (r == i) ? 1.0 : u[r] * inv_v0;
     }
     if (p >= jb && p < jb + C) {
@@ -933,6 +936,7 @@ static const PVariant kPVariants[] = {
     {16, 5, reinterpret_cast<const void*>(&qrcp_persist_kernel<16, 5>)},
     {24, 4, reinterpret_cast<const void*>(&qrcp_persist_kernel<24, 4>)},
     {32, 3, reinterpret_cast<const void*>(&qrcp_persist_kernel<32, 3>)},
+    {36, 3, reinterpret_cast<const void*>(&qrcp_persist_kernel<36, 3>)},
     {40, 2, reinterpret_cast<const void*>(&qrcp_persist_kernel<40, 2>)},
 };
 

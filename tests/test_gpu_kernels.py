@@ -112,6 +112,37 @@ def _slow_decay(d, m, seed, rate):
     return g.standard_normal((d, m)) * (2.0 ** (-rate * np.arange(m)))[g.permutation(m)]
 
 
+@pytest.mark.parametrize("path", ["auto", "persistent"])
+def test_id_batched_tallest_problems(path, monkeypatch):
+    """d above 2304 rows: the persistent variant with the most rows per lane
+    (the batch's largest d picks the variant).  Same checks as below."""
+    if path != "auto":
+        monkeypatch.setenv("HSS_QRCP_PATH", path)
+    rtol = 1e-6
+    cases = [(2400, 700, 0.37, 11), (2350, 500, 0.0, 12)]
+    Ys, refs, mats = [], [], []
+    for d, m, rate, seed in cases:
+        y = _slow_decay(d, m, seed, rate)
+        mats.append(y)
+        refs.append(interp.interpolative_decomposition(y, rtol))
+        Ys.append(torch.from_numpy(np.ascontiguousarray(y.T)).cuda())
+    print(f"id_batched tallest: {len(cases)} problems, path {path}", flush=True)
+    got = P.hss_id_batched(Ys, rtol)
+    for (k, perm, E), ref, y, (d, m, rate, seed) in zip(got, refs, mats, cases):
+        assert abs(k - ref.k) <= 1, (d, m, rate, k, ref.k)
+        if rate >= 0.3:
+            assert k == ref.k and list(perm[:k]) == list(ref.J)
+            assert np.allclose(E, ref.E, rtol=1e-8, atol=1e-8 * max(1.0, np.abs(ref.E).max()))
+        J, rest = perm[:k], perm[k:]
+        X = np.zeros((k, m))
+        X[:, J] = np.eye(k)
+        if len(rest):
+            X[:, rest] = E.T
+        nu1 = np.linalg.norm(y, axis=0).max()
+        err = np.linalg.norm(y - y[:, J] @ X, 2)
+        assert err <= 10 * np.sqrt(max(1, m - k)) * rtol * nu1, (d, m, err)
+
+
 @pytest.mark.parametrize("path", ["auto", "step", "persistent"])
 def test_id_batched_large_problems(path, monkeypatch):
     """Problems on the large-problem paths (one launch per pivot step, or
