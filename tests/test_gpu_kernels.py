@@ -112,21 +112,23 @@ def _slow_decay(d, m, seed, rate):
     return g.standard_normal((d, m)) * (2.0 ** (-rate * np.arange(m)))[g.permutation(m)]
 
 
+@pytest.mark.parametrize("cases", [[(2400, 700, 0.37, 11), (2350, 500, 0.0, 12)],
+                                   [(700, 900, 0.37, 13), (650, 600, 0.0, 14)]], ids=["d2400", "d700"])
 @pytest.mark.parametrize("path", ["auto", "persistent"])
-def test_id_batched_tallest_problems(path, monkeypatch):
-    """d above 2304 rows: the persistent variant with the most rows per lane
-    (the batch's largest d picks the variant).  Same checks as below."""
+def test_id_batched_variant_problems(path, cases, monkeypatch):
+    """The batch's largest d picks the persistent variant: above 2304 rows
+    the one with the most rows per lane, at 700 rows the 12-rows-per-lane
+    one.  Same checks as below."""
     if path != "auto":
         monkeypatch.setenv("HSS_QRCP_PATH", path)
     rtol = 1e-6
-    cases = [(2400, 700, 0.37, 11), (2350, 500, 0.0, 12)]
     Ys, refs, mats = [], [], []
     for d, m, rate, seed in cases:
         y = _slow_decay(d, m, seed, rate)
         mats.append(y)
         refs.append(interp.interpolative_decomposition(y, rtol))
         Ys.append(torch.from_numpy(np.ascontiguousarray(y.T)).cuda())
-    print(f"id_batched tallest: {len(cases)} problems, path {path}", flush=True)
+    print(f"id_batched variant: {len(cases)} problems, d max {max(c[0] for c in cases)}, path {path}", flush=True)
     got = P.hss_id_batched(Ys, rtol)
     for (k, perm, E), ref, y, (d, m, rate, seed) in zip(got, refs, mats, cases):
         assert abs(k - ref.k) <= 1, (d, m, rate, k, ref.k)
