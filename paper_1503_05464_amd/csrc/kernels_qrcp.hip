@@ -934,7 +934,7 @@ struct PVariant {
 static const PVariant kPVariants[] = {
     {8, 8, reinterpret_cast<const void*>(&qrcp_persist_kernel<8, 8>)},
     {12, 7, reinterpret_cast<const void*>(&qrcp_persist_kernel<12, 7>)},
-    {16, 5, reinterpret_cast<const void*>(&qrcp_persist_kernel<16, 5>)},
+    {16, 6, reinterpret_cast<const void*>(&qrcp_persist_kernel<16, 6>)},
     {24, 4, reinterpret_cast<const void*>(&qrcp_persist_kernel<24, 4>)},
     {32, 3, reinterpret_cast<const void*>(&qrcp_persist_kernel<32, 3>)},
     {36, 3, reinterpret_cast<const void*>(&qrcp_persist_kernel<36, 3>)},

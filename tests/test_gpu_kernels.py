@@ -113,12 +113,13 @@ def _slow_decay(d, m, seed, rate):
 
 
 @pytest.mark.parametrize("cases", [[(2400, 700, 0.37, 11), (2350, 500, 0.0, 12)],
-                                   [(700, 900, 0.37, 13), (650, 600, 0.0, 14)]], ids=["d2400", "d700"])
+                                   [(900, 1100, 0.37, 15), (1000, 700, 0.0, 16)],
+                                   [(700, 900, 0.37, 13), (650, 600, 0.0, 14)]], ids=["d2400", "d1000", "d700"])
 @pytest.mark.parametrize("path", ["auto", "persistent"])
 def test_id_batched_variant_problems(path, cases, monkeypatch):
     """The batch's largest d picks the persistent variant: above 2304 rows
-    the one with the most rows per lane, at 700 rows the 12-rows-per-lane
-    one.  Same checks as below."""
+    the one with the most rows per lane, at 1000 rows the 16-rows-per-lane
+    one, at 700 rows the 12-rows-per-lane one.  Same checks as below."""
     if path != "auto":
         monkeypatch.setenv("HSS_QRCP_PATH", path)
     rtol = 1e-6
