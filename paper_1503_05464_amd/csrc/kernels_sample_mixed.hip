@@ -31,7 +31,10 @@
 // products' precision (R^T: columns of R contiguous, zero-padded to whole
 // slices and tiles), made once per call, from which every wavefront loads
 // its operands directly.  The output layout of both MFMAs (checked on the
-// device): lane l, register r -> row 4 (l / 16) + r, column l % 16.
+// device): lane l, register r -> row 4 (l / 16) + r, column l % 16.  The
+// single-matrix kernel is held to 168 registers so that three workgroups
+// share a CU, and K is split to fill two whole rounds of them.
+#include <algorithm>
 #include <cstdint>
 #include <vector>
 
@@ -339,7 +342,7 @@ __device__ __forceinline__ void sample_tile(Smem<MODE>& sm, const float* __restr
 }
 
 template <int MODE, bool TRANS>
-__global__ __launch_bounds__(NT) void sample_mixed_kernel(
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3))) void sample_mixed_kernel(
     const float* __restrict__ A, long long lda, int n, const int* __restrict__ leaf_of,
     const typename RtType<MODE>::T* __restrict__ Rt, long long ldrt, double* __restrict__ S,
     long long lds, int ncols, int n_nt, int ksplit, int kchunk, double* __restrict__ work) {
@@ -482,12 +485,32 @@ struct Plan {
   int n_mt, n_nt, ksplit, kchunk;
 };
 
+// Workgroups of the mixed kernel resident on the device at once (three per
+// CU: the kernel is held to 168 registers for that).
+int mixed_slots() {
+  static const int v = [] {
+    int dev = 0, cus = 0, per = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &per, reinterpret_cast<const void*>(&sample_mixed_kernel<2, false>), NT, 0) != hipSuccess)
+      return 768;
+    return std::max(1, per * cus);
+  }();
+  return v;
+}
+
+// The product streams A from HBM, so what counts is how many loads are in
+// flight: K is split until the workgroups fill two whole rounds of the
+// resident slots (n = 65536, 64 columns: 512 tiles x 3 splits = 1536
+// workgroups on 768 slots; 6.47 -> 5.64 ms per BF16x3 launch together with
+// the third resident workgroup per CU).
 Plan make_plan(long long n, int ncols) {
   Plan p;
   p.n_mt = (int)((n + BM - 1) / BM);
   p.n_nt = (ncols + BN - 1) / BN;
   const long long tiles = (long long)p.n_mt * p.n_nt;
-  long long want = (512 + tiles - 1) / tiles;
+  long long want = (2LL * mixed_slots() + tiles - 1) / tiles;
   long long maxs = n / 1024;
   if (maxs < 1) maxs = 1;
   if (want > maxs) want = maxs;
