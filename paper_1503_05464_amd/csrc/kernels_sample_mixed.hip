@@ -381,7 +381,7 @@ struct GroupDesc {
 };
 
 template <int MODE, bool TRANS>
-__global__ __launch_bounds__(NT) void sample_mixed_grouped_kernel(const GroupDesc* __restrict__ g,
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3))) void sample_mixed_grouped_kernel(const GroupDesc* __restrict__ g,
                                                                   int ng) {
   __shared__ Smem<MODE> sm;
   const long long b = blockIdx.x;
