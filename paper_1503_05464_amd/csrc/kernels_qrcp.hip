@@ -473,10 +473,12 @@ __global__ __launch_bounds__(ST) void id_step_kernel(const DevProb* __restrict__
     if (T > 0) {
       double y[T > 0 ? T : 1];
       double dot = 0.0;
+      // lane's rows i + lane + 64 t, addressed from one base pointer
+      double* col = wj + i + lane;
 #pragma unroll
       for (int t = 0; t < T; ++t) {
         const int r = i + lane + 64 * t;
-        y[t] = (r < d) ? wj[r] : 0.0;
+        y[t] = (r < d) ? col[64 * t] : 0.0;
       }
 #pragma unroll
       for (int t = 0; t < T; ++t) {
@@ -484,12 +486,15 @@ __global__ __launch_bounds__(ST) void id_step_kernel(const DevProb* __restrict__
         if (r < d) dot = fma(u[r - i], y[t], dot);
       }
       const double f = tau * wave_sum(dot);
+      // the stores form their addresses afresh instead of keeping the
+      // loads' T addresses live: 2T registers per lane, not 4T
+      asm volatile("" : "+v"(col) : : "memory");
 #pragma unroll
       for (int t = 0; t < T; ++t) {
         const int r = i + lane + 64 * t;
         if (r < d) {
           const double nvv = fma(-f, u[r - i], y[t]);
-          wj[r] = nvv;
+          col[64 * t] = nvv;
           if (r > i) s = fma(nvv, nvv, s);
         }
       }
@@ -1212,12 +1217,16 @@ hipError_t launch_id_factor(IdProblem* probs, int nprob, double rtol, void* work
     if (e != hipSuccess) return e;
     int nlarge = 0;
     for (int q = 0; q < nprob; ++q) nlarge += h[q].g0 >= 0 ? 1 : 0;
-    const size_t lds = dmax <= 64 * 40 ? (size_t)dmax * 8 : 0;
+    // The register variants stage rows i..d-1 of the reflector in LDS: at
+    // most 64 * kStepTMax values.  Steps with more active rows than that
+    // take the general loop, which streams the pivot column from memory.
+    constexpr int kStepTMax = 64;
+    const size_t lds = (size_t)std::min(dmax, 64 * kStepTMax) * 8;
     for (int i = 0; i < smax; ++i) {
       // rows i..d-1 are active: registers per lane follow the largest d - i
       const int tb = (dmax - i + 63) / 64;
 #define STEP(T_) hipLaunchKernelGGL(id_step_kernel<T_>, dim3(g), dim3(ST), lds, s, dprobs, dwg, i, rtol, tm, tg, w)
-      if (dmax > 64 * 40) STEP(0);
+      if (tb > kStepTMax) STEP(0);
       else if (tb <= 2) STEP(2);
       else if (tb <= 4) STEP(4);
       else if (tb <= 8) STEP(8);
@@ -1228,7 +1237,10 @@ hipError_t launch_id_factor(IdProblem* probs, int nprob, double rtol, void* work
       else if (tb <= 28) STEP(28);
       else if (tb <= 32) STEP(32);
       else if (tb <= 36) STEP(36);
-      else STEP(40);
+      else if (tb <= 40) STEP(40);
+      else if (tb <= 48) STEP(48);
+      else if (tb <= 56) STEP(56);
+      else STEP(64);
 #undef STEP
       if ((i & 63) == 63 && i + 1 < smax) {  // stop early once every problem is done
         int nd = 0;

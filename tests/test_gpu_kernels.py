@@ -146,6 +146,44 @@ def test_id_batched_variant_problems(path, cases, monkeypatch):
         assert err <= 10 * np.sqrt(max(1, m - k)) * rtol * nu1, (d, m, err)
 
 
+_TALL_CASES = [(3300, 600, 0.37, 21), (4300, 400, 0.0, 22), (2700, 600, 0.02, 23)]
+
+
+@pytest.fixture(scope="module")
+def tall_refs():
+    mats = [_slow_decay(d, m, seed, rate) for d, m, rate, seed in _TALL_CASES]
+    return mats, [interp.interpolative_decomposition(y, 1e-6) for y in mats]
+
+
+@pytest.mark.parametrize("path", ["auto", "step"])
+def test_id_batched_tall_problems(path, tall_refs, monkeypatch):
+    """Problems taller than the persistent kernel holds (d above 2560 rows)
+    run one launch per pivot step.  While more than 4096 rows are active
+    the general loop runs, after that the register variants up to 64 rows
+    per lane; the 4300-row full-rank case crosses from one to the other.
+    Same checks as above."""
+    if path != "auto":
+        monkeypatch.setenv("HSS_QRCP_PATH", path)
+    rtol = 1e-6
+    mats, refs = tall_refs
+    Ys = [torch.from_numpy(np.ascontiguousarray(y.T)).cuda() for y in mats]
+    print(f"id_batched tall: {len(mats)} problems, path {path}", flush=True)
+    got = P.hss_id_batched(Ys, rtol)
+    for (k, perm, E), ref, y, (d, m, rate, seed) in zip(got, refs, mats, _TALL_CASES):
+        assert abs(k - ref.k) <= 1, (d, m, rate, k, ref.k)
+        if rate >= 0.3:  # separated norms: the same pivots and interpolation matrix
+            assert k == ref.k and list(perm[:k]) == list(ref.J)
+            assert np.allclose(E, ref.E, rtol=1e-8, atol=1e-8 * max(1.0, np.abs(ref.E).max()))
+        J, rest = perm[:k], perm[k:]
+        X = np.zeros((k, m))
+        X[:, J] = np.eye(k)
+        if len(rest):
+            X[:, rest] = E.T
+        nu1 = np.linalg.norm(y, axis=0).max()
+        err = np.linalg.norm(y - y[:, J] @ X, 2)
+        assert err <= 10 * np.sqrt(max(1, m - k)) * rtol * nu1, (d, m, err)
+
+
 @pytest.mark.parametrize("path", ["auto", "step", "persistent"])
 def test_id_batched_large_problems(path, monkeypatch):
     """Problems on the large-problem paths (one launch per pivot step, or
