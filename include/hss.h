@@ -256,6 +256,16 @@ hss_status hss_import(long long n, const hss_tree* tree, const int* kr, const in
 
 void hss_destroy(hss_handle h);
 
+/* Gives back to the runtime the memory that the library keeps for reuse:
+   freed device blocks of 1 MB and more (up to a quarter of each device's
+   memory is kept; a compression frees and allocates the same sizes from
+   one call to the next) and pinned host staging blocks (up to 1 GiB).
+   Memory of live handles, servers and calls in flight is not touched.
+   Waits on the host until each cached block's last use has finished.
+   Callable from any thread, at any time.  Returns HSS_OK, or HSS_ERR_HIP
+   when a runtime call failed (the other blocks are still released). */
+hss_status hss_release_cached_memory(void);
+
 /* Thread-local message of the last error (empty string if none). */
 const char* hss_last_error(void);
 

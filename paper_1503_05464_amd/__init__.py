@@ -5,8 +5,8 @@ Argument marshalling only: every step runs in the HIP kernels of
 functions keep the C names:
 
     hss_compress, hss_matvec, hss_factor, hss_solve, hss_stats, hss_ranks,
-    hss_export_node, hss_import, hss_destroy, hss_random_normal, hss_sample,
-    hss_id_batched, hss_default_opts
+    hss_export_node, hss_import, hss_destroy, hss_release_cached_memory,
+    hss_random_normal, hss_sample, hss_id_batched, hss_default_opts
 
 The library is loaded on first use; if it has not been built (see
 ``build.py``) every call raises ``RuntimeError`` -- there is no fallback.
@@ -33,7 +33,8 @@ EXPORTED = [
     "hss_default_opts", "hss_compress", "hss_compress_batched", "hss_matvec", "hss_matvec_batched",
     "hss_factor",
     "hss_solve", "hss_stats",
-    "hss_ranks", "hss_export_node", "hss_import", "hss_destroy", "hss_last_error",
+    "hss_ranks", "hss_export_node", "hss_import", "hss_destroy", "hss_release_cached_memory",
+    "hss_last_error",
     "hss_random_normal", "hss_sample", "hss_id_batched",
     "hss_server_default_opts", "hss_server_create", "hss_server_submit", "hss_server_wait",
     "hss_server_destroy",
@@ -121,6 +122,7 @@ def lib() -> C.CDLL:
         L.hss_import.argtypes = [ll, C.POINTER(hss_tree), vp, vp, vp, C.POINTER(vp)]
         L.hss_destroy.argtypes = [vp]
         L.hss_destroy.restype = None
+        L.hss_release_cached_memory.argtypes = []
         L.hss_random_normal.argtypes = [C.c_ulonglong, i, ll, i, i, i, vp, ll, vp]
         L.hss_sample.argtypes = [vp, i, i, ll, ll, vp, i, vp, vp, ll, vp, vp, ll, vp]
         L.hss_id_batched.argtypes = [i, vp, vp, vp, vp, d, vp, vp, vp, vp]
@@ -394,6 +396,12 @@ def hss_destroy(h: HSSHandle) -> None:
     if h is not None and h.ptr:
         lib().hss_destroy(h.ptr)
         h.ptr = C.c_void_p()
+
+
+def hss_release_cached_memory() -> None:
+    """Returns the device and pinned host blocks the library keeps for
+    reuse to the runtime (blocks of live handles are kept)."""
+    _check(lib().hss_release_cached_memory())
 
 
 def hss_random_normal(seed: int, which: int, n: int, col0: int, col1: int, out=None, stream=None,

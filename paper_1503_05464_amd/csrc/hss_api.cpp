@@ -275,6 +275,48 @@ void pinned_put(char* p, size_t bytes) {
 }
 }  // namespace
 
+// Frees every cached device block, each once its last use has finished, and
+// every kept pinned host block.  Blocks in use are not touched.  Returns the
+// first runtime error; the remaining blocks are still released.
+hipError_t release_cached_memory() {
+  hipError_t first = hipSuccess;
+  auto note = [&first](hipError_t e) {
+    if (first == hipSuccess && e != hipSuccess) first = e;
+  };
+  {
+    std::lock_guard<std::mutex> lk(g_dev_mu);
+    int cur = 0;
+    note(hipGetDevice(&cur));
+    std::vector<int> devs;
+    for (auto& kv : g_dev_free) {
+      const int dev = (int)(kv.first & 255);
+      const size_t cls = (size_t)(kv.first >> 8);
+      note(hipSetDevice(dev));
+      for (CachedBlock& c : kv.second) {
+        note(hipEventSynchronize(c.ev));
+        hipEventDestroy(c.ev);
+        note(hipFreeAsync(c.p, nullptr));
+        g_dev_cached -= cls;
+      }
+      if (!kv.second.empty() && std::find(devs.begin(), devs.end(), dev) == devs.end()) devs.push_back(dev);
+    }
+    g_dev_free.clear();
+    for (int dev : devs) {  // the runtime pool gives freed memory back at a synchronization
+      note(hipSetDevice(dev));
+      note(hipStreamSynchronize(nullptr));
+    }
+    note(hipSetDevice(cur));
+  }
+  std::vector<std::pair<size_t, char*>> pins;
+  {
+    std::lock_guard<std::mutex> lk(g_pin_mu);
+    pins.swap(g_pin_free);
+    g_pin_bytes = 0;
+  }
+  for (auto& b : pins) note(hipHostFree(b.second));
+  return first;
+}
+
 hipError_t Staging::init(size_t bytes, hipStream_t s) {
   size_t b = (size_t)1 << 20;
   while (b < bytes) b <<= 1;
@@ -1667,6 +1709,12 @@ hss_status hss_import(long long n, const hss_tree* tree, const int* kr, const in
 }
 
 void hss_destroy(hss_handle h) { free_handle(h); }
+
+hss_status hss_release_cached_memory(void) {
+  g_err.clear();
+  HIPCHK(hss::release_cached_memory());
+  return HSS_OK;
+}
 
 hss_status hss_random_normal(unsigned long long seed, int which, long long n, int col0, int col1,
                              int sample_prec, double* R, long long ld, void* stream) {

@@ -120,6 +120,26 @@ def test_not_converged_is_usable():
     assert torch.isfinite(P.hss_matvec(h, x)).all()
 
 
+def test_release_cached_memory_keeps_live_handles():
+    """Releasing the library's cached blocks leaves a live handle usable and
+    changes no result: the same compression after the release (fresh
+    blocks) gives bit-identical products."""
+    cfg = W.CONFIGS["toeplitz1024"]
+    A = W.toeplitz_inverse_distance(cfg["n"])
+    kw = dict(rtol=cfg["rtol"], d0=cfg["d0"], dd=cfg["dd"], leaf_size=cfg["leaf"])
+    x = torch.from_numpy(W.uniform_rhs(cfg["n"], 4, cfg["rhs_seed"])).cuda()
+    h0 = _gpu(A, **kw)
+    b0 = P.hss_matvec(h0, x).cpu().numpy()
+    h1 = _gpu(A, **kw)
+    P.hss_destroy(h1)  # its blocks go to the cache
+    P.hss_release_cached_memory()
+    assert np.array_equal(P.hss_matvec(h0, x).cpu().numpy(), b0)
+    h2 = _gpu(A, **kw)
+    assert np.array_equal(P.hss_matvec(h2, x).cpu().numpy(), b0)
+    P.hss_release_cached_memory()  # nothing cached but the blocks of h0, h2: both stay live
+    assert np.array_equal(P.hss_matvec(h2, x).cpu().numpy(), b0)
+
+
 def _oracle_to_import(Ho):
     tree = Ho.tree
     nodes = []
