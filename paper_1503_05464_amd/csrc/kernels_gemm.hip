@@ -12,9 +12,13 @@
 // split in two segments (rows below `split` from one buffer, the rest from
 // another), which stacks the two children's blocks [X_a; X_b] without a copy.
 //
-// Arithmetic: FP64 FMA on the vector ALU (on gfx950 FP64 vector and matrix
-// peaks are equal), 4 x 4 register blocking per thread, k-slices of 16
-// staged through LDS.
+// Arithmetic: the 16x16x4 FP64 MFMA, each of the four wavefronts of a
+// workgroup owning a 32 x 32 sub-tile (2 x 2 MFMA blocks).  A and B are
+// staged through LDS in k-slices of 16, both k-major so that the MFMA
+// operands are read conflict-free; the next slice is loaded into registers
+// while the current one is multiplied.  (A vector-FMA version with 4 x 4
+// outputs per thread measured 24 ms slower per N = 65536 compression and
+// within noise on batches of small products.)
 #include <climits>
 
 #include "hss_internal.h"
@@ -23,6 +27,8 @@ namespace hss {
 namespace {
 
 constexpr int TM = 64, TN = 64, TK = 16, NTH = 256;
+
+typedef double dbl4 __attribute__((ext_vector_type(4)));
 
 struct DevDesc {
   GemmDesc g;
@@ -39,8 +45,9 @@ __device__ __forceinline__ double* seg_row_out(const SegOut& s, int q) {
   return (qq < s.split) ? s.p0 + (long long)qq * s.ld : s.p1 + (long long)(qq - s.split) * s.ld;
 }
 
-__global__ __launch_bounds__(NTH) void gemm_batched_kernel(const DevDesc* __restrict__ descs,
-                                                           int nprob) {
+// held to four wavefronts per SIMD (at most 128 registers; it needs 94)
+__global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(4))) void gemm_batched_kernel(
+    const DevDesc* __restrict__ descs, int nprob) {
   // locate the problem of this tile
   const long long t = blockIdx.x;
   int lo = 0, hi = nprob - 1;
@@ -59,16 +66,12 @@ __global__ __launch_bounds__(NTH) void gemm_batched_kernel(const DevDesc* __rest
   __shared__ double Bs[TK][TN + 4];
 
   const int tid = threadIdx.x;
-  const int tx = tid & 15;  // columns c0 + 4*tx ..
-  const int ty = tid >> 4;  // rows r0 + 4*ty ..
-  double acc[4][4];
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;  // this wavefront's 32 x 32 sub-tile
 
-  for (int k0 = 0; k0 < g.K; k0 += TK) {
-    // A slice: TM x TK, 4 per thread
+  // this thread's share of a k-slice: 4 entries of A and 4 of B
+  double va[4], vb[4];
+  auto load = [&](int k0) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int e = tid + q * NTH;
@@ -81,52 +84,79 @@ __global__ __launch_bounds__(NTH) void gemm_batched_kernel(const DevDesc* __rest
         rr = e % TM;
       }
       const int r = r0 + rr, k = k0 + kk;
-      double v = 0.0;
-      if (r < g.M && k < g.K)
-        v = g.transA ? g.A[(long long)k * g.lda + r] : g.A[(long long)r * g.lda + k];
-      As[kk][rr] = v;
+      va[q] = (r < g.M && k < g.K) ? (g.transA ? g.A[(long long)k * g.lda + r] : g.A[(long long)r * g.lda + k])
+                                   : 0.0;
     }
-    // B slice: TK x TN, gathered rows
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int e = tid + q * NTH;
       const int kk = e / TN, cc = e % TN;
       const int k = k0 + kk, c = c0 + cc;
-      double v = 0.0;
-      if (k < g.K && c < g.N) v = seg_row(g.B, k)[c];
-      Bs[kk][cc] = v;
+      vb[q] = (k < g.K && c < g.N) ? seg_row(g.B, k)[c] : 0.0;
+    }
+  };
+  auto store = [&]() {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int e = tid + q * NTH;
+      if (!g.transA) As[e % TK][e / TK] = va[q];
+      else As[e / TM][e % TM] = va[q];
+      Bs[e / TN][e % TN] = vb[q];
+    }
+  };
+
+  dbl4 acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = dbl4{0.0, 0.0, 0.0, 0.0};
+
+  if (g.K > 0) {
+    load(0);
+    store();
+  }
+  __syncthreads();
+  for (int k0 = 0; k0 < g.K; k0 += TK) {
+    const int kn = k0 + TK;
+    if (kn < g.K) load(kn);  // next slice in flight while this one is multiplied
+#pragma unroll
+    for (int kk = 0; kk < TK; kk += 4) {
+      const int kr = kk + (lane >> 4);
+      double a[2], b[2];
+#pragma unroll
+      for (int mb = 0; mb < 2; ++mb) a[mb] = As[kr][wm * 32 + mb * 16 + (lane & 15)];
+#pragma unroll
+      for (int nb = 0; nb < 2; ++nb) b[nb] = Bs[kr][wn * 32 + nb * 16 + (lane & 15)];
+#pragma unroll
+      for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+        for (int nb = 0; nb < 2; ++nb)
+          acc[mb][nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[mb], b[nb], acc[mb][nb], 0, 0, 0);
     }
     __syncthreads();
-#pragma unroll
-    for (int kk = 0; kk < TK; ++kk) {
-      double a[4], b[4];
-#pragma unroll
-      for (int i = 0; i < 4; ++i) a[i] = As[kk][ty * 4 + i];
-#pragma unroll
-      for (int j = 0; j < 4; ++j) b[j] = Bs[kk][tx * 4 + j];
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = fma(a[i], b[j], acc[i][j]);
-    }
+    if (kn < g.K) store();
     __syncthreads();
   }
 
+  // D layout of the 16x16x4 f64 MFMA: lane l, register q -> row l/16 + 4q,
+  // column l%16 of the 16 x 16 block
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const int r = r0 + ty * 4 + i;
-    if (r >= g.M) continue;
-    const double* crow = (g.beta != 0.0) ? seg_row(g.C, r) : nullptr;
-    double* drow = seg_row_out(g.D, r);
+  for (int mb = 0; mb < 2; ++mb)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int c = c0 + tx * 4 + j;
-      if (c >= g.N) continue;
-      double v = g.alpha * acc[i][j];
-      if (crow) v += g.beta * crow[c];
-      drow[c] = v;
+    for (int q = 0; q < 4; ++q) {
+      const int r = r0 + wm * 32 + mb * 16 + (lane >> 4) + 4 * q;
+      if (r >= g.M) continue;
+      const double* crow = (g.beta != 0.0) ? seg_row(g.C, r) : nullptr;
+      double* drow = seg_row_out(g.D, r);
+#pragma unroll
+      for (int nb = 0; nb < 2; ++nb) {
+        const int c = c0 + wn * 32 + nb * 16 + (lane & 15);
+        if (c >= g.N) continue;
+        double v = g.alpha * acc[mb][nb][q];
+        if (crow) v += g.beta * crow[c];
+        drow[c] = v;
+      }
     }
-  }
 }
 
 }  // namespace
