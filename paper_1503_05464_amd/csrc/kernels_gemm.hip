@@ -17,8 +17,8 @@
 // staged through LDS in k-slices of 16, both k-major so that the MFMA
 // operands are read conflict-free; the next slice is loaded into registers
 // while the current one is multiplied.  (A vector-FMA version with 4 x 4
-// outputs per thread measured 24 ms slower per N = 65536 compression and
-// within noise on batches of small products.)
+// outputs per thread took 1.2 to 1.4 times as long, on large and on small
+// batched products alike.)
 #include <climits>
 
 #include "hss_internal.h"
