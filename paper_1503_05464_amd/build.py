@@ -25,7 +25,7 @@ ARCH = "gfx950"
 COMMON = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-    "-I", INCLUDE, "-Wall", "-Wno-unused-function", "-Wno-unused-result",
+    "-I", INCLUDE, "-Wall",
 ]
 
 

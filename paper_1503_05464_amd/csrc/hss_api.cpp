@@ -87,6 +87,18 @@ size_t g_dev_cached = 0;
 size_t g_dev_cap = 0;
 std::once_flag g_dev_once;
 
+}  // namespace
+
+// Orders stream s after event ev: a device-side wait, or, when that cannot be
+// queued, a host-side wait for ev (the same ordering, coarser).
+void order_after(hipStream_t s, hipEvent_t ev) {
+  if (hipStreamWaitEvent(s, ev, 0) != hipSuccess) {
+    (void)hipGetLastError();
+    (void)hipEventSynchronize(ev);
+  }
+}
+
+namespace {
 unsigned long long cache_key(size_t cls, int dev) { return ((unsigned long long)cls << 8) | (unsigned)(dev & 255); }
 
 constexpr size_t kCacheMin = (size_t)1 << 20;
@@ -109,9 +121,9 @@ void trim_cache(int dev, hipStream_t s) {
     }
     const size_t cls = (size_t)(it->first >> 8);
     for (CachedBlock& c : it->second) {
-      hipStreamWaitEvent(s, c.ev, 0);
-      hipEventDestroy(c.ev);
-      hipFreeAsync(c.p, s);
+      order_after(s, c.ev);
+      (void)hipEventDestroy(c.ev);
+      (void)hipFreeAsync(c.p, s);
       g_dev_cached -= cls;
     }
     it = g_dev_free.erase(it);
@@ -141,8 +153,8 @@ void* pool_alloc(size_t bytes, hipStream_t s) {
     CachedBlock c = it->second.back();
     it->second.pop_back();
     g_dev_cached -= cls;
-    hipStreamWaitEvent(s, c.ev, 0);
-    hipEventDestroy(c.ev);
+    order_after(s, c.ev);
+    (void)hipEventDestroy(c.ev);
     g_dev_live[c.p] = LiveBlock{cls, dev};
     return c.p;
   }
@@ -163,7 +175,7 @@ void pool_free(void* p, hipStream_t s) {
   std::lock_guard<std::mutex> lk(g_dev_mu);
   auto it = g_dev_live.find(p);
   if (it == g_dev_live.end()) {  // below the cached sizes
-    hipFreeAsync(p, s);
+    (void)hipFreeAsync(p, s);
     return;
   }
   const LiveBlock lb = it->second;
@@ -171,8 +183,8 @@ void pool_free(void* p, hipStream_t s) {
   hipEvent_t ev = nullptr;
   if (g_dev_cached + lb.cls > g_dev_cap || hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess ||
       hipEventRecord(ev, s) != hipSuccess) {
-    if (ev) hipEventDestroy(ev);
-    hipFreeAsync(p, s);
+    if (ev) (void)hipEventDestroy(ev);
+    (void)hipFreeAsync(p, s);
     return;
   }
   g_dev_free[cache_key(lb.cls, lb.dev)].push_back(CachedBlock{p, ev});
@@ -211,9 +223,11 @@ void* Scratch::ensure(size_t bytes, hipStream_t s) {
     if (s != last && p) {  // first use on another stream: wait for the previous one
       hipEvent_t ev;
       if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) == hipSuccess) {
-        hipEventRecord(ev, last);
-        hipStreamWaitEvent(s, ev, 0);
-        hipEventDestroy(ev);
+        if (hipEventRecord(ev, last) == hipSuccess) order_after(s, ev);
+        else (void)hipStreamSynchronize(last);
+        (void)hipEventDestroy(ev);
+      } else {
+        (void)hipStreamSynchronize(last);
       }
     }
     last = s;
@@ -271,7 +285,7 @@ void pinned_put(char* p, size_t bytes) {
       return;
     }
   }
-  hipHostFree(p);
+  (void)hipHostFree(p);
 }
 }  // namespace
 
@@ -294,7 +308,7 @@ hipError_t release_cached_memory() {
       note(hipSetDevice(dev));
       for (CachedBlock& c : kv.second) {
         note(hipEventSynchronize(c.ev));
-        hipEventDestroy(c.ev);
+        (void)hipEventDestroy(c.ev);
         note(hipFreeAsync(c.p, nullptr));
         g_dev_cached -= cls;
       }
@@ -331,7 +345,7 @@ hipError_t Staging::init(size_t bytes, hipStream_t s) {
 
 void Staging::release() {
   // queued copies may still read the pinned block: it is reused only after them
-  if (host && stream_used) hipStreamSynchronize(stream);
+  if (host && stream_used) (void)hipStreamSynchronize(stream);
   pinned_put(host, cap);
   pool_free(dev, stream);
   host = dev = nullptr;
@@ -501,10 +515,14 @@ struct EventTimer {  // HIP events on the compression stream, summed at the end
   std::vector<hipEvent_t> ev;
   std::vector<int> b, e, cat;  // begin, end, category (0 sample, 1 levels, 2 id, 3 sample GEMM)
   hipStream_t s = nullptr;
-  int begin() {
-    hipEvent_t x;
-    hipEventCreate(&x);
-    hipEventRecord(x, s);
+  int begin() {  // an event that cannot be made or recorded is kept as null and not timed
+    hipEvent_t x = nullptr;
+    if (hipEventCreate(&x) != hipSuccess) {
+      x = nullptr;
+    } else if (hipEventRecord(x, s) != hipSuccess) {
+      (void)hipEventDestroy(x);
+      x = nullptr;
+    }
     ev.push_back(x);
     return (int)ev.size() - 1;
   }
@@ -515,13 +533,13 @@ struct EventTimer {  // HIP events on the compression stream, summed at the end
     cat.push_back(c);
   }
   void finish(double* acc) {
-    hipStreamSynchronize(s);
+    (void)hipStreamSynchronize(s);
     for (size_t i = 0; i < b.size(); ++i) {
       float ms = 0;
-      hipEventElapsedTime(&ms, ev[b[i]], ev[e[i]]);
-      acc[cat[i]] += ms;
+      if (ev[b[i]] && ev[e[i]] && hipEventElapsedTime(&ms, ev[b[i]], ev[e[i]]) == hipSuccess) acc[cat[i]] += ms;
     }
-    for (auto x : ev) hipEventDestroy(x);
+    for (auto x : ev)
+      if (x) (void)hipEventDestroy(x);
     ev.clear();
     b.clear();
     e.clear();
@@ -783,7 +801,7 @@ hss_status process_items(Handle& L, Arena& W, std::vector<Item>& items, EventTim
     void* wk = L.work_id.ensure(wb, L.stream);
     if (!wk) return fail(HSS_ERR_ALLOC, "ID workspace");
     if (L.k_host_cap < np) {
-      if (L.k_host) hipHostFree(L.k_host);
+      if (L.k_host) (void)hipHostFree(L.k_host);
       L.k_host = nullptr;
       HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&L.k_host), (size_t)np * 2 * 4, hipHostMallocDefault));
       L.k_host_cap = np * 2;
@@ -1138,14 +1156,14 @@ hss_status new_handle(hss_handle* out, long long n, hipStream_t s, hss_handle_s*
 void free_handle(hss_handle_s* p) {
   if (!p) return;
   Handle& H = p->h;
-  if (H.stream) hipStreamSynchronize(H.stream);
+  if (H.stream) (void)hipStreamSynchronize(H.stream);
   H.gen.reset();  // frees the arena unless other handles of its batch still hold it
   H.work_id.release();
   H.work_sample.release();
   H.work_mv.release();
   H.work_misc.release();
   H.staging.release();
-  if (H.k_host) hipHostFree(H.k_host);
+  if (H.k_host) (void)hipHostFree(H.k_host);
   delete p;
 }
 
@@ -1668,8 +1686,12 @@ hss_status hss_import(long long n, const hss_tree* tree, const int* kr, const in
       v.B12 = arena_alloc<double>(H, (size_t)a.kr * c.kc);
       v.B21 = arena_alloc<double>(H, (size_t)c.kr * a.kc);
       if ((a.kr * c.kc && !g.B12) || (c.kr * a.kc && !g.B21)) return bad("B missing");
-      if (a.kr * c.kc) hipMemcpy(v.B12, g.B12, (size_t)a.kr * c.kc * 8, hipMemcpyHostToDevice);
-      if (c.kr * a.kc) hipMemcpy(v.B21, g.B21, (size_t)c.kr * a.kc * 8, hipMemcpyHostToDevice);
+      if (a.kr * c.kc &&
+          hipMemcpy(v.B12, g.B12, (size_t)a.kr * c.kc * 8, hipMemcpyHostToDevice) != hipSuccess)
+        return bad("copy B12");
+      if (c.kr * a.kc &&
+          hipMemcpy(v.B21, g.B21, (size_t)c.kr * a.kc * 8, hipMemcpyHostToDevice) != hipSuccess)
+        return bad("copy B21");
     }
     if (t == 0) continue;
     for (int side = 0; side < 2; ++side) {
@@ -1690,8 +1712,10 @@ hss_status hss_import(long long n, const hss_tree* tree, const int* kr, const in
       int* dp = arena_alloc<int>(H, (size_t)m);
       double* de = arena_alloc<double>(H, (size_t)(m - k) * k + 1);
       if (!dp || !de) return bad("alloc");
-      if (m) hipMemcpy(dp, perm.data(), (size_t)m * 4, hipMemcpyHostToDevice);
-      if ((m - k) * k) hipMemcpy(de, E, (size_t)(m - k) * k * 8, hipMemcpyHostToDevice);
+      if (m && hipMemcpy(dp, perm.data(), (size_t)m * 4, hipMemcpyHostToDevice) != hipSuccess)
+        return bad("copy permutation");
+      if ((m - k) * k && hipMemcpy(de, E, (size_t)(m - k) * k * 8, hipMemcpyHostToDevice) != hipSuccess)
+        return bad("copy E");
       if (side) {
         v.perm_c = dp;
         v.Ec = de;
@@ -1758,7 +1782,7 @@ hss_status hss_sample(const void* A, int dtype, int sample_prec, long long n, lo
     e = launch_sample_mixed(static_cast<const float*>(A), n, lda, leaf_of, ncols, sample_prec, Rr, Rc,
                             ldr, Sr, Sc, lds, work, st, s);
   }
-  if (work) hipFreeAsync(work, s);
+  if (work) (void)hipFreeAsync(work, s);
   st.release();
   HIPCHK(e);
   return HSS_OK;
@@ -1798,7 +1822,7 @@ hss_status hss_id_batched(int nprob, const double* const* ys, const int* m, cons
   for (int q = 0; q < nprob; ++q) sel[q] = q;
   if (e == hipSuccess) e = launch_id_finish(pr.data(), nprob, k, sel.data(), nprob, base, st, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
-  hipFree(base);
+  (void)hipFree(base);
   st.release();
   HIPCHK(e);
   return HSS_OK;

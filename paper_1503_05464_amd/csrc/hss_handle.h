@@ -19,6 +19,8 @@ namespace hss {
 // freeing never synchronizes the device or blocks other host threads.
 void* pool_alloc(size_t bytes, hipStream_t s);
 void pool_free(void* p, hipStream_t s);
+// orders stream s after event ev (device-side wait; host-side if that fails)
+void order_after(hipStream_t s, hipEvent_t ev);
 
 struct Arena {
   hipStream_t stream = nullptr;  // stream of the allocations and of the release

@@ -119,8 +119,8 @@ struct hss_server_s {
     const int nb = (int)batch.size();
     for (Req* r : batch)  // the inputs are read only after the submitter wrote them
       if (r->ready) {
-        hipStreamWaitEvent(s, r->ready, 0);
-        hipEventDestroy(r->ready);
+        hss::order_after(s, r->ready);
+        (void)hipEventDestroy(r->ready);
         r->ready = nullptr;
       }
     std::vector<const void*> As(nb);
@@ -150,7 +150,7 @@ struct hss_server_s {
         r->info.max_rank = stt.max_rank;
       }
     }
-    hipStreamSynchronize(s);
+    (void)hipStreamSynchronize(s);
     for (hss_handle h : hs) hss_destroy(h);
   }
 
@@ -180,7 +180,7 @@ struct hss_server_s {
       }
       finish(batch);
     }
-    if (s) hipStreamDestroy(s);
+    if (s) (void)hipStreamDestroy(s);
   }
 };
 
@@ -241,13 +241,13 @@ hss_status hss_server_submit(hss_server sv, const void* A, int dtype, long long 
   r->footprint = footprint_of(n, r->opts);
   if (hipEventCreateWithFlags(&r->ready, hipEventDisableTiming) != hipSuccess ||
       hipEventRecord(r->ready, static_cast<hipStream_t>(stream)) != hipSuccess) {
-    if (r->ready) hipEventDestroy(r->ready);
+    if (r->ready) (void)hipEventDestroy(r->ready);
     return hss::set_error(HSS_ERR_HIP, "event on the submitting stream");
   }
   {
     std::lock_guard<std::mutex> lk(sv->mu);
     if (sv->stop) {
-      hipEventDestroy(r->ready);
+      (void)hipEventDestroy(r->ready);
       return hss::set_error(HSS_ERR_STATE, "server is shutting down");
     }
     r->id = sv->next_id++;

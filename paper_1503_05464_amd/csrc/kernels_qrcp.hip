@@ -583,7 +583,7 @@ __global__ __launch_bounds__(PT) void qrcp_persist_kernel(const DevProb* __restr
   const DevProb dp = probs[q];
   const int m = dp.p.m, d = dp.p.d;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const bool leader = (blockIdx.x == dp.g0 && tid == 0);
+  const bool leader = ((int)blockIdx.x == dp.g0 && tid == 0);
   constexpr int CPG = PW * C;  // columns per workgroup
   const int jb = (blockIdx.x - dp.g0) * CPG + wave * C;
   int* __restrict__ step = w.step + dp.off;
@@ -920,8 +920,6 @@ size_t id_workspace_bytes(const IdProblem* probs, int nprob) {
 // Register-resident classes (wavefronts, columns per wavefront, rows per
 // lane) chosen so that no instance spills: -1 = use the step kernels.
 constexpr int kSmallClasses = 10;
-static int small_class(const IdProblem& p);
-static bool small_problem(const IdProblem& p) { return small_class(p) >= 0; }
 static int small_class(const IdProblem& p) {
   const int m = p.m, d = p.d;
   if (m > 256 || d > 192 || m == 0 || d == 0) return -1;
