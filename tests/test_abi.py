@@ -69,3 +69,23 @@ def test_missing_library_fails_loudly(monkeypatch):
     monkeypatch.setattr(P, "LIB_PATH", "/nonexistent/libhss.so")
     with pytest.raises(RuntimeError, match="no fallback"):
         P.lib()
+
+
+@pytest.mark.parametrize("tree, n, msg", [
+    (([0, 0, 5], [10, 5, 10], [1, -1, -1], [2, -1, -1]), 12, b"root interval"),
+    (([0, 0, 6], [10, 5, 10], [1, -1, -1], [2, -1, -1]), 10, b"do not split"),
+    (([0, 0, 5], [10, 5, 10], [1, -1, -1], [-1, -1, -1]), 10, b"one child"),
+    (([0, 0, 5], [10, 5, 10], [1, -1, -1], [7, -1, -1]), 10, b"bad child"),
+    (([0, 0, 5, 0], [10, 5, 10, 5], [1, -1, -1, -1], [2, -1, -1, -1]), 10, b"not reachable"),
+    (([0, 0, 0], [10, 0, 10], [1, -1, -1], [2, -1, -1]), 10, b"empty"),
+    (([0, 0, 5, 0, 5], [10, 5, 10, 5, 10], [1, 3, -1, -1, -1], [2, 4, -1, -1, -1]), 10, b"do not split"),
+], ids=["root", "split", "one-child", "child-index", "unreachable", "empty", "grandchildren"])
+def test_user_tree_errors(tree, n, msg):
+    """A user tree that is not a binary partition of [0, n) is rejected on
+    the host, before any device work, with a message naming the defect."""
+    L = P.lib()
+    out = ctypes.c_void_p()
+    t, keep = P._tree_struct(tree)
+    st = L.hss_compress(ctypes.c_void_p(16), P.HSS_F64, n, n, ctypes.byref(t), None, None, ctypes.byref(out))
+    assert st == P.HSS_ERR_ARG and out.value is None
+    assert msg in L.hss_last_error(), L.hss_last_error()
