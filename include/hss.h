@@ -159,7 +159,10 @@ hss_status hss_compress_batched(int nmat, const void* const* A, int dtype, const
 
 /*
  * b = A_HSS x (Alg. 2) for nrhs columns.  x: DEVICE n x nrhs (ldx >= nrhs),
- * b: DEVICE n x nrhs (ldb >= nrhs), must not overlap x.  Stream-ordered.
+ * b: DEVICE n x nrhs (ldb >= nrhs), must not overlap x.  Host-synchronous:
+ * all device work goes to `stream`, and the call returns once b is written
+ * (its launch descriptors are staged in pinned memory that the next call on
+ * the handle reuses).
  */
 hss_status hss_matvec(hss_handle h, int nrhs, const double* x, long long ldx,
                       double* b, long long ldb, void* stream);
@@ -187,7 +190,8 @@ hss_status hss_matvec_batched(int nmat, const hss_handle* h, int nrhs, const dou
 hss_status hss_factor(hss_handle h, void* stream);
 
 /* Solve A_HSS x = b after hss_factor (Alg. 4).  b, x: DEVICE n x nrhs;
- * HSS_ERR_STATE before hss_factor.  Stream-ordered. */
+ * HSS_ERR_STATE before hss_factor.  Host-synchronous, like hss_matvec: all
+ * device work goes to `stream`, and the call returns once x is written. */
 hss_status hss_solve(hss_handle h, int nrhs, const double* b, long long ldb,
                      double* x, long long ldx, void* stream);
 
@@ -364,7 +368,8 @@ hss_status hss_random_normal(unsigned long long seed, int which, long long n, in
  * Sc/Rc may be NULL.  sample_prec as in hss_sample_prec: the reduced modes
  * need dtype HSS_F32 and R already representable in their precision
  * (hss_random_normal with the same sample_prec); HSS_ERR_ARG otherwise.
- * Stream-ordered.
+ * Stream-ordered with HSS_SAMPLE_F64; the reduced-precision modes stage
+ * launch descriptors and return once the products are written.
  */
 hss_status hss_sample(const void* A, int dtype, int sample_prec, long long n, long long lda,
                       const int* leaf_of, int ncols, const double* Rr, const double* Rc,
