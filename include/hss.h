@@ -123,8 +123,9 @@ typedef struct {
  *  *out    receives a new handle (also on HSS_NOT_CONVERGED).
  * Host-synchronous: returns when the handle is complete.  All device work is
  * issued on `stream`.  The random matrices, samples and other buffers of the
- * compression (about 4 n d_max doubles and more) are freed before the call
- * returns; the handle keeps only the generators.
+ * compression (about 4 n d_max doubles and more) are released before the
+ * call returns, to the library's cache of device blocks (see
+ * hss_release_cached_memory); the handle keeps only the generators.
  */
 hss_status hss_compress(const void* A, int dtype, long long n, long long lda,
                         const hss_tree* tree, const hss_opts* opts, void* stream,
