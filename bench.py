@@ -453,8 +453,9 @@ def main() -> int:
                     help="precision of the sampling products (reduced modes need the FP32 A)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: the compression path has no multi-GPU mode "
-              "(see DESIGN.md for how it would shard)", file=sys.stderr)
+        print("bench.py runs on one GPU only: the compression path has no multi-GPU mode; "
+              "whole matrices (batches, served requests) would shard one per GPU",
+              file=sys.stderr)
         return 2
     if args.workload == "batched512":
         return run_batched(args)
