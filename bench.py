@@ -361,7 +361,7 @@ def run_serve(args) -> int:
     # admission budget: half of the device memory (the request matrices of
     # the pool live outside it)
     budget = int(0.5 * torch.cuda.mem_get_info()[1])
-    srv = P.HSSServer(hbm_budget=budget, max_batch=32, workers=4)
+    srv = P.HSSServer(hbm_budget=budget, max_batch=32, workers=args.serve_workers)
     kw0 = dict(d0=64, dd=32, d_max=1024, leaf_size=128, p_margin=32, sample_prec="bf16x3")
     print(f"[bench] serving {nreq} requests at {rate:g}/s", file=sys.stderr, flush=True)
     t_start = time.perf_counter()
@@ -420,7 +420,7 @@ def run_serve(args) -> int:
             "workload": f"serve: Poisson arrivals at {rate:g}/s (seed 6), pool of 16 FP32 matrices N log-uniform "
                         "in [512, 32768] (log kernel on a circle or Gaussian kernel in 3-D), rtol in "
                         "{1e-4, 1e-6}, nrhs in {1..64}, leaf 128, d0 64, dd 32, p_margin 32, BF16X3 sampling",
-            "requests": nreq, "workers": 4, "max_batch": 32, "hbm_budget": "50% of device memory",
+            "requests": nreq, "workers": args.serve_workers, "max_batch": 32, "hbm_budget": "50% of device memory",
         },
         "latency_s": {"p50": round(float(np.percentile(lat, 50)), 4), "p90": round(float(np.percentile(lat, 90)), 4),
                       "p99": round(float(np.percentile(lat, 99)), 4), "max": round(float(lat.max()), 4)},
@@ -444,6 +444,7 @@ def main() -> int:
     ap.add_argument("--workload", default="gauss65536", choices=sorted(WORKLOADS) + ["batched512", "serve"])
     ap.add_argument("--serve-requests", type=int, default=400, help="requests of the serve workload")
     ap.add_argument("--serve-rate", type=float, default=200.0, help="Poisson arrival rate of the serve workload")
+    ap.add_argument("--serve-workers", type=int, default=4, help="worker threads (streams) of the server")
     ap.add_argument("--rtol", type=float, default=None)
     ap.add_argument("--p-margin", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
