@@ -43,7 +43,7 @@ WORKLOADS = {
     "gauss65536": dict(n=65536, kind="gauss", leaf=256, rtol=1e-6, d0=128, dd=64, d_max=4096,
                        storage="f32", point_seed=4, p_margin=256),
     "circle16384": dict(n=16384, kind="log", leaf=128, rtol=1e-8, d0=128, dd=64, d_max=4096,
-                        storage="f64", point_seed=2, p_margin=10),
+                        storage="f64", point_seed=2, p_margin=10, ulv_rhs_seed=3),
     "toeplitz1024": dict(n=1024, kind="toeplitz", leaf=64, rtol=1e-6, d0=64, dd=32, d_max=4096,
                          storage="f64", point_seed=0, p_margin=10),
 }
@@ -467,6 +467,7 @@ def main() -> int:
     import torch
 
     import paper_1503_05464_amd as P
+    import workloads as W
 
     cfg = dict(WORKLOADS[args.workload])
     if args.rtol is not None:
@@ -484,11 +485,22 @@ def main() -> int:
     b = torch.empty_like(x)
     kw = dict(rtol=cfg["rtol"], d0=cfg["d0"], dd=cfg["dd"], d_max=cfg["d_max"], leaf_size=cfg["leaf"],
               p_margin=cfg["p_margin"], seed=0, sample_prec=args.sample_prec)
+    # workloads with a ULV solve: one N(0,1) right-hand side
+    ulv = "ulv_rhs_seed" in cfg
+    rhs = torch.from_numpy(W.normal_rhs(cfg["n"], 1, cfg["ulv_rhs_seed"])).to(dev) if ulv else None
 
     def step():
         h = P.hss_compress(A, **kw)
         P.hss_matvec(h, x, b)
-        st = P.hss_stats(h)
+        st = dict(P.hss_stats(h))
+        if ulv:  # factor and solve return once their results are written
+            t1 = time.perf_counter()
+            P.hss_factor(h)
+            t2 = time.perf_counter()
+            P.hss_solve(h, rhs)
+            t3 = time.perf_counter()
+            st["t_factor_ms"] = (t2 - t1) * 1e3
+            st["t_solve_ms"] = (t3 - t2) * 1e3
         P.hss_destroy(h)
         return st
 
@@ -543,6 +555,17 @@ def main() -> int:
     bh = P.hss_matvec(h, xs)
     bd = dense_matvec(A, xs)
     mv_err = float(torch.linalg.norm(bh - bd) / torch.linalg.norm(bd))
+    solve_err = None
+    if ulv:  # backward error of the ULV solution against the dense A: ||A x - b|| / (||A||_2 ||x||)
+        P.hss_factor(h)
+        xsol = P.hss_solve(h, rhs)
+        r = dense_matvec(A, xsol) - rhs
+        v = torch.ones((cfg["n"], 1), dtype=torch.float64, device=dev)
+        for _ in range(20):  # ||A||_2 by power iteration (a lower bound)
+            v = dense_matvec(A, v)
+            v = v / torch.linalg.norm(v)
+        anorm = float(torch.linalg.norm(dense_matvec(A, v)))
+        solve_err = float(torch.linalg.norm(r)) / (anorm * float(torch.linalg.norm(xsol)))
     frob = None
     if not args.no_frob:
         frob = frob_error(P, h, A)
@@ -575,13 +598,16 @@ def main() -> int:
             "sample_prec": args.sample_prec,
             "n": cfg["n"], "rtol": cfg["rtol"], "d_final": st["d_final"], "passes": st["passes"],
             "max_rank": st["max_rank"], "converged": bool(st["converged"]),
-            "step": "hss_compress + hss_matvec(nrhs=1) + hss_destroy",
+            "step": "hss_compress + hss_matvec(nrhs=1) + " + ("hss_factor + hss_solve(nrhs=1) + " if ulv else "")
+                    + "hss_destroy",
         },
         "roofline": roofline,
         "cpu_baseline": cpu,
-        "accuracy": {"matvec_rel_err_vs_dense": mv_err, "frob_rel_err": frob, "bound": 10 * cfg["rtol"]},
+        "accuracy": {"matvec_rel_err_vs_dense": mv_err, "frob_rel_err": frob, "bound": 10 * cfg["rtol"],
+                     **({"solve_backward_err": solve_err} if ulv else {})},
         "breakdown_ms": {k: round(float(np.median([s[k] for s in stats])), 2)
-                         for k in ("t_total_ms", "t_sample_ms", "t_sample_gemm_ms", "t_levels_ms", "t_id_ms")},
+                         for k in ("t_total_ms", "t_sample_ms", "t_sample_gemm_ms", "t_levels_ms", "t_id_ms")
+                         + (("t_factor_ms", "t_solve_ms") if ulv else ())},
     }
     print(json.dumps(out), flush=True)
     return 0
