@@ -119,6 +119,7 @@ __global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(4))) void g
   for (int k0 = 0; k0 < g.K; k0 += TK) {
     const int kn = k0 + TK;
     if (kn < g.K) load(kn);  // next slice in flight while this one is multiplied
+    __builtin_amdgcn_s_setprio(1);  // multiplying wavefronts issue first
 #pragma unroll
     for (int kk = 0; kk < TK; kk += 4) {
       const int kr = kk + (lane >> 4);
@@ -133,6 +134,7 @@ __global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(4))) void g
         for (int nb = 0; nb < 2; ++nb)
           acc[mb][nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[mb], b[nb], acc[mb][nb], 0, 0, 0);
     }
+    __builtin_amdgcn_s_setprio(0);
     __syncthreads();
     if (kn < g.K) store();
     __syncthreads();

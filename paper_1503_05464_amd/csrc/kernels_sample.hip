@@ -230,6 +230,10 @@ __global__ __launch_bounds__(NT) void sample_kernel(
       load_a<TA, TRANS>(va, A, lda, n, i0, kn, kend, leaf_of, vec_a, mask_for(kn));
       load_r<BK>(vr, R, ldr, kn, kend, c0, ncols, vec_r);
     }
+    // the wavefronts multiplying take issue priority over those still
+    // loading or storing the next slice (8.99 -> 8.36 ms per launch at
+    // n = 65536, 64 columns)
+    __builtin_amdgcn_s_setprio(1);
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 4) {
       const int kr = kk + (lane >> 4);
@@ -244,6 +248,7 @@ __global__ __launch_bounds__(NT) void sample_kernel(
         for (int nb = 0; nb < 2; ++nb)
           acc[mb][nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[mb], b[nb], acc[mb][nb], 0, 0, 0);
     }
+    __builtin_amdgcn_s_setprio(0);
     __syncthreads();
     if (kn < kend) {
       store_a<TA, TRANS>(As, va);
