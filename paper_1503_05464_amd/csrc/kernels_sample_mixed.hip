@@ -296,7 +296,7 @@ __device__ __forceinline__ void sample_tile(Smem<MODE>& sm, const float* __restr
       }
     } else {
       // multiplying wavefronts issue first (5.72 -> 5.62 ms per launch; the
-      // FP32 mode measured no better with it)
+      // FP32 mode runs slower with it: 6.71 -> 6.87 ms)
       __builtin_amdgcn_s_setprio(1);
 #pragma unroll
       for (int t = 0; t < 3; ++t) {
