@@ -31,51 +31,49 @@ __global__ __launch_bounds__(NT) void vt_leaf_kernel(const VtLeafDesc* __restric
 // columns): lower: X = T^{-1} X with T lower triangular (unit diagonal if
 // unit); upper: likewise with T upper triangular.  One workgroup per problem
 // and block of NT right-hand-side columns (grid y); each thread owns one
-// column.
+// column, all 64 rows of it in registers.  The LDS copy of T is padded to
+// 64 x 64 with the identity, so the padded rows solve to zero and the
+// unrolled loops need no test against nb: with one, the compiler kept the
+// column in scratch memory.
 __global__ __launch_bounds__(NT) void tri_block_kernel(const TriDesc* __restrict__ d) {
   __shared__ double T[64][65];
   const TriDesc g = d[blockIdx.x];
   const int nb = g.nb;
   const int cbeg = blockIdx.y * NT;
   if (cbeg >= g.nrhs) return;
-  for (int e = threadIdx.x; e < nb * nb; e += NT) {
-    const int r = e / nb, c = e % nb;
-    T[r][c] = g.T[(long long)r * g.ldt + c];
+  for (int e = threadIdx.x; e < 64 * 64; e += NT) {  // a unit diagonal is stored as 1: s / 1 = s exactly
+    const int r = e >> 6, c = e & 63;
+    T[r][c] = (r < nb && c < nb && !(g.unit && r == c)) ? g.T[(long long)r * g.ldt + c] : (r == c ? 1.0 : 0.0);
   }
   __syncthreads();
-  {
-    const int col = cbeg + threadIdx.x;
-    if (col >= g.nrhs) return;
-    double x[64];
+  const int col = cbeg + threadIdx.x;
+  if (col >= g.nrhs) return;
+  double x[64];
 #pragma unroll
-    for (int r = 0; r < 64; ++r) x[r] = (r < nb) ? g.X[(long long)r * g.ldx + col] : 0.0;
-    if (g.lower) {
-#pragma unroll
-      for (int r = 0; r < 64; ++r) {
-        if (r < nb) {
-          double s = x[r];
-#pragma unroll
-          for (int c = 0; c < 64; ++c)
-            if (c < r) s = fma(-T[r][c], x[c], s);
-          x[r] = g.unit ? s : s / T[r][r];
-        }
-      }
-    } else {
-#pragma unroll
-      for (int r = 63; r >= 0; --r) {
-        if (r < nb) {
-          double s = x[r];
-#pragma unroll
-          for (int c = 0; c < 64; ++c)
-            if (c > r && c < nb) s = fma(-T[r][c], x[c], s);
-          x[r] = g.unit ? s : s / T[r][r];
-        }
-      }
-    }
-#pragma unroll
-    for (int r = 0; r < 64; ++r)
-      if (r < nb) g.X[(long long)r * g.ldx + col] = x[r];
+  for (int r = 0; r < 64; ++r) {  // rows past nb read row 0 and are zeroed
+    const double v = g.X[(long long)(r < nb ? r : 0) * g.ldx + col];
+    x[r] = r < nb ? v : 0.0;
   }
+  // column by column: once x[c] is final, the updates of the other rows are
+  // independent of each other
+  if (g.lower) {
+#pragma unroll
+    for (int c = 0; c < 64; ++c) {
+      x[c] = x[c] / T[c][c];
+#pragma unroll
+      for (int r = c + 1; r < 64; ++r) x[r] = fma(-T[r][c], x[c], x[r]);
+    }
+  } else {
+#pragma unroll
+    for (int c = 63; c >= 0; --c) {
+      x[c] = x[c] / T[c][c];
+#pragma unroll
+      for (int r = 0; r < c; ++r) x[r] = fma(-T[r][c], x[c], x[r]);
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < 64; ++r)
+    if (r < nb) g.X[(long long)r * g.ldx + col] = x[r];
 }
 
 // Y = [u_0 .. u_{r-1}] (m x r, row-major, ld r) with u_i = (0.., 1, Z[i][i+1..m-1]):
