@@ -873,9 +873,13 @@ __global__ __launch_bounds__(NT) void trsm_diag_kernel(const DiagDesc* __restric
   }
   const DiagDesc g = descs[lo];
   const int nb = g.b1 - g.b0;
-  for (int e = threadIdx.x; e < nb * nb; e += NT) {
-    const int bb = e / nb, aa = e % nb;
-    Rt[bb][aa] = (aa <= bb) ? g.W[(long long)g.perm[g.b0 + bb] * g.ldw + g.b0 + aa] : 0.0;
+  // padded to 64 x 64 with the identity: the padded entries solve to zero
+  // and the unrolled loops below need no test against nb
+  for (int e = threadIdx.x; e < 64 * 64; e += NT) {
+    const int bb = e >> 6, aa = e & 63;
+    Rt[bb][aa] = (bb < nb && aa <= bb)
+                     ? g.W[(long long)g.perm[g.b0 + bb] * g.ldw + g.b0 + aa]
+                     : (aa == bb ? 1.0 : 0.0);
   }
   __syncthreads();
   const int c = (int)(blockIdx.x - g.wg0) * NT + threadIdx.x;
@@ -883,16 +887,17 @@ __global__ __launch_bounds__(NT) void trsm_diag_kernel(const DiagDesc* __restric
   double* x = g.E + (long long)c * g.k + g.b0;
   double xv[64];
 #pragma unroll
-  for (int a = 0; a < 64; ++a) xv[a] = (a < nb) ? x[a] : 0.0;
+  for (int a = 0; a < 64; ++a) {  // entries past nb read entry 0 and are zeroed
+    const double v = x[a < nb ? a : 0];
+    xv[a] = a < nb ? v : 0.0;
+  }
+  // column by column, from the last: once x[b] is final, the updates of the
+  // entries above it are independent of each other
 #pragma unroll
-  for (int a = 63; a >= 0; --a) {
-    if (a < nb) {
-      double s = xv[a];
+  for (int b = 63; b >= 0; --b) {
+    xv[b] = xv[b] / Rt[b][b];
 #pragma unroll
-      for (int b = a + 1; b < 64; ++b)
-        if (b < nb) s = fma(-xv[b], Rt[b][a], s);
-      xv[a] = s / Rt[a][a];
-    }
+    for (int a = 0; a < b; ++a) xv[a] = fma(-xv[b], Rt[b][a], xv[a]);
   }
 #pragma unroll
   for (int a = 0; a < 64; ++a)
