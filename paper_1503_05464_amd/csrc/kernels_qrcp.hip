@@ -128,12 +128,6 @@ void carve(const IdProblem* probs, int nprob, void* base, Work& w, long long& tm
   w.W = reinterpret_cast<double*>(take(tw * 8));
 }
 
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
-
 // wavefront sums of N values at once: butterfly over lanes, the first four
 // levels by DPP (quad permutes, then half-row and row mirrors), the last two
 // by cross-row shuffles.  Every lane ends with the same sums.
@@ -157,6 +151,14 @@ __device__ __forceinline__ void wave_sum_n(double (&v)[N]) {
   for (int c = 0; c < N; ++c) v[c] += __shfl_xor(v[c], 16, 64);
 #pragma unroll
   for (int c = 0; c < N; ++c) v[c] += __shfl_xor(v[c], 32, 64);
+}
+
+// wavefront sum of one value, by the same butterfly (four DPP levels, two
+// cross-row shuffles); every lane ends with the sum
+__device__ __forceinline__ double wave_sum(double v) {
+  double a[1] = {v};
+  wave_sum_n<1>(a);
+  return a[0];
 }
 
 __device__ __forceinline__ void better(double& bv, int& bi, double ov, int oi) {
