@@ -168,6 +168,21 @@ __device__ __forceinline__ void better(double& bv, int& bi, double ov, int oi) {
   }
 }
 
+// wavefront argmax of (value, index) under `better`, by the same butterfly
+// as wave_sum_n: the order is total, so every lane ends with the same pair
+template <int CTRL>
+__device__ __forceinline__ int dpp_i(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
+}
+__device__ __forceinline__ void wave_argmax(double& bv, int& bi) {
+  better(bv, bi, dpp_d<0xB1>(bv), dpp_i<0xB1>(bi));
+  better(bv, bi, dpp_d<0x4E>(bv), dpp_i<0x4E>(bi));
+  better(bv, bi, dpp_d<0x141>(bv), dpp_i<0x141>(bi));
+  better(bv, bi, dpp_d<0x140>(bv), dpp_i<0x140>(bi));
+  better(bv, bi, __shfl_xor(bv, 16, 64), __shfl_xor(bi, 16, 64));
+  better(bv, bi, __shfl_xor(bv, 32, 64), __shfl_xor(bi, 32, 64));
+}
+
 // ---------------------------------------------------------------------------
 // small problems: one workgroup, matrix in registers
 // ---------------------------------------------------------------------------
@@ -216,8 +231,7 @@ __global__ __launch_bounds__(RW * 64) void qrcp_reg_kernel(const DevProb* __rest
     int bi = INT_MAX;
     for (int j = tid; j < m; j += RW * 64)
       if (step_s[j] < 0) better(bv, bi, nrm_s[j], j);
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) better(bv, bi, __shfl_xor(bv, o, 64), __shfl_xor(bi, o, 64));
+    wave_argmax(bv, bi);
     if (lane == 0) {
       red_v[wave] = bv;
       red_i[wave] = bi;
@@ -415,8 +429,7 @@ __global__ __launch_bounds__(ST) void id_step_kernel(const DevProb* __restrict__
     double bv = -1.0;
     int bi = INT_MAX;
     for (int t = tid; t < dp.G; t += ST) better(bv, bi, cv[t], ci[t]);
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) better(bv, bi, __shfl_xor(bv, o, 64), __shfl_xor(bi, o, 64));
+    wave_argmax(bv, bi);
     if (lane == 0) {
       rv[wave] = bv;
       ri[wave] = bi;
@@ -681,8 +694,7 @@ __global__ __launch_bounds__(PT) void qrcp_persist_kernel(const DevProb* __restr
       if (ok) better(gv, gi, __longlong_as_double((long long)(a ^ kSignBit)), (int)(unsigned)b);
     }
     if (!ok) s_ok = 0;
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) better(gv, gi, __shfl_xor(gv, o, 64), __shfl_xor(gi, o, 64));
+    wave_argmax(gv, gi);
     // rv / ri: every thread read them in publish before its closing barrier
     if (lane == 0) {
       rv[wave] = gv;
