@@ -15,6 +15,33 @@ namespace {
 
 constexpr int NT = 256;
 
+// Wavefront argmax of (|value|, row) for the pivot search: the larger value,
+// the lower row on ties.  Butterfly of four DPP levels (quad permutes, then
+// half-row and row mirrors) and two cross-row shuffles; the order is total,
+// so every lane ends with the same pair.
+template <int CTRL>
+__device__ __forceinline__ int piv_dpp(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
+}
+template <int CTRL>
+__device__ __forceinline__ double piv_dpp_d(double v) {
+  return __hiloint2double(piv_dpp<CTRL>(__double2hiint(v)), piv_dpp<CTRL>(__double2loint(v)));
+}
+__device__ __forceinline__ void piv_better(double& bv, int& bi, double ov, int oi) {
+  if (ov > bv || (ov == bv && oi < bi)) {
+    bv = ov;
+    bi = oi;
+  }
+}
+__device__ __forceinline__ void pivot_argmax(double& bv, int& bi) {
+  piv_better(bv, bi, piv_dpp_d<0xB1>(bv), piv_dpp<0xB1>(bi));
+  piv_better(bv, bi, piv_dpp_d<0x4E>(bv), piv_dpp<0x4E>(bi));
+  piv_better(bv, bi, piv_dpp_d<0x141>(bv), piv_dpp<0x141>(bi));
+  piv_better(bv, bi, piv_dpp_d<0x140>(bv), piv_dpp<0x140>(bi));
+  piv_better(bv, bi, __shfl_xor(bv, 16, 64), __shfl_xor(bi, 16, 64));
+  piv_better(bv, bi, __shfl_xor(bv, 32, 64), __shfl_xor(bi, 32, 64));
+}
+
 // V^T of a leaf as rows of Z: Z[a][J[a]] = 1, Z[a][rest[j]] = E[j][a].
 __global__ __launch_bounds__(NT) void vt_leaf_kernel(const VtLeafDesc* __restrict__ d) {
   const VtLeafDesc g = d[blockIdx.y];
@@ -147,15 +174,7 @@ __global__ __launch_bounds__(1024) void lu_panel_kernel(double* __restrict__ A, 
         bi = r;
       }
     }
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-      const double ov = __shfl_xor(bv, o, 64);
-      const int oi = __shfl_xor(bi, o, 64);
-      if (ov > bv || (ov == bv && oi < bi)) {
-        bv = ov;
-        bi = oi;
-      }
-    }
+    pivot_argmax(bv, bi);
     if (lane == 0) {
       rv[wave] = bv;
       ri[wave] = bi;
@@ -241,15 +260,7 @@ __global__ __launch_bounds__(1024) void lu_panel_reg_kernel(double* __restrict__
           bi = r;
         }
       }
-#pragma unroll
-      for (int o = 32; o > 0; o >>= 1) {
-        const double ov = __shfl_xor(bv, o, 64);
-        const int oi = __shfl_xor(bi, o, 64);
-        if (ov > bv || (ov == bv && oi < bi)) {
-          bv = ov;
-          bi = oi;
-        }
-      }
+      pivot_argmax(bv, bi);
       if (lane == 0) {
         rv[wave] = bv;
         ri[wave] = bi;
