@@ -578,8 +578,11 @@ def main() -> int:
         print("[bench] cpu baseline (oracle, bounded sample)", file=sys.stderr, flush=True)
         cpu = cpu_baseline(cfg, pts, st["d_final"], args.cpu_panel)
 
+    headline = "HSS compress s at N=65536 rtol1e-6 + % GEMM roofline; p50/p99 req latency"
     out = {
-        "metric": "HSS compress s at N=65536 rtol1e-6 + % GEMM roofline; p50/p99 req latency",
+        "metric": headline if args.workload == "gauss65536" else
+        f"HSS {'compress + ULV factor/solve' if ulv else 'compress'} s per step at N={cfg['n']} "
+        f"rtol{cfg['rtol']:g}",
         "value": round(ms / 1e3, 4),
         "unit": "s",
         "n_gpus": 1,
