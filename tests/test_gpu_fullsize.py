@@ -138,7 +138,7 @@ def test_compress_circle16384_acceptance():
     assert _frob(h, A) <= 10 * cfg["rtol"]
 
 
-@pytest.mark.parametrize("pm", [10, 256])
+@pytest.mark.parametrize("pm", [10, 200, 256])
 def test_gauss4096_against_stored_oracle(pm):
     path = os.path.join(GOLDEN, f"oracle_gauss4096_rtol1e-06_pm{pm}.json")
     if not os.path.exists(path):
