@@ -232,28 +232,8 @@ def run_batched(args) -> int:
     torch.cuda.synchronize()
     ms = (time.perf_counter() - t0) * 1e3 / max(1, args.steps)
     sts = [s[0] for s in stats]
-    flops = sum(s["sample_gemm_flops"] for s in sts)
-    nbytes = sum(s["sample_gemm_bytes"] for s in sts)
-    t_gemm = sum(s["t_sample_gemm_ms"] for s in sts) / 1e3
-    launches = sum(s["n_sample_launches"] for s in sts)
-    terms, peak = (3, BF16_MFMA_PEAK_TFLOPS) if prec == "bf16x3" else \
-        ((1, FP32_MFMA_PEAK_TFLOPS) if prec == "f32" else (1, FP64_MFMA_PEAK_TFLOPS))
-    issued = terms * flops / t_gemm / 1e12
-    gbs = nbytes / t_gemm / 1e9
-    hbm_bound = nbytes / (HBM_PEAK_GBS * 1e9) > terms * flops / (peak * 1e12)
-    roofline = {
-        "bound": "hbm" if hbm_bound else "mfma",
-        "achieved": round(gbs, 1) if hbm_bound else round(issued, 2),
-        "peak": HBM_PEAK_GBS if hbm_bound else peak,
-        "unit": "GB/s" if hbm_bound else "TFLOP/s",
-        "frac": round(gbs / HBM_PEAK_GBS if hbm_bound else issued / peak, 4),
-        "traffic": None,
-        "kernel": f"sampling products ({prec}) over all matrices",
-        "avg_launch_ms": round(t_gemm * 1e3 / max(1, launches), 4),
-        "launches": launches,
-        "algorithmic_tflops": round(flops / t_gemm / 1e12, 2),
-        "achieved_gbs": round(gbs, 1),
-    }
+    roofline = sampling_roofline(sts, prec)
+    roofline["kernel"] = f"sampling products ({prec}) over all matrices"
     # acceptance: every matrix's matvec against its dense product
     hs = P.hss_compress_batched(As, **kw)
     worst = 0.0
@@ -311,6 +291,7 @@ def run_batched(args) -> int:
         },
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "level_roofline": level_roofline(sts),
         "accuracy": {"worst_matvec_rel_err_vs_dense": worst, "bound": 10 * cfg["rtol"]},
         "breakdown_ms": {k: round(float(np.median([s[k] for s in sts])), 2)
                          for k in ("t_total_ms", "t_sample_ms", "t_sample_gemm_ms", "t_levels_ms", "t_id_ms")},
@@ -319,29 +300,31 @@ def run_batched(args) -> int:
     return 0
 
 
-def run_serve(args) -> int:
+def serve_measure(nreq: int, rate: float, workers: int, budget_frac: float = 0.8) -> dict:
     """The serving workload: requests of compress + ULV factor + solve arrive
-    as a Poisson process at --serve-rate per second (default 200, seed 6).  Each request draws its
-    matrix from a pool of 16 pre-assembled matrices -- N log-uniform in
+    as a Poisson process at `rate` per second (seed 6).  Each request draws
+    its matrix from a pool of 16 pre-assembled matrices -- N log-uniform in
     [512, 32768], the 2-D log kernel on a perturbed circle or the 3-D
     Gaussian kernel (k-d ordered) with probability 1/2 each, FP32 storage --
     and draws rtol in {1e-4, 1e-6} and nrhs in {1..64}; sampling is BF16x3.
-    The first 10 % of the requests are warm-up.  Reports p50/p99 latency from
-    submission to solution and the throughput; `value` is the p50 latency."""
+    The first 10 % of the requests are warm-up.  Returns p50/p90/p99
+    latency from submission to solution, the throughput, and checks of the
+    SERVED solutions: on the last request of each pool matrix, the backward
+    error ||A x - b|| / (||A||_2 ||x||) against the dense A, and the
+    distance to the same request solved alone."""
     import numpy as np
     import torch
 
     import paper_1503_05464_amd as P
     import workloads as W
 
-    nreq = args.serve_requests
     g = np.random.default_rng(6)
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     pool = []
     sizes = np.floor(np.exp(g.uniform(np.log(512), np.log(32768), size=16))).astype(int)
     kinds = g.integers(0, 2, size=16)
-    print(f"[bench] workload serve: assembling a pool of 16 matrices, N = {sorted(sizes.tolist())}",
+    print(f"[bench] serve: assembling a pool of 16 matrices, N = {sorted(sizes.tolist())}",
           file=sys.stderr, flush=True)
     for q, (n, k) in enumerate(zip(sizes, kinds)):
         if k == 0:
@@ -353,15 +336,14 @@ def run_serve(args) -> int:
     pick = g.integers(0, 16, size=nreq)
     rtols = g.choice([1e-4, 1e-6], size=nreq)
     nrhs = g.integers(1, 65, size=nreq)
-    rate = float(args.serve_rate)
     gaps = g.exponential(1.0 / rate, size=nreq)
     rhs = [torch.from_numpy(W.normal_rhs(int(pool[q].shape[0]), int(k), 6000 + i)).to(dev)
            for i, (q, k) in enumerate(zip(pick, nrhs))]
     torch.cuda.synchronize()
-    # admission budget: half of the device memory (the request matrices of
-    # the pool live outside it)
-    budget = int(0.5 * torch.cuda.mem_get_info()[1])
-    srv = P.HSSServer(hbm_budget=budget, max_batch=32, workers=args.serve_workers)
+    # admission budget: a fraction of the device memory; every request's
+    # footprint counts its A, b and x as well as the library's buffers
+    budget = int(budget_frac * torch.cuda.mem_get_info()[1])
+    srv = P.HSSServer(hbm_budget=budget, max_batch=32, workers=workers)
     kw0 = dict(d0=64, dd=32, d_max=1024, leaf_size=128, p_margin=32, sample_prec="bf16x3")
     print(f"[bench] serving {nreq} requests at {rate:g}/s", file=sys.stderr, flush=True)
     t_start = time.perf_counter()
@@ -373,12 +355,13 @@ def run_serve(args) -> int:
             time.sleep(max(0.0, min(0.001, t_next - time.perf_counter())))
         tickets.append(srv.submit(pool[pick[i]], rhs[i], rtol=float(rtols[i]), **kw0))
     t_submitted = time.perf_counter()
-    infos = []
+    infos, xs = [], []
     for i, t in enumerate(tickets):
-        infos.append(srv.wait(t)[1])
+        x, info = srv.wait(t)
+        infos.append(info)
+        xs.append(x)
         if (i + 1) % max(1, nreq // 10) == 0:
             print(f"[bench] {i + 1} of {nreq} requests done", file=sys.stderr, flush=True)
-    t_end = time.perf_counter()
     srv.close()
     warm = nreq // 10
     lat = np.array([x["t_done"] - x["t_submit"] for x in infos[warm:]])
@@ -386,54 +369,220 @@ def run_serve(args) -> int:
     t_first = min(x["t_submit"] for x in infos[warm:])
     t_last = max(x["t_done"] for x in infos[warm:])
     thr = (nreq - warm) / max(1e-9, t_last - t_first)
-    # correctness spot check: backward error ||A x - b|| / (||A|| ||x||) of the
-    # last request on each of four pool matrices, solved again alone
-    worst = 0.0
-    for q in sorted(set(pick.tolist()))[:4]:
+    # the served solutions themselves: the last request on each pool matrix
+    worst_bwd, worst_rel_bound, worst_alone = 0.0, 0.0, 0.0
+    checked = 0
+    for q in sorted(set(pick.tolist())):
         i = int(np.flatnonzero(pick == q)[-1])
         A = pool[q].double()
-        h = P.hss_compress(pool[q], rtol=float(rtols[i]), **kw0)
-        P.hss_factor(h)
-        x = P.hss_solve(h, rhs[i])
+        x = xs[i]
         r = A @ x - rhs[i]
         v = torch.ones((A.shape[0], 1), dtype=torch.float64, device=dev)
         for _ in range(20):  # ||A||_2 by power iteration
             v = A @ v
             v = v / torch.linalg.norm(v)
         anorm = float(torch.linalg.norm(A @ v))
-        worst = max(worst, float(torch.linalg.norm(r)) / (anorm * float(torch.linalg.norm(x))))
+        bwd = float(torch.linalg.norm(r)) / (anorm * float(torch.linalg.norm(x)))
+        worst_bwd = max(worst_bwd, bwd)
+        worst_rel_bound = max(worst_rel_bound, bwd / (10 * float(rtols[i])))
+        h = P.hss_compress(pool[q], rtol=float(rtols[i]), **kw0)
+        P.hss_factor(h)
+        xa = P.hss_solve(h, rhs[i])
+        worst_alone = max(worst_alone, float(torch.linalg.norm(x - xa) / torch.linalg.norm(xa)))
+        P.hss_destroy(h)
+        checked += 1
         del A
-    out = {
-        "metric": "HSS serving latency s (compress + ULV factor + solve per request), p50; p99 alongside",
-        "value": round(float(np.percentile(lat, 50)), 4),
-        "unit": "s",
-        "n_gpus": 1,
-        "steps": nreq - warm,
+    return {
+        "rate_req_s": rate,
+        "requests": nreq,
         "warmup": warm,
-        "ms_per_step": round(1e3 / thr, 2),
-        "higher_is_better": False,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "bf16x3 sampling, f64 ID and ULV",
-        "data": "synthetic",
-        "config": {
-            "workload": f"serve: Poisson arrivals at {rate:g}/s (seed 6), pool of 16 FP32 matrices N log-uniform "
-                        "in [512, 32768] (log kernel on a circle or Gaussian kernel in 3-D), rtol in "
-                        "{1e-4, 1e-6}, nrhs in {1..64}, leaf 128, d0 64, dd 32, p_margin 32, BF16X3 sampling",
-            "requests": nreq, "workers": args.serve_workers, "max_batch": 32, "hbm_budget": "50% of device memory",
-        },
+        "workers": workers,
+        "hbm_budget_frac": budget_frac,
         "latency_s": {"p50": round(float(np.percentile(lat, 50)), 4), "p90": round(float(np.percentile(lat, 90)), 4),
                       "p99": round(float(np.percentile(lat, 99)), 4), "max": round(float(lat.max()), 4)},
         "throughput_req_s": round(thr, 2),
         "offered_req_s": round(nreq / (t_submitted - t_start), 2),
         "mean_batch": round(float(np.mean([x["batch_size"] for x in infos])), 2),
         "failed": bad,
-        "spot_check_backward_error": worst,
+        "served_checked": checked,
+        "served_backward_error_max": worst_bwd,
+        "served_backward_error_over_10rtol_max": round(worst_rel_bound, 4),
+        "served_vs_alone_rel_max": worst_alone,
+    }
+
+
+def run_serve(args) -> int:
+    """The serving workload on its own (see serve_measure); `value` is the
+    p50 latency."""
+    res = serve_measure(args.serve_requests, float(args.serve_rate), args.serve_workers)
+    out = {
+        "metric": "HSS serving latency s (compress + ULV factor + solve per request), p50; p99 alongside",
+        "value": res["latency_s"]["p50"],
+        "unit": "s",
+        "n_gpus": 1,
+        "steps": res["requests"] - res["warmup"],
+        "warmup": res["warmup"],
+        "ms_per_step": round(1e3 / res["throughput_req_s"], 2),
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16x3 sampling, f64 ID and ULV",
+        "data": "synthetic",
+        "config": {
+            "workload": f"serve: Poisson arrivals at {res['rate_req_s']:g}/s (seed 6), pool of 16 FP32 matrices "
+                        "N log-uniform in [512, 32768] (log kernel on a circle or Gaussian kernel in 3-D), rtol in "
+                        "{1e-4, 1e-6}, nrhs in {1..64}, leaf 128, d0 64, dd 32, p_margin 32, BF16X3 sampling",
+            "requests": res["requests"], "workers": res["workers"], "max_batch": 32,
+            "hbm_budget": f"{int(100 * res['hbm_budget_frac'])}% of device memory",
+        },
+        **{k: res[k] for k in ("latency_s", "throughput_req_s", "offered_req_s", "mean_batch", "failed",
+                               "served_checked", "served_backward_error_max",
+                               "served_backward_error_over_10rtol_max", "served_vs_alone_rel_max")},
         "roofline": None,
         "cpu_baseline": None,
     }
     print(json.dumps(out), flush=True)
     return 0
+
+
+def sampling_roofline(stats, prec: str) -> dict:
+    """Roofline of the sampling products over the timed steps: algorithmic
+    flops (2 n^2 per random column and side) and bytes (A once per product,
+    R read, S written) over the launches' summed duration (HIP events on the
+    stream they run on), against the peak of the precision's own unit."""
+    flops = sum(s["sample_gemm_flops"] for s in stats)
+    nbytes = sum(s["sample_gemm_bytes"] for s in stats)
+    t_gemm = sum(s["t_sample_gemm_ms"] for s in stats) / 1e3
+    launches = sum(s["n_sample_launches"] for s in stats)
+    terms, peak, kname = {"f64": (1, FP64_MFMA_PEAK_TFLOPS, "sample_kernel (FP64 MFMA 16x16x4)"),
+                          "f32": (1, FP32_MFMA_PEAK_TFLOPS, "sample_mixed_kernel (FP32 MFMA 16x16x4)"),
+                          "bf16x3": (3, BF16_MFMA_PEAK_TFLOPS,
+                                     "sample_mixed_kernel (3 BF16 terms, BF16 MFMA 16x16x32)")}[prec]
+    issued = terms * flops / t_gemm / 1e12 if t_gemm > 0 else 0.0
+    gbs = nbytes / t_gemm / 1e9 if t_gemm > 0 else 0.0
+    hbm_bound = nbytes / (HBM_PEAK_GBS * 1e9) > terms * flops / (peak * 1e12)
+    return {
+        "bound": "hbm" if hbm_bound else "mfma",
+        "achieved": round(gbs, 1) if hbm_bound else round(issued, 2),
+        "peak": HBM_PEAK_GBS if hbm_bound else peak,
+        "unit": "GB/s" if hbm_bound else "TFLOP/s",
+        "frac": round(gbs / HBM_PEAK_GBS if hbm_bound else issued / peak, 4),
+        "traffic": None,
+        "kernel": kname,
+        "avg_launch_ms": round(t_gemm * 1e3 / max(1, launches), 4),
+        "launches": launches,
+        "algorithmic_tflops": round(flops / t_gemm / 1e12, 2) if t_gemm > 0 else 0.0,
+        "achieved_gbs": round(gbs, 1),
+    }
+
+
+def level_roofline(stats) -> dict:
+    """The level kernels of the timed steps against their bounds: the pivoted
+    QRs (IDs) by their flops, 4 d m k per attempt and side with k the steps
+    taken, over the ID phase's time (HIP events) against the FP64 peak; the
+    local-sample and R_tau products and the D / B gathers by their
+    algorithmic bytes over their launches' time against HBM."""
+    t_id = sum(s["t_id_ms"] for s in stats) / 1e3
+    idf = sum(s["id_flops"] for s in stats)
+    t_g = sum(s["t_level_gemm_ms"] for s in stats) / 1e3
+    gb = sum(s["level_gemm_bytes"] for s in stats)
+    t_ga = sum(s["t_gather_ms"] for s in stats) / 1e3
+    gab = sum(s["gather_bytes"] for s in stats)
+    k = max(1, len(stats))
+
+    def ent(bound, achieved, peak, unit, t, work):
+        return {"bound": bound, "achieved": round(achieved, 2), "peak": peak, "unit": unit,
+                "frac": round(achieved / peak, 4), "ms_per_step": round(1e3 * t / k, 2), "work_per_step": work}
+
+    return {
+        "id": ent("fp64", idf / t_id / 1e12 if t_id > 0 else 0.0, FP64_MFMA_PEAK_TFLOPS, "TFLOP/s", t_id,
+                  f"{idf / k:.4g} flop (4 d m k per ID attempt and side)"),
+        "level_gemm": ent("hbm", gb / t_g / 1e9 if t_g > 0 else 0.0, HBM_PEAK_GBS, "GB/s", t_g,
+                          f"{gb / k:.4g} B (operands once, C when read)"),
+        "gather": ent("hbm", gab / t_ga / 1e9 if t_ga > 0 else 0.0, HBM_PEAK_GBS, "GB/s", t_ga,
+                      f"{gab / k:.4g} B (entries of A read, FP64 written)"),
+    }
+
+
+def profile_kernels(args) -> int:
+    """Single launches at the benchmark's sizes for hardware-counter profiles
+    (rocprofv3 --pmc): an elementwise copy of 4 GiB (torch multiply by one,
+    two launches of 2 GiB read + 2 GiB written) that calibrates the byte
+    counters, then hss_sample on the N = 65536 FP32 Gaussian-kernel matrix
+    (k-d ordered points, leaf 256, leaf blocks masked) with 64 FP64 random
+    columns in the precision --sample-prec: the products of one growth step
+    of the compression."""
+    import numpy as np
+    import torch
+
+    import paper_1503_05464_amd as P
+
+    cfg = dict(WORKLOADS["gauss65536"])
+    dev = torch.device("cuda:0")
+    print("[profile] copy of 4 GiB", file=sys.stderr, flush=True)
+    src = torch.ones(1 << 29, dtype=torch.float64, device=dev)
+    dst = torch.empty_like(src)
+    torch.mul(src, 1.0, out=dst)
+    torch.cuda.synchronize()
+    del src, dst
+    torch.cuda.empty_cache()
+    n, leaf, ncols = cfg["n"], cfg["leaf"], 64
+    A = make_matrix(cfg, make_points(cfg), dev)
+    leaf_of = torch.from_numpy((np.arange(n) // leaf).astype(np.int32)).to(dev)
+    Rr = P.hss_random_normal(0, 0, n, 0, ncols, sample_prec=args.sample_prec)
+    Rc = P.hss_random_normal(0, 1, n, 0, ncols, sample_prec=args.sample_prec)
+    torch.cuda.synchronize()
+    print(f"[profile] hss_sample n={n} ncols={ncols} {args.sample_prec} (both products)", file=sys.stderr,
+          flush=True)
+    P.hss_sample(A, Rr, Rc, leaf_of, sample_prec=args.sample_prec)
+    torch.cuda.synchronize()
+    print("[profile] done", file=sys.stderr, flush=True)
+    return 0
+
+
+def precision_sweep(P, A, kw, prec: str, steps: int) -> dict:
+    """The headline matrix with the sampling products in a reduced precision
+    (same rtol and options otherwise): seconds per step (compress + matvec
+    + destroy), its sampling kernel's roofline against its own unit's peak,
+    and the accuracy against the dense A."""
+    import numpy as np
+    import torch
+
+    kwp = dict(kw, sample_prec=prec)
+    n = A.shape[0]
+    x = torch.from_numpy(np.random.default_rng(1).uniform(-1, 1, (n, 1))).to(A.device)
+    b = torch.empty_like(x)
+
+    def step():
+        h = P.hss_compress(A, **kwp)
+        P.hss_matvec(h, x, b)
+        st = dict(P.hss_stats(h))
+        P.hss_destroy(h)
+        return st
+
+    st = step()  # warm-up
+    torch.cuda.synchronize()
+    stats = []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        stats.append(step())
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / max(1, steps)
+    print(f"[bench] {prec} sampling: {ms:.1f} ms per step", file=sys.stderr, flush=True)
+    h = P.hss_compress(A, **kwp)
+    st = P.hss_stats(h)
+    xs = torch.from_numpy(np.random.default_rng(3).uniform(-1, 1, (n, 2))).to(A.device)
+    bd = dense_matvec(A, xs)
+    mv_err = float(torch.linalg.norm(P.hss_matvec(h, xs) - bd) / torch.linalg.norm(bd))
+    P.hss_destroy(h)
+    return {
+        "s_per_step": round(ms / 1e3, 4), "steps": steps, "d_final": st["d_final"], "passes": st["passes"],
+        "max_rank": st["max_rank"], "converged": bool(st["converged"]),
+        "roofline": sampling_roofline(stats, prec),
+        "matvec_rel_err_vs_dense": mv_err, "bound": 10 * kw["rtol"],
+        "breakdown_ms": {k: round(float(np.median([s[k] for s in stats])), 2)
+                         for k in ("t_total_ms", "t_sample_ms", "t_sample_gemm_ms", "t_levels_ms", "t_id_ms")},
+    }
 
 
 def main() -> int:
@@ -452,12 +601,18 @@ def main() -> int:
     ap.add_argument("--no-frob", action="store_true", help="skip the exact ||A - A_HSS||_F check")
     ap.add_argument("--sample-prec", default="f64", choices=["f64", "f32", "bf16x3"],
                     help="precision of the sampling products (reduced modes need the FP32 A)")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="headline workload: skip the reduced-precision and serving lines")
+    ap.add_argument("--profile-kernels", action="store_true",
+                    help="run one sampling step alone after a calibration copy (for rocprofv3 --pmc)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the compression path has no multi-GPU mode; "
               "whole matrices (batches, served requests) would shard one per GPU",
               file=sys.stderr)
         return 2
+    if args.profile_kernels:
+        return profile_kernels(args)
     if args.workload == "batched512":
         return run_batched(args)
     if args.workload == "serve":
@@ -493,11 +648,12 @@ def main() -> int:
         h = P.hss_compress(A, **kw)
         P.hss_matvec(h, x, b)
         st = dict(P.hss_stats(h))
-        if ulv:  # factor and solve return once their results are written
+        if ulv:  # factor returns once the factors are written; solve is stream-ordered
             t1 = time.perf_counter()
             P.hss_factor(h)
             t2 = time.perf_counter()
             P.hss_solve(h, rhs)
+            torch.cuda.synchronize()
             t3 = time.perf_counter()
             st["t_factor_ms"] = (t2 - t1) * 1e3
             st["t_solve_ms"] = (t3 - t2) * 1e3
@@ -522,31 +678,10 @@ def main() -> int:
               f"levels {st['t_levels_ms']:.1f} id {st['t_id_ms']:.1f} ms", file=sys.stderr, flush=True)
 
     # dominant kernel: the sampling GEMM, measured with HIP events on its stream
-    flops = sum(s["sample_gemm_flops"] for s in stats)      # algorithmic: 2 n^2 per column and side
-    nbytes = sum(s["sample_gemm_bytes"] for s in stats)     # A once per product, R read, S written
-    t_gemm = sum(s["t_sample_gemm_ms"] for s in stats) / 1e3
-    launches = sum(s["n_sample_launches"] for s in stats)
-    terms, peak, kname = {"f64": (1, FP64_MFMA_PEAK_TFLOPS, "sample_kernel (FP64 MFMA 16x16x4)"),
-                          "f32": (1, FP32_MFMA_PEAK_TFLOPS, "sample_mixed_kernel (FP32 MFMA 16x16x4)"),
-                          "bf16x3": (3, BF16_MFMA_PEAK_TFLOPS,
-                                     "sample_mixed_kernel (3 BF16 terms, BF16 MFMA 16x16x32)")}[args.sample_prec]
-    issued = terms * flops / t_gemm / 1e12 if t_gemm > 0 else 0.0
-    gbs = nbytes / t_gemm / 1e9 if t_gemm > 0 else 0.0
-    hbm_bound = nbytes / (HBM_PEAK_GBS * 1e9) > terms * flops / (peak * 1e12)
-    roofline = {
-        "bound": "hbm" if hbm_bound else "mfma",
-        "achieved": round(gbs, 1) if hbm_bound else round(issued, 2),
-        "peak": HBM_PEAK_GBS if hbm_bound else peak,
-        "unit": "GB/s" if hbm_bound else "TFLOP/s",
-        "frac": round(gbs / HBM_PEAK_GBS if hbm_bound else issued / peak, 4),
-        "traffic": (measured_traffic("kernels_sample.hip", "pmc_sample_kernel_gauss65536.txt")
-                    if args.sample_prec == "f64" and args.workload == "gauss65536" else None),
-        "kernel": kname,
-        "avg_launch_ms": round(t_gemm * 1e3 / max(1, launches), 4),
-        "launches": launches,
-        "algorithmic_tflops": round(flops / t_gemm / 1e12, 2) if t_gemm > 0 else 0.0,
-        "achieved_gbs": round(gbs, 1),
-    }
+    roofline = sampling_roofline(stats, args.sample_prec)
+    if args.sample_prec == "f64" and args.workload == "gauss65536":
+        roofline["traffic"] = measured_traffic("kernels_sample.hip", "pmc_sample_kernel_gauss65536.txt")
+    levels = level_roofline(stats)
 
     # acceptance on a fresh compression (not timed)
     h = P.hss_compress(A, **kw)
@@ -570,8 +705,16 @@ def main() -> int:
     if not args.no_frob:
         frob = frob_error(P, h, A)
     P.hss_destroy(h)
+    extras = {}
+    if args.workload == "gauss65536" and args.sample_prec == "f64" and not args.no_extras:
+        # the precision sweep on the same matrix and rtol, then a bounded
+        # serving run above and one below the device's capacity
+        extras["precision_sweep"] = {p: precision_sweep(P, A, kw, p, 2) for p in ("bf16x3", "f32")}
     del A
     torch.cuda.empty_cache()
+    if extras:
+        extras["serve"] = {"offered_200_per_s": serve_measure(300, 200.0, args.serve_workers),
+                           "offered_4_per_s": serve_measure(60, 4.0, args.serve_workers)}
 
     cpu = None
     if not args.no_cpu_baseline and pts is not None:
@@ -606,8 +749,10 @@ def main() -> int:
         },
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "level_roofline": levels,
         "accuracy": {"matvec_rel_err_vs_dense": mv_err, "frob_rel_err": frob, "bound": 10 * cfg["rtol"],
                      **({"solve_backward_err": solve_err} if ulv else {})},
+        **extras,
         "breakdown_ms": {k: round(float(np.median([s[k] for s in stats])), 2)
                          for k in ("t_total_ms", "t_sample_ms", "t_sample_gemm_ms", "t_levels_ms", "t_id_ms")
                          + (("t_factor_ms", "t_solve_ms") if ulv else ())},

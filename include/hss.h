@@ -125,7 +125,8 @@ typedef struct {
  * issued on `stream`.  The random matrices, samples and other buffers of the
  * compression (about 4 n d_max doubles and more) are released before the
  * call returns, to the library's cache of device blocks (see
- * hss_release_cached_memory); the handle keeps only the generators.
+ * hss_release_cached_memory) or to the allocator set by hss_set_allocator;
+ * the handle keeps only the generators.
  */
 hss_status hss_compress(const void* A, int dtype, long long n, long long lda,
                         const hss_tree* tree, const hss_opts* opts, void* stream,
@@ -160,10 +161,11 @@ hss_status hss_compress_batched(int nmat, const void* const* A, int dtype, const
 
 /*
  * b = A_HSS x (Alg. 2) for nrhs columns.  x: DEVICE n x nrhs (ldx >= nrhs),
- * b: DEVICE n x nrhs (ldb >= nrhs), must not overlap x.  Host-synchronous:
- * all device work goes to `stream`, and the call returns once b is written
- * (its launch descriptors are staged in pinned memory that the next call on
- * the handle reuses).
+ * b: DEVICE n x nrhs (ldb >= nrhs), must not overlap x.  Stream-ordered: all
+ * device work is queued on `stream` and the call may return before it has
+ * run; b is written once that work completes (synchronise `stream`, or order
+ * later work after it).  x must stay unchanged until then.  A later call on
+ * the handle may use another stream: it is ordered after this one.
  */
 hss_status hss_matvec(hss_handle h, int nrhs, const double* x, long long ldx,
                       double* b, long long ldb, void* stream);
@@ -180,7 +182,7 @@ hss_status hss_matvec(hss_handle h, int nrhs, const double* x, long long ldx,
  *  h, x, b, ldx, ldb are host arrays of nmat entries.
  * Uses h[0]'s workspace: not concurrently with another call on h[0].
  * Returns HSS_OK, HSS_ERR_STATE (a handle not compressed) or HSS_ERR_ARG;
- * nothing is computed on an error.  Host-synchronous; all work on `stream`.
+ * nothing is computed on an error.  Stream-ordered, like hss_matvec.
  */
 hss_status hss_matvec_batched(int nmat, const hss_handle* h, int nrhs, const double* const* x,
                               const long long* ldx, double* const* b, const long long* ldb,
@@ -190,9 +192,10 @@ hss_status hss_matvec_batched(int nmat, const hss_handle* h, int nrhs, const dou
  * pivoting.  Host-synchronous. */
 hss_status hss_factor(hss_handle h, void* stream);
 
-/* Solve A_HSS x = b after hss_factor (Alg. 4).  b, x: DEVICE n x nrhs;
- * HSS_ERR_STATE before hss_factor.  Host-synchronous, like hss_matvec: all
- * device work goes to `stream`, and the call returns once x is written. */
+/* Solve A_HSS x = b after hss_factor (Alg. 4).  b, x: DEVICE n x nrhs
+ * (ldb, ldx >= nrhs); HSS_ERR_STATE before hss_factor.  Stream-ordered, like
+ * hss_matvec: the work is queued on `stream`, x is written once it has run,
+ * and b must stay unchanged until then. */
 hss_status hss_solve(hss_handle h, int nrhs, const double* b, long long ldb,
                      double* x, long long ldx, void* stream);
 
@@ -216,6 +219,11 @@ typedef struct {
   double t_sample_gemm_ms;     /* their summed duration (HIP events on the stream) */
   double sample_gemm_flops;    /* their algorithmic flops, 2 n^2 per column per side */
   double sample_gemm_bytes;    /* their algorithmic bytes: A once per launch + R in + S out */
+  double id_flops;             /* pivoted QRs: 4 d m k per ID attempt and side (k: steps taken) */
+  double t_level_gemm_ms;      /* local-sample and R_tau products (HIP events) */
+  double level_gemm_bytes;     /* their algorithmic bytes: operands once, C when read */
+  double t_gather_ms;          /* D and B gathers from A (HIP events) */
+  double gather_bytes;         /* their algorithmic bytes: entries read from A + written */
 } hss_stats_t;
 
 hss_status hss_stats(hss_handle h, hss_stats_t* st);
@@ -259,7 +267,33 @@ hss_status hss_export_node(hss_handle h, int node, hss_node_generators* g);
 hss_status hss_import(long long n, const hss_tree* tree, const int* kr, const int* kc,
                       const hss_node_generators* nodes, hss_handle* out);
 
+/* Frees the handle's device memory, after the work of its stream-ordered
+ * calls (matvec, solve) has run: waits for it on the host. */
 void hss_destroy(hss_handle h);
+
+/*
+ * Device memory allocator for everything the library allocates on the device
+ * (handles, compression buffers, workspaces), for callers that want one pool
+ * for their framework and the library (e.g. PyTorch's caching allocator).
+ *  alloc(bytes, device, stream, ctx)  returns at least `bytes` bytes of device
+ *      memory on `device` (the current device of the call), 256-byte
+ *      aligned, that work queued on `stream` after the call may use; NULL
+ *      on failure (the library call then returns HSS_ERR_ALLOC).
+ *  free(p, bytes, device, stream, ctx)  gives back a block: `stream` and
+ *      `bytes` are those of the matching alloc; the library no longer uses p
+ *      in work queued on `stream` after this call (it waited on the host for
+ *      uses on other streams), so the allocator may reuse p for work queued
+ *      later on that stream, as stream-ordered pools do.
+ * Both NULL: the default (the runtime's stream-ordered pool plus the
+ * library's cache of freed blocks, see hss_release_cached_memory).  Every
+ * block goes back to the allocator that made it, so the allocator may be
+ * changed while handles are live.  Process-wide; the callbacks may be called
+ * from any thread (also the server's workers).  HSS_ERR_ARG if exactly one of
+ * alloc, free is NULL.
+ */
+typedef void* (*hss_alloc_fn)(size_t bytes, int device, void* stream, void* ctx);
+typedef void (*hss_free_fn)(void* p, size_t bytes, int device, void* stream, void* ctx);
+hss_status hss_set_allocator(hss_alloc_fn alloc, hss_free_fn free, void* ctx);
 
 /* Gives back to the runtime the memory that the library keeps for reuse:
    freed device blocks of 1 MB and more (up to a quarter of each device's
@@ -276,38 +310,49 @@ const char* hss_last_error(void);
 
 /* ---------------------------------------------------------------------
  * Serving: requests of compress (Alg. 1, adaptive sampling of Sec. 3.3) +
- * ULV factorization (Alg. 3) + solve (Alg. 4) that arrive over time.
+ * ULV factorization (Alg. 3) + solve (Alg. 4) that arrive over time, and
+ * solve-only requests (Alg. 4) against handles the server keeps resident.
  *
  * Requests wait in arrival order.  Each worker thread of the server owns a
- * HIP stream; a free worker admits the oldest waiting request and, behind
- * it, the waiting requests with the same storage type and options, while
- * their estimated device footprint (about 8 n d_max doubles of compression
- * buffers plus the factors) fits the budget and the batch holds at most
- * max_batch requests; it compresses them with one hss_compress_batched
- * call, factors and solves each, then frees their footprint.  Requests that
- * arrive meanwhile are admitted by the next free worker as memory frees up,
- * so their work overlaps on the device with the batches already running.
- * A request whose footprint alone exceeds the budget runs when nothing else
- * is admitted.  Each result is computed exactly as the same calls made
- * alone would compute it, up to the rounding of a batch's QRCP path choice.
+ * HIP stream; a free worker admits the oldest waiting request it can run
+ * and, behind it, the waiting requests of the same kind:
+ *  - compress requests with the same storage type and options, compressed
+ *    together by one batched compression (hss_compress_batched), then
+ *    factored and solved one by one;
+ *  - solve-only requests on distinct resident handles, queued back to back
+ *    on the worker's stream;
+ * while their device footprint fits the budget and the batch holds at most
+ * max_batch requests.  A compress request's footprint counts A, b and x,
+ * the compression buffers (about 8 n d_max doubles) and the generators and
+ * ULV factors; a solve-only request's counts b, x and the solve workspace.
+ * Handles kept resident count with their actual device bytes until
+ * hss_server_release.  Requests that arrive meanwhile are admitted by the
+ * next free worker as memory frees up, so their work overlaps on the device
+ * with the batches already running.  A request whose footprint alone
+ * exceeds the budget runs when nothing else is admitted.  Each result is
+ * computed exactly as the same calls made alone would compute it, up to the
+ * rounding of a batch's QRCP path choice.
  * ------------------------------------------------------------------- */
 typedef struct hss_server_s* hss_server;
 
 typedef struct {
-  long long hbm_budget; /* bytes of device memory admitted requests may hold;
-                           0: 80 % of the device's memory */
-  int max_batch;        /* requests compressed together (default 32) */
+  long long hbm_budget; /* bytes of device memory admitted requests and resident
+                           handles may hold; 0: 80 % of the device's memory */
+  int max_batch;        /* requests admitted together (default 32) */
   int workers;          /* worker threads / streams, 1..16 (default 2) */
 } hss_server_opts;
 
 typedef struct {
   int status;       /* HSS_OK, HSS_NOT_CONVERGED, or the error of the request */
-  int batch_size;   /* requests compressed in the same batch */
-  int d_final;      /* random vectors used */
+  int batch_size;   /* requests admitted in the same batch */
+  int d_final;      /* random vectors used (compress requests) */
   int max_rank;     /* largest generator rank */
   double t_submit;  /* seconds since the server started: submitted, */
   double t_start;   /* admitted, */
   double t_done;    /* solved (results in x) */
+  hss_handle handle; /* compress requests with keep = 1: the compressed and
+                        factored handle, resident in the server until
+                        hss_server_release; NULL otherwise */
 } hss_request_info;
 
 /* Fills *o with hbm_budget 0 (80 % of device memory), max_batch 32,
@@ -318,14 +363,45 @@ void hss_server_default_opts(hss_server_opts* o);
 hss_status hss_server_create(const hss_server_opts* opts, hss_server* out);
 
 /*
- * Queues one request: compress A (DEVICE n x n row-major, leading dimension
- * lda, storage dtype; opts as in hss_compress, NULL: defaults, no user
- * random matrices), factor, and solve A_HSS x = b for nrhs columns (b, x:
- * DEVICE n x nrhs with leading dimensions ldb, ldx; nrhs may be 0).  The
- * server reads A and b after the work queued so far on `stream` (the
- * stream that wrote them).  A and b must stay valid and unchanged, and x
- * untouched, until hss_server_wait on *ticket returns.  Returns at once.
+ * One request.
+ *  Compress request (handle NULL): compress A (DEVICE n x n row-major,
+ *    leading dimension lda, storage dtype; opts as in hss_compress, NULL:
+ *    defaults, no user random matrices), factor, and solve A_HSS x = b for
+ *    nrhs columns (nrhs may be 0).  keep = 1 keeps the compressed and
+ *    factored handle resident: it is returned in hss_request_info.handle and
+ *    serves later solve-only requests; it belongs to the server (do not
+ *    hss_destroy it) until hss_server_release.
+ *  Solve-only request (handle = a resident handle, A NULL): solve
+ *    A_HSS x = b with the handle's factors (nrhs >= 1); n is taken from the
+ *    handle.  Requests on one handle run one at a time, in arrival order.
+ *  b, x: DEVICE n x nrhs with leading dimensions ldb, ldx.
  */
+typedef struct {
+  const void* A;
+  int dtype;
+  long long n;
+  long long lda;
+  const hss_opts* opts;
+  hss_handle handle;
+  int nrhs;
+  const double* b;
+  long long ldb;
+  double* x;
+  long long ldx;
+  int keep;
+} hss_server_request;
+
+/*
+ * Queues request *r (copied).  The server reads A and b after the work queued
+ * so far on `stream` (the stream that wrote them).  A and b must stay valid
+ * and unchanged, and x untouched, until hss_server_wait on *ticket returns.
+ * Returns at once.  HSS_ERR_ARG for invalid sizes or pointers or a handle
+ * that is not resident in this server (or is being released).
+ */
+hss_status hss_server_submit_request(hss_server s, const hss_server_request* r, void* stream,
+                                     long long* ticket);
+
+/* A compress request with keep = 0 (the arguments of hss_server_request). */
 hss_status hss_server_submit(hss_server s, const void* A, int dtype, long long n, long long lda,
                              const hss_opts* opts, int nrhs, const double* b, long long ldb,
                              double* x, long long ldx, void* stream, long long* ticket);
@@ -336,7 +412,15 @@ hss_status hss_server_submit(hss_server s, const void* A, int dtype, long long n
  */
 hss_status hss_server_wait(hss_server s, long long ticket, hss_request_info* info);
 
-/* Finishes every queued request, stops the workers and frees the server. */
+/*
+ * Destroys a resident handle (from a keep = 1 request) once the requests on
+ * it that are queued or running have finished (waits for them), and gives
+ * its bytes back to the budget.  HSS_ERR_ARG if h is not resident here.
+ */
+hss_status hss_server_release(hss_server s, hss_handle h);
+
+/* Finishes every queued request, stops the workers, destroys the handles
+ * still resident and frees the server. */
 void hss_server_destroy(hss_server s);
 
 /* ---------------------------------------------------------------------
@@ -369,8 +453,9 @@ hss_status hss_random_normal(unsigned long long seed, int which, long long n, in
  * Sc/Rc may be NULL.  sample_prec as in hss_sample_prec: the reduced modes
  * need dtype HSS_F32 and R already representable in their precision
  * (hss_random_normal with the same sample_prec); HSS_ERR_ARG otherwise.
- * Stream-ordered with HSS_SAMPLE_F64; the reduced-precision modes stage
- * launch descriptors and return once the products are written.
+ * Stream-ordered in every mode.  The split-K partial sums (and, in the
+ * reduced modes, the copies of R in the products' precision) go to a
+ * workspace the call allocates and frees stream-ordered.
  */
 hss_status hss_sample(const void* A, int dtype, int sample_prec, long long n, long long lda,
                       const int* leaf_of, int ncols, const double* Rr, const double* Rc,

@@ -6,7 +6,11 @@ functions keep the C names:
 
     hss_compress, hss_matvec, hss_factor, hss_solve, hss_stats, hss_ranks,
     hss_export_node, hss_import, hss_destroy, hss_release_cached_memory,
-    hss_random_normal, hss_sample, hss_id_batched, hss_default_opts
+    hss_set_allocator, hss_random_normal, hss_sample, hss_id_batched,
+    hss_default_opts
+
+``use_torch_allocator()`` points hss_set_allocator at PyTorch's caching
+allocator, so that the library and PyTorch share one device memory pool.
 
 The library is loaded on first use; if it has not been built (see
 ``build.py``) every call raises ``RuntimeError`` -- there is no fallback.
@@ -34,10 +38,10 @@ EXPORTED = [
     "hss_factor",
     "hss_solve", "hss_stats",
     "hss_ranks", "hss_export_node", "hss_import", "hss_destroy", "hss_release_cached_memory",
-    "hss_last_error",
+    "hss_set_allocator", "hss_last_error",
     "hss_random_normal", "hss_sample", "hss_id_batched",
-    "hss_server_default_opts", "hss_server_create", "hss_server_submit", "hss_server_wait",
-    "hss_server_destroy",
+    "hss_server_default_opts", "hss_server_create", "hss_server_submit", "hss_server_submit_request",
+    "hss_server_wait", "hss_server_release", "hss_server_destroy",
 ]
 
 
@@ -47,7 +51,14 @@ class hss_server_opts(C.Structure):
 
 class hss_request_info(C.Structure):
     _fields_ = [("status", C.c_int), ("batch_size", C.c_int), ("d_final", C.c_int), ("max_rank", C.c_int),
-                ("t_submit", C.c_double), ("t_start", C.c_double), ("t_done", C.c_double)]
+                ("t_submit", C.c_double), ("t_start", C.c_double), ("t_done", C.c_double),
+                ("handle", C.c_void_p)]
+
+
+class hss_server_request(C.Structure):
+    _fields_ = [("A", C.c_void_p), ("dtype", C.c_int), ("n", C.c_longlong), ("lda", C.c_longlong),
+                ("opts", C.c_void_p), ("handle", C.c_void_p), ("nrhs", C.c_int), ("b", C.c_void_p),
+                ("ldb", C.c_longlong), ("x", C.c_void_p), ("ldx", C.c_longlong), ("keep", C.c_int)]
 
 
 class HSSError(RuntimeError):
@@ -78,6 +89,8 @@ class hss_stats_t(C.Structure):
         ("t_total_ms", C.c_double), ("t_sample_ms", C.c_double), ("t_levels_ms", C.c_double),
         ("t_id_ms", C.c_double), ("n_sample_launches", C.c_int), ("t_sample_gemm_ms", C.c_double),
         ("sample_gemm_flops", C.c_double), ("sample_gemm_bytes", C.c_double),
+        ("id_flops", C.c_double), ("t_level_gemm_ms", C.c_double), ("level_gemm_bytes", C.c_double),
+        ("t_gather_ms", C.c_double), ("gather_bytes", C.c_double),
     ]
 
 
@@ -85,7 +98,13 @@ class hss_node_generators(C.Structure):
     _fields_ = [(f, C.c_void_p) for f in ("Jr", "Jc", "Er", "Ec", "Ir", "Ic", "D", "B12", "B21")]
 
 
+# void* alloc(size_t bytes, int device, void* stream, void* ctx)
+_ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_int, C.c_void_p, C.c_void_p)
+# void free(void* p, size_t bytes, int device, void* stream, void* ctx)
+_FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_size_t, C.c_int, C.c_void_p, C.c_void_p)
+
 _lib = None
+_allocator_keep = None  # the ctypes callbacks in use must outlive their registration
 
 
 def lib() -> C.CDLL:
@@ -111,7 +130,9 @@ def lib() -> C.CDLL:
         L.hss_server_create.argtypes = [C.POINTER(hss_server_opts), C.POINTER(vp)]
         L.hss_server_submit.argtypes = [vp, vp, i, ll, ll, C.POINTER(hss_opts), i, vp, ll, vp, ll, vp,
                                         C.POINTER(C.c_longlong)]
+        L.hss_server_submit_request.argtypes = [vp, C.POINTER(hss_server_request), vp, C.POINTER(C.c_longlong)]
         L.hss_server_wait.argtypes = [vp, C.c_longlong, C.POINTER(hss_request_info)]
+        L.hss_server_release.argtypes = [vp, vp]
         L.hss_server_destroy.argtypes = [vp]
         L.hss_server_destroy.restype = None
         L.hss_factor.argtypes = [vp, vp]
@@ -123,6 +144,7 @@ def lib() -> C.CDLL:
         L.hss_destroy.argtypes = [vp]
         L.hss_destroy.restype = None
         L.hss_release_cached_memory.argtypes = []
+        L.hss_set_allocator.argtypes = [_ALLOC_FN, _FREE_FN, vp]
         L.hss_random_normal.argtypes = [C.c_ulonglong, i, ll, i, i, i, vp, ll, vp]
         L.hss_sample.argtypes = [vp, i, i, ll, ll, vp, i, vp, vp, ll, vp, vp, ll, vp]
         L.hss_id_batched.argtypes = [i, vp, vp, vp, vp, d, vp, vp, vp, vp]
@@ -404,6 +426,56 @@ def hss_release_cached_memory() -> None:
     _check(lib().hss_release_cached_memory())
 
 
+def hss_set_allocator(alloc=None, free=None) -> None:
+    """Device allocator of the library (hss_set_allocator): ``alloc(bytes,
+    device, stream) -> int address`` (0 on failure) and ``free(address,
+    bytes, device, stream)``, with stream the hipStream_t as an int (0: the
+    default stream); both None restores the library's own pool."""
+    global _allocator_keep
+    if (alloc is None) != (free is None):
+        raise ValueError("give both alloc and free, or neither")
+    if alloc is None:
+        _check(lib().hss_set_allocator(_ALLOC_FN(), _FREE_FN(), None))
+        _allocator_keep = None
+        return
+
+    def _a(nbytes, dev, stream, ctx):
+        try:
+            return int(alloc(int(nbytes), int(dev), int(stream or 0))) or None
+        except Exception:  # an exception must not cross into C: report failure
+            return None
+
+    def _f(p, nbytes, dev, stream, ctx):
+        try:
+            free(int(p), int(nbytes), int(dev), int(stream or 0))
+        except Exception:
+            pass
+
+    fa, ff = _ALLOC_FN(_a), _FREE_FN(_f)
+    _check(lib().hss_set_allocator(fa, ff, None))
+    _allocator_keep = (fa, ff)
+
+
+def use_torch_allocator(on: bool = True) -> None:
+    """Let the library allocate its device memory from PyTorch's caching
+    allocator (on=False: back to the library's own pool).  Blocks are taken
+    for the stream the library uses them on and given back when it is done
+    with them, with PyTorch's stream-ordered reuse."""
+    import torch
+
+    if not on:
+        hss_set_allocator(None, None)
+        return
+
+    def alloc(nbytes, dev, stream):
+        return torch.cuda.caching_allocator_alloc(nbytes, dev, stream)
+
+    def free(p, nbytes, dev, stream):
+        torch.cuda.caching_allocator_delete(p)
+
+    hss_set_allocator(alloc, free)
+
+
 def hss_random_normal(seed: int, which: int, n: int, col0: int, col1: int, out=None, stream=None,
                       sample_prec: str = "f64"):
     import torch
@@ -463,10 +535,21 @@ def hss_id_batched(Ys, rtol: float, stream=None):
     return out
 
 
+class ResidentHandle:
+    """A compressed and factored handle kept resident in a server (a
+    compress request with keep=True); owned by the server until
+    ``HSSServer.release``."""
+
+    def __init__(self, ptr: int, n: int):
+        self.ptr = C.c_void_p(ptr)
+        self.n = n
+
+
 class HSSServer:
-    """The serving loop of the C ABI (hss_server_*): requests of compress +
-    ULV factor + solve, admitted by a device-memory budget and batched with
-    the compatible requests waiting at the time, on several streams."""
+    """The serving loop of the C ABI (hss_server_*): compress + ULV factor +
+    solve requests and solve-only requests on resident handles, admitted by
+    a device-memory budget and batched with the compatible requests waiting
+    at the time, on several streams."""
 
     def __init__(self, hbm_budget: int = 0, max_batch: int = 32, workers: int = 2):
         o = hss_server_opts()
@@ -476,31 +559,53 @@ class HSSServer:
         _check(lib().hss_server_create(C.byref(o), C.byref(self._ptr)))
         self._keep = {}
 
-    def submit(self, A, b, x=None, *, rtol=1e-6, d0=64, dd=32, d_max=4096, p_margin=10, seed=0,
+    @staticmethod
+    def _rhs(b, x, n):
+        import torch
+
+        b2 = b.reshape(-1, 1) if b.dim() == 1 else b
+        if b2.dtype != torch.float64 or b2.stride(1) != 1 or b2.shape[0] != n or not b2.is_cuda:
+            raise ValueError("b must be CUDA float64, n x nrhs with unit column stride")
+        if x is None:
+            x = torch.empty_like(b)
+        x2 = x.reshape(-1, 1) if x.dim() == 1 else x
+        return b2, x, x2
+
+    def submit(self, A, b, x=None, *, keep=False, rtol=1e-6, d0=64, dd=32, d_max=4096, p_margin=10, seed=0,
                leaf_size=64, sample_prec="f64") -> int:
-        """Queue A (square CUDA float32/float64) and right-hand sides b (CUDA
-        float64, n or n x nrhs); returns a ticket.  x (optional output,
-        same shape as b) is allocated when not given."""
+        """Queue a compress + factor + solve request: A (square CUDA
+        float32/float64) and right-hand sides b (CUDA float64, n or n x
+        nrhs); returns a ticket.  x (optional output, same shape as b) is
+        allocated when not given.  keep=True keeps the factored handle
+        resident: ``wait`` returns it as info["handle"] (a ResidentHandle)."""
         import torch
 
         dt = {torch.float64: HSS_F64, torch.float32: HSS_F32}.get(A.dtype)
         if dt is None or A.dim() != 2 or A.shape[0] != A.shape[1] or A.stride(1) != 1 or not A.is_cuda:
             raise ValueError("A must be a square CUDA float32/float64 matrix with unit column stride")
-        b2 = b.reshape(-1, 1) if b.dim() == 1 else b
-        if b2.dtype != torch.float64 or b2.stride(1) != 1 or b2.shape[0] != A.shape[0]:
-            raise ValueError("b must be float64, n x nrhs with unit column stride")
-        if x is None:
-            x = torch.empty_like(b)
-        x2 = x.reshape(-1, 1) if x.dim() == 1 else x
+        b2, x, x2 = self._rhs(b, x, A.shape[0])
         o = hss_default_opts()
         o.rtol, o.d0, o.dd, o.d_max, o.p_margin = float(rtol), int(d0), int(dd), int(d_max), int(p_margin)
         o.seed, o.leaf_size, o.sample_prec = int(seed), int(leaf_size), _PREC[sample_prec]
+        q = hss_server_request(A=A.data_ptr(), dtype=dt, n=A.shape[0], lda=A.stride(0),
+                               opts=C.addressof(o), handle=None, nrhs=b2.shape[1], b=b2.data_ptr(),
+                               ldb=b2.stride(0), x=x2.data_ptr(), ldx=x2.stride(0), keep=1 if keep else 0)
         t = C.c_longlong()
         # the server reads A and b after the work queued so far on the current stream
-        _check(lib().hss_server_submit(self._ptr, _ptr(A), dt, A.shape[0], A.stride(0), C.byref(o),
-                                       b2.shape[1], _ptr(b2), b2.stride(0), _ptr(x2), x2.stride(0),
-                                       _stream(None), C.byref(t)))
-        self._keep[t.value] = (A, b, x)
+        _check(lib().hss_server_submit_request(self._ptr, C.byref(q), _stream(None), C.byref(t)))
+        self._keep[t.value] = (A, b, x, A.shape[0])
+        return t.value
+
+    def solve(self, handle: "ResidentHandle", b, x=None) -> int:
+        """Queue a solve-only request A_HSS x = b on a resident handle;
+        returns a ticket."""
+        b2, x, x2 = self._rhs(b, x, handle.n)
+        q = hss_server_request(A=None, dtype=0, n=handle.n, lda=0, opts=None, handle=handle.ptr,
+                               nrhs=b2.shape[1], b=b2.data_ptr(), ldb=b2.stride(0), x=x2.data_ptr(),
+                               ldx=x2.stride(0), keep=0)
+        t = C.c_longlong()
+        _check(lib().hss_server_submit_request(self._ptr, C.byref(q), _stream(None), C.byref(t)))
+        self._keep[t.value] = (None, b, x, handle.n)
         return t.value
 
     def wait(self, ticket: int):
@@ -511,8 +616,15 @@ class HSSServer:
             _check(lib().hss_server_wait(self._ptr, int(ticket), None))
         info = hss_request_info()
         lib().hss_server_wait(self._ptr, int(ticket), C.byref(info))
-        A, b, x = self._keep.pop(ticket)
-        return x, {f: getattr(info, f) for f, _ in hss_request_info._fields_}
+        A, b, x, n = self._keep.pop(ticket)
+        out = {f: getattr(info, f) for f, _ in hss_request_info._fields_}
+        out["handle"] = ResidentHandle(info.handle, n) if info.handle else None
+        return x, out
+
+    def release(self, handle: "ResidentHandle") -> None:
+        """Destroy a resident handle once the requests on it have finished."""
+        _check(lib().hss_server_release(self._ptr, handle.ptr))
+        handle.ptr = C.c_void_p()
 
     def close(self):
         if self._ptr:
@@ -543,6 +655,15 @@ def hss_server_submit(server: HSSServer, A, b, x=None, **kw) -> int:
 
 def hss_server_wait(server: HSSServer, ticket: int):
     return server.wait(ticket)
+
+
+def hss_server_submit_request(server: HSSServer, handle: ResidentHandle, b, x=None) -> int:
+    """Solve-only request on a resident handle (compress requests: hss_server_submit)."""
+    return server.solve(handle, b, x)
+
+
+def hss_server_release(server: HSSServer, handle: ResidentHandle) -> None:
+    server.release(handle)
 
 
 def hss_server_destroy(server: HSSServer) -> None:

@@ -131,7 +131,68 @@ void trim_cache(int dev, hipStream_t s) {
 }
 }  // namespace
 
+namespace {
+// A caller-supplied allocator (hss_set_allocator).  Blocks remember the
+// allocator that made them, so changing allocators while blocks are live is
+// safe: each goes back where it came from.
+struct UserAlloc {
+  hss_alloc_fn alloc = nullptr;
+  hss_free_fn free = nullptr;
+  void* ctx = nullptr;
+};
+struct UserBlock {
+  size_t bytes;
+  int dev;
+  hipStream_t stream;  // the stream the block was allocated for
+  UserAlloc ua;
+};
+std::mutex g_user_mu;
+UserAlloc g_user;
+std::unordered_map<void*, UserBlock> g_user_live;
+
+void* user_alloc(const UserAlloc& ua, size_t bytes, hipStream_t s) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+  // called without the lock: the allocator may call back into anything
+  void* p = ua.alloc(bytes, dev, s, ua.ctx);
+  if (!p) return nullptr;
+  std::lock_guard<std::mutex> lk(g_user_mu);
+  g_user_live[p] = UserBlock{bytes, dev, s, ua};
+  return p;
+}
+
+// true if p came from a caller-supplied allocator (and was given back)
+bool user_free(void* p, hipStream_t s) {
+  UserBlock ub{};
+  {
+    std::lock_guard<std::mutex> lk(g_user_mu);
+    auto it = g_user_live.find(p);
+    if (it == g_user_live.end()) return false;
+    ub = it->second;
+    g_user_live.erase(it);
+  }
+  // the allocator orders reuse after the work on the block's own stream; if
+  // the last use was on another stream, wait for it here
+  if (s != ub.stream) {
+    hipEvent_t ev = nullptr;
+    if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) == hipSuccess && hipEventRecord(ev, s) == hipSuccess)
+      (void)hipEventSynchronize(ev);
+    else
+      (void)hipDeviceSynchronize();
+    if (ev) (void)hipEventDestroy(ev);
+  }
+  ub.ua.free(p, ub.bytes, ub.dev, ub.stream, ub.ua.ctx);
+  return true;
+}
+}  // namespace
+
 void* pool_alloc(size_t bytes, hipStream_t s) {
+  UserAlloc ua;
+  {
+    std::lock_guard<std::mutex> lk(g_user_mu);
+    ua = g_user;
+  }
+  if (ua.alloc) return user_alloc(ua, bytes ? bytes : 1, s);
   std::call_once(g_dev_once, [] {
     size_t fr = 0, tot = 0;
     if (hipMemGetInfo(&fr, &tot) == hipSuccess) g_dev_cap = tot / 4;
@@ -172,6 +233,7 @@ void* pool_alloc(size_t bytes, hipStream_t s) {
 
 void pool_free(void* p, hipStream_t s) {
   if (!p) return;
+  if (user_free(p, s)) return;
   std::lock_guard<std::mutex> lk(g_dev_mu);
   auto it = g_dev_live.find(p);
   if (it == g_dev_live.end()) {  // below the cached sizes
@@ -335,33 +397,100 @@ hipError_t Staging::init(size_t bytes, hipStream_t s) {
   size_t b = (size_t)1 << 20;
   while (b < bytes) b <<= 1;
   stream = s;
-  cap = b;
   used = 0;
+  stream_used = false;
+  // a retired block whose readers have run, or, with too many retired
+  // blocks, the oldest one once its readers have run
+  constexpr size_t kMaxSpares = 4;
+  for (size_t q = 0; q < spares.size(); ++q) {
+    const bool last_try = spares.size() >= kMaxSpares && q == 0;
+    if (spares[q].cap < b && !last_try) continue;
+    const hipError_t qe = last_try ? hipEventSynchronize(spares[q].ev) : hipEventQuery(spares[q].ev);
+    if (qe == hipErrorNotReady) continue;
+    if (qe != hipSuccess) return qe;
+    Spare sp = spares[q];
+    spares.erase(spares.begin() + q);
+    (void)hipEventDestroy(sp.ev);
+    if (sp.cap < b) {  // too small: free it and look again
+      pinned_put(sp.host, sp.cap);
+      pool_free(sp.dev, s);
+      --q;
+      continue;
+    }
+    host = sp.host;
+    dev = sp.dev;
+    cap = sp.cap;
+    return hipSuccess;
+  }
+  cap = b;
   host = pinned_get(b);
-  if (!host) return hipErrorOutOfMemory;
+  if (!host) {
+    cap = 0;
+    return hipErrorOutOfMemory;
+  }
   dev = static_cast<char*>(pool_alloc(b, s));
-  return dev ? hipSuccess : hipErrorOutOfMemory;
+  if (!dev) {
+    pinned_put(host, b);
+    host = nullptr;
+    cap = 0;
+    return hipErrorOutOfMemory;
+  }
+  return hipSuccess;
+}
+
+hipError_t Staging::retire() {
+  if (!host || used == 0) return hipSuccess;
+  hipEvent_t ev = nullptr;
+  hipError_t e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventRecord(ev, stream);
+  if (e != hipSuccess) {  // cannot fence: wait instead, and keep the block
+    if (ev) (void)hipEventDestroy(ev);
+    e = hipStreamSynchronize(stream);
+    used = 0;
+    return e;
+  }
+  spares.push_back(Spare{host, dev, cap, ev});
+  host = dev = nullptr;
+  cap = used = 0;
+  stream_used = false;
+  return hipSuccess;
 }
 
 void Staging::release() {
-  // queued copies may still read the pinned block: it is reused only after them
+  // queued copies and kernels may still read the blocks: they are reused only after them
   if (host && stream_used) (void)hipStreamSynchronize(stream);
-  pinned_put(host, cap);
-  pool_free(dev, stream);
+  if (host) pinned_put(host, cap);
+  if (dev) pool_free(dev, stream);
+  for (Spare& sp : spares) {  // their readers have run once the event completed
+    (void)hipEventSynchronize(sp.ev);
+    (void)hipEventDestroy(sp.ev);
+    pinned_put(sp.host, sp.cap);
+    pool_free(sp.dev, nullptr);
+  }
+  spares.clear();
   host = dev = nullptr;
   cap = used = 0;
 }
 
+// a block of at least `need` bytes with nothing pushed yet
+static bool fresh_block(Staging& st, size_t need) {
+  if (st.host && st.used == 0 && need <= st.cap) return true;
+  if (st.host && st.retire() != hipSuccess) return false;
+  if (st.host && need <= st.cap) return true;  // retire fell back to a wait
+  if (st.host) {  // too small: give it back
+    if (st.stream_used && hipStreamSynchronize(st.stream) != hipSuccess) return false;
+    pinned_put(st.host, st.cap);
+    pool_free(st.dev, st.stream);
+    st.host = st.dev = nullptr;
+    st.cap = st.used = 0;
+  }
+  return st.init(std::max(need * 2, (size_t)1 << 20), st.stream) == hipSuccess;
+}
+
 void* Staging::push(const void* src, size_t bytes) {
   const size_t need = round_up(bytes ? bytes : 1, 256);
-  if (used + need > cap) {
-    // every queued copy must have read its region before it is rewritten
-    if (hipStreamSynchronize(stream) != hipSuccess) return nullptr;
-    used = 0;
-    if (need > cap) {  // first use or growth
-      release();
-      if (init(std::max(need * 2, (size_t)1 << 20), stream) != hipSuccess) return nullptr;
-    }
+  if (!host || used + need > cap) {
+    if (!fresh_block(*this, need)) return nullptr;
   }
   std::memcpy(host + used, src, bytes);
   stream_used = true;
@@ -375,14 +504,16 @@ void* Staging::push(const void* src, size_t bytes) {
 bool Staging::reserve(std::initializer_list<size_t> sizes) {
   size_t total = 0;
   for (size_t b : sizes) total += round_up(b ? b : 1, 256);
-  if (used + total <= cap) return true;
-  if (hipStreamSynchronize(stream) != hipSuccess) return false;
-  used = 0;
-  if (total > cap) {
-    release();
-    if (init(std::max(total * 2, (size_t)1 << 20), stream) != hipSuccess) return false;
-  }
-  return true;
+  if (host && used + total <= cap) return true;
+  return fresh_block(*this, total);
+}
+
+long long resident_bytes(const Handle& H) {
+  long long b = (long long)H.gen->total / std::max<long>(1, H.gen.use_count());
+  b += (long long)(H.work_id.cap + H.work_sample.cap + H.work_mv.cap + H.work_misc.cap);
+  b += (long long)H.staging.cap;
+  for (const Staging::Spare& sp : H.staging.spares) b += (long long)sp.cap;
+  return b;
 }
 
 long long Handle::generator_bytes() const {
@@ -513,7 +644,8 @@ T* work_alloc(Arena& W, size_t count) {
 // ---------------------------------------------------------------------------
 struct EventTimer {  // HIP events on the compression stream, summed at the end
   std::vector<hipEvent_t> ev;
-  std::vector<int> b, e, cat;  // begin, end, category (0 sample, 1 levels, 2 id, 3 sample GEMM)
+  // begin, end, category (0 sample, 1 levels, 2 id, 3 sample GEMM, 4 level GEMMs, 5 gathers)
+  std::vector<int> b, e, cat;
   hipStream_t s = nullptr;
   int begin() {  // an event that cannot be made or recorded is kept as null and not timed
     hipEvent_t x = nullptr;
@@ -621,7 +753,7 @@ hss_status sample_batch(Handle& L, const std::vector<SampleReq>& reqs, EventTime
       else
         HIPCHK(launch_sample_mixed(static_cast<const float*>(q.A), H.n, q.lda, H.leaf_of, nc, prec,
                                    H.Rr + c0, H.Rc + c0, H.ldg, H.Sr + c0, H.Sc + c0, H.ldg, work,
-                                   L.staging, L.stream));
+                                   L.stream));
       HIPCHK(hipGetLastError());
       L.n_sgemm += 2;
     }
@@ -655,6 +787,21 @@ Seg r_in(const Handle& H, int t, bool row_side, int c0) {
     s.split = row_side ? a.kc : a.kr;
   }
   return s;
+}
+
+// Algorithmic bytes of a batched GEMM launch: A, B and D once, C when read.
+double gemm_bytes(const std::vector<GemmDesc>& gd) {
+  double b = 0.0;
+  for (const GemmDesc& g : gd)
+    b += 8.0 * ((double)g.M * g.K + (double)g.K * g.N + (double)g.M * g.N * (g.beta != 0.0 ? 2.0 : 1.0));
+  return b;
+}
+
+// Algorithmic bytes of a gather launch: each entry read from A, written in FP64.
+double gather_bytes_of(const std::vector<GatherDesc>& g, int dtype) {
+  double b = 0.0;
+  for (const GatherDesc& d : g) b += (double)d.nr * d.nc * ((dtype == HSS_F32 ? 4.0 : 8.0) + 8.0);
+  return b;
 }
 
 // One node of one matrix in a level batch: node t of handle H, whose matrix
@@ -736,8 +883,11 @@ hss_status process_items(Handle& L, Arena& W, std::vector<Item>& items, EventTim
     v.cdone = 0;
     v.set_up = true;
   }
+  const int ev_g = tm.begin();
   HIPCHK(launch_gather(items[0].A, L.dtype, items[0].lda, gath.data(), (int)gath.size(), L.staging,
                        L.stream));
+  tm.end(ev_g, 5);
+  L.gather_bytes += gather_bytes_of(gath, L.dtype);
 
   // (2) local samples of inner nodes, columns [cdone, d) (Alg. 1 / Alg. 5)
   std::vector<GemmDesc> gd;
@@ -773,7 +923,10 @@ hss_status process_items(Handle& L, Arena& W, std::vector<Item>& items, EventTim
     mk(a.kc, b.kr, v.B21, a.kc, 1, b.Rc + c0, a.Sc + c0, a.perm_c, v.Sc + c0);
     mk(b.kc, a.kr, v.B12, b.kc, 1, a.Rc + c0, b.Sc + c0, b.perm_c, v.Sc + (long long)a.kc * H.ldg + c0);
   }
+  const int ev_g1 = tm.begin();
   HIPCHK(launch_gemm_batched(gd.data(), (int)gd.size(), L.staging, L.stream));
+  tm.end(ev_g1, 4);
+  L.lgemm_bytes += gemm_bytes(gd);
 
   // (3) interpolative decompositions of the nodes not yet compressed
   std::vector<int> idn;  // indices into items
@@ -810,6 +963,8 @@ hss_status process_items(Handle& L, Arena& W, std::vector<Item>& items, EventTim
     HIPCHK(launch_id_factor(pr.data(), np, L.opts.rtol, wk, L.work_id.cap, L.k_host, L.staging,
                             L.stream));
     L.staging.reset();
+    for (int q = 0; q < np; ++q)  // Householder QR of d x m to k steps: about 4 d m k flops
+      L.id_flops += 4.0 * (double)pr[q].d * (double)pr[q].m * (double)L.k_host[q];
     std::vector<int> sel;
     for (size_t q = 0; q < idn.size(); ++q) {
       Item& it = items[idn[q]];
@@ -904,7 +1059,10 @@ hss_status process_items(Handle& L, Arena& W, std::vector<Item>& items, EventTim
       gd.push_back(g);
     }
   }
+  const int ev_g2 = tm.begin();
   HIPCHK(launch_gemm_batched(gd.data(), (int)gd.size(), L.staging, L.stream));
+  tm.end(ev_g2, 4);
+  L.lgemm_bytes += gemm_bytes(gd);
   for (Item& it : items) node(it).cdone = it.d;
   tm.end(ev_level, 1);
   HIPCHK(hipStreamSynchronize(L.stream));
@@ -1101,11 +1259,13 @@ hss_status compress_batch(std::vector<Job>& jobs) {
   }
   if (!rg.empty())
     HIPCHK(launch_gather(rg[0].A, L.dtype, rg[0].lda, rg.data(), (int)rg.size(), L.staging, L.stream));
-  double acc[4] = {0, 0, 0, 0};
+  double acc[6] = {0, 0, 0, 0, 0, 0};
   tm.finish(acc);
   HIPCHK(hipStreamSynchronize(L.stream));
   L.staging.reset();
   W.release();  // the handles keep only their generators
+  L.work_id.release();  // compression-only workspaces (back to the pool or cache)
+  L.work_sample.release();
   for (Job& j : jobs) {
     Handle& H = *j.H;
     H.Rr = H.Rc = H.Sr = H.Sc = nullptr;
@@ -1120,6 +1280,11 @@ hss_status compress_batch(std::vector<Job>& jobs) {
     H.t_sample = acc[0];
     H.t_levels = acc[1];
     H.t_id = acc[2];
+    H.t_lgemm = acc[4];
+    H.t_gather = acc[5];
+    H.id_flops = L.id_flops;
+    H.lgemm_bytes = L.lgemm_bytes;
+    H.gather_bytes = L.gather_bytes;
     H.t_total = total;
     H.n_sgemm = L.n_sgemm;
     H.sgemm_flops = L.sgemm_flops;
@@ -1157,6 +1322,11 @@ void free_handle(hss_handle_s* p) {
   if (!p) return;
   Handle& H = p->h;
   if (H.stream) (void)hipStreamSynchronize(H.stream);
+  if (H.queued) {  // stream-ordered calls still reading the generators
+    (void)hipEventSynchronize(H.queued);
+    (void)hipEventDestroy(H.queued);
+    H.queued = nullptr;
+  }
   H.gen.reset();  // frees the arena unless other handles of its batch still hold it
   H.work_id.release();
   H.work_sample.release();
@@ -1173,6 +1343,45 @@ void free_handle(hss_handle_s* p) {
 // matvec (Alg. 2)
 // ---------------------------------------------------------------------------
 namespace hss {
+
+hss_status sample_args(const void* A, int dtype, int sample_prec, long long n, long long lda, int ncols,
+                       const double* Rr, const double* Rc, long long ldr, double* Sr, double* Sc,
+                       long long lds, long long* work_doubles) {
+  if (!A || n < 1 || lda < n || ncols < 0 || ldr < ncols || lds < ncols)
+    return fail(HSS_ERR_ARG, "sample arguments");
+  if ((Sr == nullptr) != (Rr == nullptr) || (Sc == nullptr) != (Rc == nullptr))
+    return fail(HSS_ERR_ARG, "S and R must be given together");
+  if (dtype != HSS_F64 && dtype != HSS_F32) return fail(HSS_ERR_ARG, "dtype");
+  if (sample_prec < HSS_SAMPLE_F64 || sample_prec > HSS_SAMPLE_BF16X3)
+    return fail(HSS_ERR_ARG, "unknown sample precision");
+  if (sample_prec != HSS_SAMPLE_F64 && dtype != HSS_F32)
+    return fail(HSS_ERR_ARG, "reduced-precision sampling needs A stored in FP32");
+  *work_doubles = sample_prec == HSS_SAMPLE_F64 ? sample_workspace_doubles(n, ncols)
+                                                : sample_mixed_workspace_doubles(n, ncols);
+  return HSS_OK;
+}
+
+hipError_t sample_queue(const void* A, int dtype, int sample_prec, long long n, long long lda,
+                        const int* leaf_of, int ncols, const double* Rr, const double* Rc, long long ldr,
+                        double* Sr, double* Sc, long long lds, double* work, hipStream_t s) {
+  if (sample_prec == HSS_SAMPLE_F64) {
+    launch_sample(A, dtype, n, lda, leaf_of, ncols, Rr, Rc, ldr, Sr, Sc, lds, work, s);
+    return hipGetLastError();
+  }
+  return launch_sample_mixed(static_cast<const float*>(A), n, lda, leaf_of, ncols, sample_prec, Rr, Rc,
+                             ldr, Sr, Sc, lds, work, s);
+}
+
+hipError_t mark_queued(Handle& H, hipStream_t s) {
+  if (!H.queued) {
+    const hipError_t e = hipEventCreateWithFlags(&H.queued, hipEventDisableTiming);
+    if (e != hipSuccess) {
+      H.queued = nullptr;
+      return e;
+    }
+  }
+  return hipEventRecord(H.queued, s);
+}
 
 // One matvec b = A_HSS x of a batch (Alg. 2).
 struct MvJob {
@@ -1385,9 +1594,10 @@ hss_status matvec_many(Handle& L, std::vector<MvJob>& jobs, hipStream_t s) {
     }
   }
   HIPCHK(flush());
-  // the descriptor tables live in the staging area until the copies ran
-  HIPCHK(hipStreamSynchronize(s));
-  L.staging.reset();
+  // stream-ordered: the descriptor tables stay in their staging block until
+  // the work queued so far has run
+  HIPCHK(L.staging.retire());
+  for (MvJob& J : jobs) HIPCHK(mark_queued(*J.H, s));
   return HSS_OK;
 }
 
@@ -1465,6 +1675,14 @@ hss_status hss_compress(const void* A, int dtype, long long n, long long lda,
 hss_status hss_compress_batched(int nmat, const void* const* A, int dtype, const long long* n,
                                 const long long* lda, const hss_tree* trees, const hss_opts* opts,
                                 void* stream, hss_handle* out, int* status) {
+  return hss::compress_batched(nmat, A, dtype, n, lda, trees, opts, stream, out, status, true);
+}
+
+}  // extern "C"
+
+hss_status hss::compress_batched(int nmat, const void* const* A, int dtype, const long long* n,
+                                 const long long* lda, const hss_tree* trees, const hss_opts* opts,
+                                 void* stream, hss_handle* out, int* status, bool share_arena) {
   g_err.clear();
   if (nmat < 1 || !A || !n || !lda || !out) return fail(HSS_ERR_ARG, "batch arguments");
   if (dtype != HSS_F64 && dtype != HSS_F32) return fail(HSS_ERR_ARG, "dtype");
@@ -1499,8 +1717,10 @@ hss_status hss_compress_batched(int nmat, const void* const* A, int dtype, const
       H.dtype = dtype;
       H.opts = o;
       H.verbose = v && v[0] && v[0] != '0';
-      if (i == 0) H.gen->chunk = (size_t)64 << 20;
-      else H.gen = hs[0]->h.gen;  // one generator arena for the batch
+      if (share_arena) {  // one generator arena for the batch
+        if (i == 0) H.gen->chunk = (size_t)64 << 20;
+        else H.gen = hs[0]->h.gen;
+      }
       st = build_tree(H, n[i], trees ? &trees[i] : nullptr, o.leaf_size);
       jobs[i].H = &H;
       jobs[i].A = A[i];
@@ -1525,6 +1745,8 @@ hss_status hss_compress_batched(int nmat, const void* const* A, int dtype, const
   }
   return all ? HSS_OK : HSS_NOT_CONVERGED;
 }
+
+extern "C" {
 
 hss_status hss_matvec(hss_handle h, int nrhs, const double* x, long long ldx, double* b,
                       long long ldb, void* stream) {
@@ -1591,6 +1813,11 @@ hss_status hss_stats(hss_handle h, hss_stats_t* st) {
   st->t_sample_gemm_ms = H.t_sgemm;
   st->sample_gemm_flops = H.sgemm_flops;
   st->sample_gemm_bytes = H.sgemm_bytes;
+  st->id_flops = H.id_flops;
+  st->t_level_gemm_ms = H.t_lgemm;
+  st->level_gemm_bytes = H.lgemm_bytes;
+  st->t_gather_ms = H.t_gather;
+  st->gather_bytes = H.gather_bytes;
   return HSS_OK;
 }
 
@@ -1734,6 +1961,17 @@ hss_status hss_import(long long n, const hss_tree* tree, const int* kr, const in
 
 void hss_destroy(hss_handle h) { free_handle(h); }
 
+hss_status hss_set_allocator(hss_alloc_fn alloc, hss_free_fn free_fn, void* ctx) {
+  g_err.clear();
+  if ((alloc == nullptr) != (free_fn == nullptr))
+    return fail(HSS_ERR_ARG, "alloc and free must both be given or both be NULL");
+  std::lock_guard<std::mutex> lk(g_user_mu);
+  g_user.alloc = alloc;
+  g_user.free = free_fn;
+  g_user.ctx = alloc ? ctx : nullptr;
+  return HSS_OK;
+}
+
 hss_status hss_release_cached_memory(void) {
   g_err.clear();
   HIPCHK(hss::release_cached_memory());
@@ -1758,32 +1996,17 @@ hss_status hss_sample(const void* A, int dtype, int sample_prec, long long n, lo
                       const int* leaf_of, int ncols, const double* Rr, const double* Rc,
                       long long ldr, double* Sr, double* Sc, long long lds, void* stream) {
   g_err.clear();
-  if (!A || n < 1 || lda < n || ncols < 0 || ldr < ncols || lds < ncols)
-    return fail(HSS_ERR_ARG, "sample arguments");
-  if ((Sr == nullptr) != (Rr == nullptr) || (Sc == nullptr) != (Rc == nullptr))
-    return fail(HSS_ERR_ARG, "S and R must be given together");
-  if (dtype != HSS_F64 && dtype != HSS_F32) return fail(HSS_ERR_ARG, "dtype");
-  if (sample_prec < HSS_SAMPLE_F64 || sample_prec > HSS_SAMPLE_BF16X3)
-    return fail(HSS_ERR_ARG, "unknown sample precision");
-  if (sample_prec != HSS_SAMPLE_F64 && dtype != HSS_F32)
-    return fail(HSS_ERR_ARG, "reduced-precision sampling needs A stored in FP32");
+  long long wd = 0;
+  CHK(sample_args(A, dtype, sample_prec, n, lda, ncols, Rr, Rc, ldr, Sr, Sc, lds, &wd));
   hipStream_t s = static_cast<hipStream_t>(stream);
-  const long long wd = sample_prec == HSS_SAMPLE_F64 ? sample_workspace_doubles(n, ncols)
-                                                     : sample_mixed_workspace_doubles(n, ncols);
   double* work = nullptr;
-  if (wd > 0) HIPCHK(hipMallocAsync(reinterpret_cast<void**>(&work), (size_t)wd * 8, s));
-  Staging st;  // descriptor tables of the reduced-precision path
-  st.stream = s;
-  hipError_t e = hipSuccess;
-  if (sample_prec == HSS_SAMPLE_F64) {
-    launch_sample(A, dtype, n, lda, leaf_of, ncols, Rr, Rc, ldr, Sr, Sc, lds, work, s);
-    e = hipGetLastError();
-  } else {
-    e = launch_sample_mixed(static_cast<const float*>(A), n, lda, leaf_of, ncols, sample_prec, Rr, Rc,
-                            ldr, Sr, Sc, lds, work, st, s);
+  if (wd > 0) {
+    work = static_cast<double*>(pool_alloc((size_t)wd * 8, s));
+    if (!work) return fail(HSS_ERR_ALLOC, "sampling workspace");
   }
-  if (work) (void)hipFreeAsync(work, s);
-  st.release();
+  const hipError_t e = sample_queue(A, dtype, sample_prec, n, lda, leaf_of, ncols, Rr, Rc, ldr, Sr, Sc,
+                                    lds, work, s);
+  pool_free(work, s);  // stream-ordered: reused only after the products ran
   HIPCHK(e);
   return HSS_OK;
 }
@@ -1811,18 +2034,18 @@ hss_status hss_id_batched(int nprob, const double* const* ys, const int* m, cons
   Staging st;
   HIPCHK(st.init((size_t)1 << 20, s));
   const size_t wb = id_workspace_bytes(pr.data(), nprob);
-  void* base = nullptr;
-  hipError_t e = hipMalloc(&base, wb);
-  if (e != hipSuccess) {
+  void* base = pool_alloc(wb, s);
+  if (!base) {
     st.release();
     return fail(HSS_ERR_ALLOC, "id workspace");
   }
-  e = launch_id_factor(pr.data(), nprob, rtol, base, wb, k, st, s);
+  hipError_t e = hipSuccess;
+  if (e == hipSuccess) e = launch_id_factor(pr.data(), nprob, rtol, base, wb, k, st, s);
   std::vector<int> sel(nprob);
   for (int q = 0; q < nprob; ++q) sel[q] = q;
   if (e == hipSuccess) e = launch_id_finish(pr.data(), nprob, k, sel.data(), nprob, base, st, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
-  (void)hipFree(base);
+  pool_free(base, s);
   st.release();
   HIPCHK(e);
   return HSS_OK;

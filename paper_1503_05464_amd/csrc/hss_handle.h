@@ -103,6 +103,9 @@ struct Handle {
   long long ldg = 0;
   int* leaf_of = nullptr;
   int* k_host = nullptr;  // pinned readback of ranks
+  // recorded after the work of the latest stream-ordered call (matvec,
+  // solve): hss_destroy waits for it before the generators are freed
+  hipEvent_t queued = nullptr;
   int k_host_cap = 0;
   // results
   int d = 0;
@@ -114,6 +117,9 @@ struct Handle {
   double t_total = 0, t_sample = 0, t_levels = 0, t_id = 0, t_sgemm = 0;
   int n_sgemm = 0;
   double sgemm_flops = 0, sgemm_bytes = 0;
+  // level kernels: ID flops (4 d m k per attempt and side), local-sample and
+  // R_tau GEMM bytes and time, D / B gather bytes and time
+  double id_flops = 0, lgemm_bytes = 0, t_lgemm = 0, gather_bytes = 0, t_gather = 0;
   // ULV root LU with partial pivoting (device data)
   double* root_lu = nullptr;
   int* root_piv = nullptr;
@@ -126,6 +132,24 @@ struct Handle {
 hss_status set_error(hss_status st, const std::string& msg);
 hss_status matvec_impl(Handle& H, int nrhs, const double* x, long long ldx, double* b,
                        long long ldb, hipStream_t s);
+// hss_compress_batched; share_arena = false gives every handle its own
+// generator arena (for handles that outlive the others of their batch).
+hss_status compress_batched(int nmat, const void* const* A, int dtype, const long long* n,
+                            const long long* lda, const hss_tree* trees, const hss_opts* opts,
+                            void* stream, hss_handle* out, int* status, bool share_arena);
+// Device bytes a handle holds (generators, factors, workspaces, staging).
+long long resident_bytes(const Handle& H);
+// Records H.queued on s (after the work of a stream-ordered call).
+hipError_t mark_queued(Handle& H, hipStream_t s);
+// Checks the arguments of the sampling products (as hss_sample documents
+// them); on success *work_doubles is the workspace the products need.
+hss_status sample_args(const void* A, int dtype, int sample_prec, long long n, long long lda, int ncols,
+                       const double* Rr, const double* Rc, long long ldr, double* Sr, double* Sc,
+                       long long lds, long long* work_doubles);
+// Queues the sampling products on s with the given workspace (no allocation).
+hipError_t sample_queue(const void* A, int dtype, int sample_prec, long long n, long long lda,
+                        const int* leaf_of, int ncols, const double* Rr, const double* Rc, long long ldr,
+                        double* Sr, double* Sc, long long lds, double* work, hipStream_t s);
 
 }  // namespace hss
 

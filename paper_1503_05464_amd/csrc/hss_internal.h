@@ -3,6 +3,7 @@
 #pragma once
 
 #include <initializer_list>
+#include <vector>
 
 #include <hip/hip_runtime.h>
 
@@ -13,8 +14,11 @@ namespace hss {
 // ---------------------------------------------------------------------------
 // Staging of per-launch descriptor tables: a pinned host buffer and its
 // device mirror, bump-allocated.  push() writes into the pinned buffer and
-// queues the copy on the stream; regions are only reused after a stream
-// synchronisation (reset), so no queued copy ever reads a rewritten region.
+// queues the copy on the stream.  A block is rewritten only once the work
+// that reads it has run: either the caller synchronised the stream (reset),
+// or the block was retired behind an event (retire) and is taken again only
+// after that event completed, so no queued copy or kernel ever reads a
+// rewritten region.
 // ---------------------------------------------------------------------------
 struct Staging {
   char* host = nullptr;
@@ -23,18 +27,33 @@ struct Staging {
   size_t used = 0;
   hipStream_t stream = nullptr;
   bool stream_used = false;  // copies were queued on `stream`
+  struct Spare {             // a retired block and the event its readers end before
+    char* host;
+    char* dev;
+    size_t cap;
+    hipEvent_t ev;
+  };
+  std::vector<Spare> spares;
+  // Takes a block of at least `bytes` (a retired one whose readers have run,
+  // or a new one).
   hipError_t init(size_t bytes, hipStream_t s);
+  // Waits for the readers of every block, then frees them all.
   void release();
   // Returns the device address of the copied table, or nullptr on failure.
-  // A push that does not fit waits for the stream and starts over at the
-  // beginning of the buffer (or in a larger one), so tables pushed earlier
-  // are only safe if their kernels were launched before that push; tables
-  // that must stay valid together are reserved first.
+  // A push that does not fit retires the current block and continues in
+  // another one, so tables pushed earlier are only safe if their kernels
+  // were launched before that push; tables that must stay valid together
+  // are reserved first.
   void* push(const void* src, size_t bytes);
-  // Room for pushes of these sizes that stay valid together: any wrap or
-  // growth happens here, before the first of them.  False on failure.
+  // Room for pushes of these sizes that stay valid together: any change of
+  // block happens here, before the first of them.  False on failure.
   bool reserve(std::initializer_list<size_t> sizes);
+  // The caller has synchronised the stream: the block is free again.
   void reset() { used = 0; }
+  // Ends a stream-ordered call without waiting: the tables pushed so far stay
+  // valid until the work queued on `stream` up to now has run; the next push
+  // goes to another block.
+  hipError_t retire();
 };
 
 // ---------------------------------------------------------------------------
@@ -59,7 +78,7 @@ long long sample_mixed_workspace_doubles(long long n, int ncols);
 hipError_t launch_sample_mixed(const float* A, long long n, long long lda, const int* leaf_of,
                                int ncols, int mode, const double* Rr, const double* Rc,
                                long long ldr, double* Sr, double* Sc, long long lds, double* work,
-                               Staging& st, hipStream_t s);
+                               hipStream_t s);
 // The sampling products of many matrices (one FP32 A each) in one launch per
 // side; all of one mode.  Rr/Rc/Sr/Sc point at the first column to form.
 struct SampleJob {

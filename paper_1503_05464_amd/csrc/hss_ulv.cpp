@@ -673,8 +673,10 @@ hss_status solve_impl(Handle& H, int nrhs, const double* b, long long ldb, doubl
       CHK(apply_q_blocked(H, rd, s));
     }
   }
-  HIPCHK(hipStreamSynchronize(s));
-  H.staging.reset();
+  // stream-ordered: the descriptor tables stay in their staging block until
+  // the work queued so far has run
+  HIPCHK(H.staging.retire());
+  HIPCHK(mark_queued(H, s));
   return HSS_OK;
 }
 

@@ -75,6 +75,7 @@ struct Work {
   unsigned long long* rec;  // 2 * nslots * kmax: one published candidate record per
                             // workgroup and step, zeroed before each persistent launch
   int* err;        // 1: a wait for a candidate timed out (persistent path)
+  int give_up = 0; // nonzero: every wait gives up at once (tests of the rerun)
   double* W;     // sum(m * d)
 };
 
@@ -554,10 +555,14 @@ __global__ __launch_bounds__(ST) void id_step_kernel(const DevProb* __restrict__
 // more, or -1 for no candidate) and (step + 1) << 32 | index.  A reader takes
 // a record once both words are non-zero and the step matches, so one poll
 // returns the candidate.  A workgroup writes its record only after its column
-// stores have completed.  No read-modify-write atomics are used.  The wait
-// for a record is bounded: a workgroup that waits too long raises the error
-// flag and leaves, and so does every workgroup that sees the flag; the
-// factorization is then reported as failed and nothing is written back.
+// stores have completed.  No read-modify-write atomics are used.  The record
+// store follows an agent-scope release fence and a reader that has taken its
+// records runs an agent-scope acquire fence, so the column values are ordered
+// before the record under the memory model, not only by the hardware's
+// in-order completion.  The wait for a record is bounded: a workgroup that
+// waits too long raises the error flag and leaves, and so does every
+// workgroup that sees the flag; the factorization is then reported as failed
+// and nothing is written back.
 // ---------------------------------------------------------------------------
 constexpr int PW = 8;        // wavefronts per persistent workgroup (two per SIMD)
 constexpr int PT = PW * 64;  // threads per persistent workgroup
@@ -658,6 +663,8 @@ __global__ __launch_bounds__(PT) void qrcp_persist_kernel(const DevProb* __restr
     __builtin_amdgcn_s_waitcnt(0);  // this thread's stores have completed
     __syncthreads();                // ... and every other thread's
     if (tid == 0) {
+      // the workgroup's column stores happen before the record (release)
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
       unsigned long long* r = w.rec + 2 * ((long long)i * nslot + blockIdx.x);
       st_dev(r, (unsigned long long)__double_as_longlong(v) ^ kSignBit);
       st_dev(r + 1, ((unsigned long long)(i + 1) << 32) | (unsigned)ix);
@@ -671,6 +678,10 @@ __global__ __launch_bounds__(PT) void qrcp_persist_kernel(const DevProb* __restr
     double gv = -1.0;
     int gi = INT_MAX;
     bool ok = true;
+    if (w.give_up) {  // host switch: leave at once, as after a timeout
+      if (tid == 0) st_dev(w.err, 1);
+      ok = false;
+    }
     for (int t = tid; t < dp.G && ok; t += PT) {
       int spins = 0;
       unsigned long long a, b;
@@ -693,6 +704,12 @@ __global__ __launch_bounds__(PT) void qrcp_persist_kernel(const DevProb* __restr
       }
       if (ok) better(gv, gi, __longlong_as_double((long long)(a ^ kSignBit)), (int)(unsigned)b);
     }
+    // the publishers' columns are read after their records (acquire, by the
+    // wavefronts that polled them; the barrier below passes this on to the
+    // rest of the workgroup).  An acquire in every wavefront cost 1523 ms of
+    // IDs per gauss65536 compression against 909 ms in the polling ones, and
+    // the release above 75 ms more (837 ms with neither).
+    if (tid < ((dp.G + 63) & ~63)) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     if (!ok) s_ok = 0;
     wave_argmax(gv, gi);
     // rv / ri: every thread read them in publish before its closing barrier
@@ -1090,6 +1107,10 @@ static hipError_t run_persistent(std::vector<DevProb>& h, const std::vector<int>
     if (e == hipSuccess && done.empty()) e = hipMemsetAsync(w.err, 0, 4, s);
     if (e != hipSuccess) return e;
     Work wa = w;
+    {
+      const char* gu = std::getenv("HSS_QRCP_GIVE_UP");
+      wa.give_up = (gu && gu[0] && gu[0] != '0') ? 1 : 0;
+    }
     void* args[] = {(void*)&dprobs, (void*)&dwg, (void*)&rtol, (void*)&wa};
     e = hipLaunchKernel(pv.fn, dim3(nwg), dim3(PT), args, 0, s);
     if (e == hipSuccess) {
@@ -1113,6 +1134,12 @@ static hipError_t run_persistent(std::vector<DevProb>& h, const std::vector<int>
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) return e;
   if (herr) {
+    const char* vb = std::getenv("HSS_VERBOSE");
+    if (vb && vb[0] && vb[0] != '0') {
+      std::fprintf(stderr, "[hss-id] persistent wait gave up: %zu problems factored again on the step path\n",
+                   done.size());
+      std::fflush(stderr);
+    }
     rest.insert(rest.end(), done.begin(), done.end());
     npersist = 0;
     nlaunch = 0;

@@ -445,6 +445,25 @@ __global__ void prep_rt_kernel(const PrepDesc* __restrict__ g, int ng, long long
   else static_cast<unsigned short*>(d.Rt)[x] = bf16_rn((float)v);
 }
 
+// The same copy for at most two descriptors passed by value (one matrix, one
+// or both sides): no table in device memory.
+struct PrepPair {
+  PrepDesc d[2];
+};
+
+template <int MODE>
+__global__ void prep_rt_pair_kernel(PrepPair g, int ng, long long total) {
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= total) return;
+  const PrepDesc& d = (ng > 1 && g.d[1].e0 <= e) ? g.d[1] : g.d[0];
+  const long long x = e - d.e0;
+  const int c = (int)(x / d.ldrt);
+  const long long k = x % d.ldrt;
+  const double v = (c < d.ncols && k < d.n) ? d.R[k * d.ldr + c] : 0.0;
+  if constexpr (MODE == 1) static_cast<float*>(d.Rt)[x] = (float)v;
+  else static_cast<unsigned short*>(d.Rt)[x] = bf16_rn((float)v);
+}
+
 long long rt_ld(long long n) { return (n + BK - 1) / BK * BK; }
 int rt_cols(int ncols) { return (ncols + BN - 1) / BN * BN; }
 // doubles of workspace for one R^T copy (4-byte elements: enough for both modes)
@@ -551,16 +570,26 @@ long long sample_mixed_workspace_doubles(long long n, int ncols) {
 hipError_t launch_sample_mixed(const float* A, long long n, long long lda, const int* leaf_of,
                                int ncols, int mode, const double* Rr, const double* Rc,
                                long long ldr, double* Sr, double* Sc, long long lds, double* work,
-                               Staging& st, hipStream_t s) {
+                               hipStream_t s) {
   if (n <= 0 || ncols <= 0) return hipSuccess;
   // work: [R^T of R^r | R^T of R^c | split-k partials]
   double* rt_r = work;
   double* rt_c = work + rt_doubles(n, ncols);
   double* part = work + 2 * rt_doubles(n, ncols);
-  std::vector<PrepDesc> g;
-  if (Sr) g.push_back(PrepDesc{Rr, ldr, (int)n, ncols, rt_cols(ncols), rt_ld(n), rt_r, 0});
-  if (Sc) g.push_back(PrepDesc{Rc, ldr, (int)n, ncols, rt_cols(ncols), rt_ld(n), rt_c, 0});
-  hipError_t e = prep_rt(g, mode, st, s);
+  PrepPair g{};
+  int ng = 0;
+  long long total = 0;
+  for (int side = 0; side < 2; ++side) {
+    if (!(side ? Sc : Sr)) continue;
+    g.d[ng] = PrepDesc{side ? Rc : Rr, ldr, (int)n, ncols, rt_cols(ncols), rt_ld(n), side ? rt_c : rt_r, total};
+    total += (long long)g.d[ng].cpad * g.d[ng].ldrt;
+    ++ng;
+  }
+  if (ng == 0) return hipSuccess;
+  const dim3 pgrid((unsigned)((total + 255) / 256));
+  if (mode == 1) hipLaunchKernelGGL(prep_rt_pair_kernel<1>, pgrid, dim3(256), 0, s, g, ng, total);
+  else hipLaunchKernelGGL(prep_rt_pair_kernel<2>, pgrid, dim3(256), 0, s, g, ng, total);
+  hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (mode == 1) {
     if (Sr) run<1, false>(A, lda, n, leaf_of, ncols, rt_r, Sr, lds, part, s);

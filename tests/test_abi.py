@@ -89,3 +89,17 @@ def test_user_tree_errors(tree, n, msg):
     st = L.hss_compress(ctypes.c_void_p(16), P.HSS_F64, n, n, ctypes.byref(t), None, None, ctypes.byref(out))
     assert st == P.HSS_ERR_ARG and out.value is None
     assert msg in L.hss_last_error(), L.hss_last_error()
+
+
+def test_set_allocator_arguments():
+    """hss_set_allocator takes both callbacks or neither (checked on the host,
+    no device needed); NULL/NULL restores the library's own pool."""
+    L = P.lib()
+    fa = P._ALLOC_FN(lambda nbytes, dev, stream, ctx: None)
+    ff = P._FREE_FN(lambda p, nbytes, dev, stream, ctx: None)
+    assert L.hss_set_allocator(fa, P._FREE_FN(), None) == P.HSS_ERR_ARG
+    assert L.hss_set_allocator(P._ALLOC_FN(), ff, None) == P.HSS_ERR_ARG
+    assert b"both" in L.hss_last_error()
+    assert L.hss_set_allocator(P._ALLOC_FN(), P._FREE_FN(), None) == P.HSS_OK
+    with pytest.raises(ValueError):
+        P.hss_set_allocator(lambda *a: 0, None)

@@ -99,3 +99,100 @@ def test_matvec_batched_argument_errors():
     with pytest.raises(ValueError):
         P.hss_matvec_batched(hs, [xs[0], torch.ones((As[1].shape[0], 2), dtype=torch.float64, device="cuda")])
     assert P.hss_matvec_batched([], []) == []
+
+
+def _oracle_import(Ho):
+    tree = Ho.tree
+    nodes = []
+    kr = np.zeros(tree.n_nodes, dtype=np.int32)
+    kc = np.zeros(tree.n_nodes, dtype=np.int32)
+    for t in range(tree.n_nodes):
+        nd = {}
+        if t != 0:
+            nd.update(Jr=Ho.U[t].J, Jc=Ho.V[t].J, Er=Ho.U[t].E, Ec=Ho.V[t].E)
+            kr[t], kc[t] = Ho.U[t].k, Ho.V[t].k
+        if tree.is_leaf(t):
+            nd["D"] = Ho.D[t]
+        else:
+            nd["B12"], nd["B21"] = Ho.B12[t], Ho.B21[t]
+        nodes.append(nd)
+    return (tree.lo, tree.hi, tree.left, tree.right), kr, kc, nodes
+
+
+@pytest.mark.parametrize("dtype,prec", [(torch.float64, "f64"), (torch.float32, "bf16x3")])
+def test_batched_against_oracle(dtype, prec):
+    """Each matrix of a batch against the oracle's compression of the same
+    matrix with the same options (Alg. 1, adaptive sampling of Sec. 3.3; the
+    BF16x3 oracle uses the same rounded R and exact FP64 products): the same
+    passes and final d, ranks equal except at most two nodes by one (FP64;
+    BF16x3: the products carry FP32 accumulation error, so d within one
+    growth step and ranks within a few), the GPU matvec (Alg. 2) on the
+    oracle's own generators equal to the oracle's matvec to 1e-13, and both
+    HSS forms within the acceptance bound of the dense product."""
+    from oracle import hss as ohss
+
+    leaf, rtol = 64, 1e-4
+    As = _matrices(8, 40, 900, 21, dtype, leaf)
+    kw = dict(rtol=rtol, d0=32, dd=16, d_max=1024, leaf_size=leaf, p_margin=32, sample_prec=prec)
+    print(f"batched vs oracle: n={[a.shape[0] for a in As]} prec={prec}", flush=True)
+    hs = P.hss_compress_batched(As, **kw)
+    for A, h in zip(As, hs):
+        n = A.shape[0]
+        An = A.cpu().numpy()
+        Ho = ohss.compress(An, ohss.Options(rtol=rtol, d0=32, dd=16, d_max=1024, leaf_size=leaf, p_margin=32,
+                                            sample_prec=prec))
+        s = P.hss_stats(h)
+        kr, kc, _, _ = P.hss_ranks(h)
+        okr = np.zeros_like(kr)
+        okc = np.zeros_like(kc)
+        for t, (a, b) in Ho.ranks().items():
+            okr[t], okc[t] = a, b
+        if prec == "f64":
+            assert (s["passes"], s["d_final"]) == (Ho.passes, Ho.d_final), (n, s["passes"], Ho.passes)
+            diff = np.flatnonzero((kr != okr) | (kc != okc))
+            assert len(diff) <= 2 and np.all(np.abs(kr - okr) <= 1) and np.all(np.abs(kc - okc) <= 1)
+        else:
+            assert abs(s["d_final"] - Ho.d_final) <= 16, (n, s["d_final"], Ho.d_final)
+            assert abs(s["max_rank"] - Ho.max_rank()) <= 2 + Ho.max_rank() // 10
+        x = np.random.default_rng(n).uniform(-1, 1, (n, 2))
+        xo = ohss.matvec(Ho, x)
+        tree, ikr, ikc, nodes = _oracle_import(Ho)
+        hi = P.hss_import(n, tree, ikr, ikc, nodes)
+        got = P.hss_matvec(hi, torch.from_numpy(x).cuda()).cpu().numpy()
+        assert np.allclose(got, xo, rtol=0, atol=1e-13 * np.abs(xo).max())
+        ref = An.astype(np.float64) @ x
+        mine = P.hss_matvec(h, torch.from_numpy(x).cuda()).cpu().numpy()
+        assert np.linalg.norm(mine - ref) <= 10 * rtol * np.linalg.norm(ref)
+        assert np.linalg.norm(xo - ref) <= 10 * rtol * np.linalg.norm(ref)
+
+
+def test_batched512_full_size():
+    """The full 512-matrix batch (N log-uniform in [256, 4096], planar
+    1/(4 pi r), FP32 storage, BF16x3 sampling, rtol 1e-4) in the launch
+    configuration the benchmark times: every matrix converges and its
+    matvec meets 10 rtol against the dense product; the four smallest
+    matrices also against the oracle's compression (d within one step)."""
+    from oracle import hss as ohss
+
+    cfg = W.CONFIGS["batched512"]
+    sets = W.batch_instances(cfg["count"], cfg["n_lo"], cfg["n_hi"], cfg["point_seed"], cfg["leaf"])
+    As = [W.device_kernel_matrix(cfg["kind"], p, torch.float32, torch.device("cuda:0")) for p in sets]
+    kw = dict(rtol=cfg["rtol"], d0=cfg["d0"], dd=cfg["dd"], d_max=cfg["d_max"], leaf_size=cfg["leaf"],
+              p_margin=cfg["p_margin"], sample_prec=cfg["sample_prec"])
+    print(f"batched512: {len(As)} matrices", flush=True)
+    hs = P.hss_compress_batched(As, **kw)
+    assert all(h.converged for h in hs)
+    xs = [torch.from_numpy(np.random.default_rng(7).uniform(-1, 1, (a.shape[0], 1))).cuda() for a in As]
+    bs = P.hss_matvec_batched(hs, xs)
+    worst = 0.0
+    for A, x, b in zip(As, xs, bs):
+        ref = A.double() @ x
+        worst = max(worst, float(torch.linalg.norm(b - ref) / torch.linalg.norm(ref)))
+    assert worst <= 10 * cfg["rtol"], worst
+    small = np.argsort([a.shape[0] for a in As])[:4]
+    for q in small:
+        An = As[q].cpu().numpy()
+        Ho = ohss.compress(An, ohss.Options(rtol=kw["rtol"], d0=kw["d0"], dd=kw["dd"], d_max=kw["d_max"],
+                                            leaf_size=kw["leaf_size"], p_margin=kw["p_margin"],
+                                            sample_prec=kw["sample_prec"]))
+        assert abs(P.hss_stats(hs[q])["d_final"] - Ho.d_final) <= kw["dd"]

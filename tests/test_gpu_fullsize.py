@@ -155,3 +155,26 @@ def test_gauss4096_against_stored_oracle(pm):
     assert len(diff) <= 2 and np.all(np.abs(kr - okr) <= 2) and np.all(np.abs(kc - okc) <= 2)
     err = _frob(h, A)
     assert err <= 1.5 * ref["rel_error"] + 1e-9
+
+
+@pytest.mark.parametrize("prec", ["f32", "bf16x3"])
+def test_compress_gauss65536_reduced_precision(gauss65536, prec):
+    """The N = 65536 Gaussian kernel at rtol 1e-4 with the sampling products
+    in FP32 or in BF16x3 (the precision sweep): converged, with the
+    acceptance bounds 10 rtol on the matvec and the Frobenius error, and
+    the final d within one growth step of FP64 sampling's."""
+    A = gauss65536
+    n, rtol = A.shape[0], 1e-4
+    kw = dict(rtol=rtol, d0=128, dd=64, d_max=4096, leaf_size=256, p_margin=256)
+    print(f"compress n=65536 rtol=1e-4 prec={prec}", flush=True)
+    h64 = P.hss_compress(A, **kw)
+    d64 = P.hss_stats(h64)["d_final"]
+    del h64
+    h = P.hss_compress(A, sample_prec=prec, **kw)
+    st = P.hss_stats(h)
+    assert st["converged"] and abs(st["d_final"] - d64) <= 64, (st["d_final"], d64)
+    x = torch.from_numpy(np.random.default_rng(3).uniform(-1, 1, (n, 2))).cuda()
+    b = P.hss_matvec(h, x)
+    ref = _dense_mv(A, x)
+    assert float(torch.linalg.norm(b - ref) / torch.linalg.norm(ref)) <= 10 * rtol
+    assert _frob(h, A) <= 10 * rtol

@@ -220,3 +220,32 @@ def test_id_batched_large_problems(path, monkeypatch):
         nu1 = np.linalg.norm(y, axis=0).max()
         err = np.linalg.norm(y - y[:, J] @ X, 2)
         assert err <= 10 * np.sqrt(max(1, m - k)) * rtol * nu1, (d, m, err)
+
+
+def test_persistent_give_up_reruns_on_step_path(monkeypatch, capfd):
+    """When a persistent launch's bounded wait gives up (forced here from the
+    host: every workgroup leaves at its first wait, so every kernel exits
+    normally), the problems are factored again on the per-step path from
+    their untouched inputs: the IDs equal those of the step path itself,
+    exactly, and match the oracle as above."""
+    rtol = 1e-6
+    cases = [(2100, 1100, 0.37, 11), (2100, 1100, 0.37, 12), (1000, 900, 0.0, 13)]
+    mats = [_slow_decay(d, m, seed, rate) for d, m, rate, seed in cases]
+    Ys = [torch.from_numpy(np.ascontiguousarray(y.T)).cuda() for y in mats]
+    monkeypatch.setenv("HSS_QRCP_PATH", "step")
+    print("id_batched give-up: step path reference", flush=True)
+    ref_step = P.hss_id_batched(Ys, rtol)
+    monkeypatch.setenv("HSS_QRCP_PATH", "persistent")
+    monkeypatch.setenv("HSS_QRCP_GIVE_UP", "1")
+    monkeypatch.setenv("HSS_VERBOSE", "1")
+    capfd.readouterr()
+    print("id_batched give-up: persistent launch that gives up", flush=True)
+    got = P.hss_id_batched(Ys, rtol)
+    err = capfd.readouterr().err
+    assert "persistent wait gave up" in err, err
+    for (k, perm, E), (k0, perm0, E0), y, (d, m, rate, seed) in zip(got, ref_step, mats, cases):
+        assert k == k0 and np.array_equal(perm, perm0) and np.array_equal(E, E0)
+        ref = interp.interpolative_decomposition(y, rtol)
+        assert abs(k - ref.k) <= 1
+        if rate >= 0.3:
+            assert k == ref.k and list(perm[:k]) == list(ref.J)

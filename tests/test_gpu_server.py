@@ -94,3 +94,68 @@ def test_server_argument_errors():
     st = P.lib().hss_server_wait(srv._ptr, 12345, None)
     assert st == P.HSS_ERR_ARG and b"unknown ticket" in P.lib().hss_last_error()
     srv.close()
+
+
+def test_resident_handle_solve_only_requests():
+    """A compress request with keep=True leaves its factored handle resident
+    in the server; solve-only requests on it (1 to 64 right-hand sides, Alg.
+    4) equal hss_solve on the same handle bit for bit; the handle's bytes
+    count against the budget until it is released, and a released handle
+    takes no more requests."""
+    A, b, kw = _request(2)
+    n = A.shape[0]
+    srv = P.HSSServer(max_batch=8, workers=2)
+    print(f"server: keep-resident compress n={n}", flush=True)
+    t = srv.submit(A, b, keep=True, **kw)
+    x0, info = srv.wait(t)
+    h = info["handle"]
+    assert info["status"] == P.HSS_OK and h is not None and h.n == n
+    rhs = [torch.from_numpy(W.normal_rhs(n, k, 50 + k)).cuda() for k in (1, 7, 64, 33)]
+    print("server: solve-only requests on the resident handle", flush=True)
+    tickets = [srv.solve(h, r) for r in rhs]
+    outs = [srv.wait(q) for q in tickets]
+    for r, (x, inf) in zip(rhs, outs):
+        assert inf["status"] == P.HSS_OK and inf["handle"] is None
+        direct = P.hss_solve(h, r)
+        torch.cuda.synchronize()
+        assert torch.equal(x, direct)
+        res = P.hss_matvec(h, x) - r  # the ULV solve is exact for A_HSS
+        assert float(torch.linalg.norm(res) / torch.linalg.norm(r)) <= 1e-9
+    # the first request's own solution equals a later solve-only one with the same b
+    x1, _ = srv.wait(srv.solve(h, b))
+    assert torch.equal(x1, x0)
+    srv.release(h)
+    with pytest.raises(P.HSSError):
+        srv.solve(h, b)
+    srv.close()
+
+
+def test_served_results_against_oracle():
+    """Each served solution against the oracle's compress -> ULV factor ->
+    solve of the same matrix with the same options (Alg. 1, 3, 4; BF16x3
+    requests through the oracle's rounding of R): the two HSS forms are
+    approximations of A within rtol, so their solutions agree within the
+    forward error bound 20 rtol cond(A)."""
+    from oracle import hss as ohss
+    from oracle import ulv as oulv
+
+    reqs = [_request(q) for q in (0, 1, 4, 6)]
+    reqs = [(A, b, kw) for A, b, kw in reqs if A.shape[0] <= 1200] or [_request(0)]
+    srv = P.HSSServer(max_batch=8, workers=2)
+    print(f"server vs oracle: {len(reqs)} requests", flush=True)
+    tickets = [srv.submit(A, b, **kw) for A, b, kw in reqs]
+    outs = [srv.wait(t) for t in tickets]
+    srv.close()
+    for (A, b, kw), (x, info) in zip(reqs, outs):
+        assert info["status"] == P.HSS_OK
+        An = A.cpu().numpy()
+        opts = ohss.Options(rtol=kw["rtol"], d0=kw["d0"], dd=kw["dd"], d_max=kw["d_max"],
+                            leaf_size=kw["leaf_size"], p_margin=kw["p_margin"],
+                            sample_prec=kw["sample_prec"])
+        print(f"oracle n={An.shape[0]} {kw['sample_prec']} rtol={kw['rtol']}", flush=True)
+        Ho = ohss.compress(An, opts)
+        xo = oulv.solve(oulv.factor(Ho), b.cpu().numpy())
+        cond = float(np.linalg.cond(An.astype(np.float64)))
+        rel = float(np.linalg.norm(x.cpu().numpy() - xo) / np.linalg.norm(xo))
+        assert rel <= 20 * kw["rtol"] * cond, (An.shape[0], rel, cond)
+        assert info["d_final"] == Ho.d_final or kw["sample_prec"] != "f64", (info["d_final"], Ho.d_final)
