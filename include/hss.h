@@ -462,6 +462,25 @@ hss_status hss_sample(const void* A, int dtype, int sample_prec, long long n, lo
                       long long ldr, double* Sr, double* Sc, long long lds, void* stream);
 
 /*
+ * hss_sample for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation.  Same
+ * arguments, same kernels and the same bits as hss_sample; the caller passes
+ * the inputs and outputs, and the workspace comes from one fixed array of
+ * 2^24 doubles (128 MiB) of device memory that the library holds on each
+ * device it runs on until the process ends.  The call allocates nothing (no
+ * hipMalloc, hipFree, pool or pinned staging).  Sizes whose workspace exceeds
+ * the array (FP64: split-K partials of n x ncols per split; reduced modes:
+ * also two n x ncols copies of R) return HSS_ERR_ARG with the needed size;
+ * n = 65536 with 64 columns fits in every precision.  Stream-ordered.  Every
+ * call on one device shares that array: calls that overlap on one device
+ * (on different streams, or from different threads) race and give wrong
+ * results; calls ordered on one stream are safe.
+ */
+hss_status hss_sample_noalloc(const void* A, int dtype, int sample_prec, long long n, long long lda,
+                              const int* leaf_of, int ncols, const double* Rr, const double* Rc,
+                              long long ldr, double* Sr, double* Sc, long long lds, void* stream);
+
+/*
  * Batched interpolative decompositions (Sec. 2.2, Sec. 3.2).  Problem p
  * takes the rows of a DEVICE matrix Y_p^T (m[p] rows, d[p] columns, leading
  * dimension ldy[p], pointer ys[p]) -- i.e. Y_p is d x m and its columns are

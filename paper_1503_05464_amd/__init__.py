@@ -39,7 +39,7 @@ EXPORTED = [
     "hss_solve", "hss_stats",
     "hss_ranks", "hss_export_node", "hss_import", "hss_destroy", "hss_release_cached_memory",
     "hss_set_allocator", "hss_last_error",
-    "hss_random_normal", "hss_sample", "hss_id_batched",
+    "hss_random_normal", "hss_sample", "hss_sample_noalloc", "hss_id_batched",
     "hss_server_default_opts", "hss_server_create", "hss_server_submit", "hss_server_submit_request",
     "hss_server_wait", "hss_server_release", "hss_server_destroy",
 ]
@@ -147,6 +147,7 @@ def lib() -> C.CDLL:
         L.hss_set_allocator.argtypes = [_ALLOC_FN, _FREE_FN, vp]
         L.hss_random_normal.argtypes = [C.c_ulonglong, i, ll, i, i, i, vp, ll, vp]
         L.hss_sample.argtypes = [vp, i, i, ll, ll, vp, i, vp, vp, ll, vp, vp, ll, vp]
+        L.hss_sample_noalloc.argtypes = [vp, i, i, ll, ll, vp, i, vp, vp, ll, vp, vp, ll, vp]
         L.hss_id_batched.argtypes = [i, vp, vp, vp, vp, d, vp, vp, vp, vp]
         for f in EXPORTED:
             if f not in ("hss_default_opts", "hss_destroy", "hss_last_error", "hss_server_default_opts",
@@ -507,6 +508,28 @@ def hss_sample(A, Rr=None, Rc=None, leaf_of=None, stream=None, sample_prec: str 
                             _ptr(Rr) if Rr is not None else None, _ptr(Rc) if Rc is not None else None,
                             R.stride(0), _ptr(Sr) if Sr is not None else None,
                             _ptr(Sc) if Sc is not None else None, S.stride(0), _stream(stream)))
+    return Sr, Sc
+
+
+def hss_sample_noalloc(A, Rr, Rc, Sr, Sc, leaf_of=None, stream=None, sample_prec: str = "f64"):
+    """hss_sample into caller-provided outputs Sr, Sc (CUDA float64, n x
+    ncols, or None together with their R) with the library's fixed scratch
+    as workspace: the call allocates no device memory.  Returns (Sr, Sc)."""
+    import torch
+
+    dt = {torch.float64: HSS_F64, torch.float32: HSS_F32}[A.dtype]
+    R = Rr if Rr is not None else Rc
+    S = Sr if Sr is not None else Sc
+    if Rr is not None and Rc is not None and Rr.stride(0) != Rc.stride(0):
+        raise ValueError("Rr and Rc must share a leading dimension")
+    if Sr is not None and Sc is not None and Sr.stride(0) != Sc.stride(0):
+        raise ValueError("Sr and Sc must share a leading dimension")
+    _check(lib().hss_sample_noalloc(_ptr(A), dt, _PREC[sample_prec], A.shape[0], A.stride(0),
+                                    _ptr(leaf_of) if leaf_of is not None else None, R.shape[1],
+                                    _ptr(Rr) if Rr is not None else None,
+                                    _ptr(Rc) if Rc is not None else None, R.stride(0),
+                                    _ptr(Sr) if Sr is not None else None,
+                                    _ptr(Sc) if Sc is not None else None, S.stride(0), _stream(stream)))
     return Sr, Sc
 
 
