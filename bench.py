@@ -372,6 +372,7 @@ def serve_measure(nreq: int, rate: float, workers: int, budget_frac: float = 0.8
     # the served solutions themselves: the last request on each pool matrix
     worst_bwd, worst_rel_bound, worst_alone = 0.0, 0.0, 0.0
     checked = 0
+    detail = []
     for q in sorted(set(pick.tolist())):
         i = int(np.flatnonzero(pick == q)[-1])
         A = pool[q].double()
@@ -385,6 +386,8 @@ def serve_measure(nreq: int, rate: float, workers: int, budget_frac: float = 0.8
         bwd = float(torch.linalg.norm(r)) / (anorm * float(torch.linalg.norm(x)))
         worst_bwd = max(worst_bwd, bwd)
         worst_rel_bound = max(worst_rel_bound, bwd / (10 * float(rtols[i])))
+        detail.append({"n": int(A.shape[0]), "kernel": "log" if kinds[q] == 0 else "gauss",
+                       "rtol": float(rtols[i]), "nrhs": int(nrhs[i]), "backward_error": bwd})
         h = P.hss_compress(pool[q], rtol=float(rtols[i]), **kw0)
         P.hss_factor(h)
         xa = P.hss_solve(h, rhs[i])
@@ -408,6 +411,7 @@ def serve_measure(nreq: int, rate: float, workers: int, budget_frac: float = 0.8
         "served_backward_error_max": worst_bwd,
         "served_backward_error_over_10rtol_max": round(worst_rel_bound, 4),
         "served_vs_alone_rel_max": worst_alone,
+        "served_checks": sorted(detail, key=lambda r: -r["backward_error"] / r["rtol"])[:4],
     }
 
 
@@ -437,7 +441,8 @@ def run_serve(args) -> int:
         },
         **{k: res[k] for k in ("latency_s", "throughput_req_s", "offered_req_s", "mean_batch", "failed",
                                "served_checked", "served_backward_error_max",
-                               "served_backward_error_over_10rtol_max", "served_vs_alone_rel_max")},
+                               "served_backward_error_over_10rtol_max", "served_vs_alone_rel_max",
+                               "served_checks")},
         "roofline": None,
         "cpu_baseline": None,
     }

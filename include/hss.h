@@ -481,6 +481,28 @@ hss_status hss_sample_noalloc(const void* A, int dtype, int sample_prec, long lo
                               long long ldr, double* Sr, double* Sc, long long lds, void* stream);
 
 /*
+ * Batched FP64 GEMMs C_p = alpha op(A_p) B_p + beta C_p, op(A) = A or A^T, in
+ * one launch of the kernel that runs the library's per-node products (local
+ * samples and R_tau of Alg. 1, the sweeps of Alg. 2, the ULV updates of Alg.
+ * 3/4).  For parity tests and for the tile autotuner.
+ *  M, N, K, lda, transA, ldb, ldc: host arrays of nprob entries.
+ *  A, B, C: host arrays of nprob DEVICE pointers, row-major: op(A_p) is
+ *           M x K (A_p is M x K with lda >= K, or K x M with lda >= M if
+ *           transA), B_p is K x N (ldb >= N), C_p is M x N (ldc >= N).  C_p
+ *           must not overlap A_p or B_p.
+ *  variant  tile shape 0 .. hss_gemm_variants()-1, or < 0 for the shape the
+ *           tuning table gives the batch's size class (what the library uses).
+ * Stream-ordered.  HSS_ERR_ARG for invalid sizes or a variant out of range.
+ */
+hss_status hss_gemm_batched(int nprob, const int* M, const int* N, const int* K, const double* const* A,
+                            const long long* lda, const int* transA, const double* const* B,
+                            const long long* ldb, double* const* C, const long long* ldc, double alpha,
+                            double beta, int variant, void* stream);
+
+/* Number of tile shapes of hss_gemm_batched. */
+int hss_gemm_variants(void);
+
+/*
  * Batched interpolative decompositions (Sec. 2.2, Sec. 3.2).  Problem p
  * takes the rows of a DEVICE matrix Y_p^T (m[p] rows, d[p] columns, leading
  * dimension ldy[p], pointer ys[p]) -- i.e. Y_p is d x m and its columns are

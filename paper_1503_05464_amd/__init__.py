@@ -39,7 +39,8 @@ EXPORTED = [
     "hss_solve", "hss_stats",
     "hss_ranks", "hss_export_node", "hss_import", "hss_destroy", "hss_release_cached_memory",
     "hss_set_allocator", "hss_last_error",
-    "hss_random_normal", "hss_sample", "hss_sample_noalloc", "hss_id_batched",
+    "hss_random_normal", "hss_sample", "hss_sample_noalloc", "hss_id_batched", "hss_gemm_batched",
+    "hss_gemm_variants",
     "hss_server_default_opts", "hss_server_create", "hss_server_submit", "hss_server_submit_request",
     "hss_server_wait", "hss_server_release", "hss_server_destroy",
 ]
@@ -149,9 +150,11 @@ def lib() -> C.CDLL:
         L.hss_sample.argtypes = [vp, i, i, ll, ll, vp, i, vp, vp, ll, vp, vp, ll, vp]
         L.hss_sample_noalloc.argtypes = [vp, i, i, ll, ll, vp, i, vp, vp, ll, vp, vp, ll, vp]
         L.hss_id_batched.argtypes = [i, vp, vp, vp, vp, d, vp, vp, vp, vp]
+        L.hss_gemm_batched.argtypes = [i, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, d, d, i, vp]
+        L.hss_gemm_variants.argtypes = []
         for f in EXPORTED:
             if f not in ("hss_default_opts", "hss_destroy", "hss_last_error", "hss_server_default_opts",
-                         "hss_server_destroy"):
+                         "hss_server_destroy", "hss_gemm_variants"):
                 getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -531,6 +534,41 @@ def hss_sample_noalloc(A, Rr, Rc, Sr, Sc, leaf_of=None, stream=None, sample_prec
                                     _ptr(Sr) if Sr is not None else None,
                                     _ptr(Sc) if Sc is not None else None, S.stride(0), _stream(stream)))
     return Sr, Sc
+
+
+def hss_gemm_variants() -> int:
+    return int(lib().hss_gemm_variants())
+
+
+def hss_gemm_batched(As, Bs, Cs, transA=None, alpha=1.0, beta=0.0, variant=-1, stream=None):
+    """C_p = alpha op(A_p) B_p + beta C_p for lists of CUDA float64 matrices
+    (row-major, unit column stride), in one launch of the library's batched
+    GEMM with tile shape `variant` (-1: the tuning table's choice).  Returns
+    Cs."""
+    nprob = len(As)
+    if not (len(Bs) == len(Cs) == nprob):
+        raise ValueError("one B and one C per A")
+    tr = [bool(t) for t in (transA or [False] * nprob)]
+    for a, b, c in zip(As, Bs, Cs):
+        for x in (a, b, c):
+            if x.dim() != 2 or not x.is_cuda or (x.numel() > 0 and x.stride(1) != 1):
+                raise ValueError("matrices must be 2-D CUDA tensors with unit column stride")
+    M = np.array([c.shape[0] for c in Cs], dtype=np.int32)
+    N = np.array([c.shape[1] for c in Cs], dtype=np.int32)
+    K = np.array([b.shape[0] for b in Bs], dtype=np.int32)
+    for q, (a, t) in enumerate(zip(As, tr)):
+        if (a.shape if not t else a.shape[::-1]) != (M[q], K[q]) or Bs[q].shape[1] != N[q]:
+            raise ValueError(f"problem {q}: shapes do not match")
+    ptr = lambda xs: np.array([x.data_ptr() for x in xs], dtype=np.uint64)
+    ld = lambda xs: np.array([max(1, x.shape[1]) if x.numel() == 0 else max(1, x.stride(0)) for x in xs],
+                            dtype=np.int64)
+    ap, bp, cp = ptr(As), ptr(Bs), ptr(Cs)
+    la, lb, lc = ld(As), ld(Bs), ld(Cs)
+    ta = np.array(tr, dtype=np.int32)
+    _check(lib().hss_gemm_batched(nprob, _np_ptr(M), _np_ptr(N), _np_ptr(K), _np_ptr(ap), _np_ptr(la),
+                                  _np_ptr(ta), _np_ptr(bp), _np_ptr(lb), _np_ptr(cp), _np_ptr(lc),
+                                  float(alpha), float(beta), int(variant), _stream(stream)))
+    return Cs
 
 
 def hss_id_batched(Ys, rtol: float, stream=None):

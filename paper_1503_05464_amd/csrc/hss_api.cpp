@@ -400,8 +400,9 @@ hipError_t Staging::init(size_t bytes, hipStream_t s) {
   used = 0;
   stream_used = false;
   // a retired block whose readers have run, or, with too many retired
-  // blocks, the oldest one once its readers have run
-  constexpr size_t kMaxSpares = 4;
+  // blocks (many stream-ordered calls queued and not yet run), the oldest
+  // one once its readers have run
+  constexpr size_t kMaxSpares = 32;
   for (size_t q = 0; q < spares.size(); ++q) {
     const bool last_try = spares.size() >= kMaxSpares && q == 0;
     if (spares[q].cap < b && !last_try) continue;
@@ -692,6 +693,9 @@ hss_status sample_batch(Handle& L, const std::vector<SampleReq>& reqs, EventTime
   if (reqs.empty()) return HSS_OK;
   const int ev0 = tm.begin();
   const int prec = L.opts.sample_prec;
+  // the new random columns of every matrix and side in one launch, rounded
+  // to the products' precision (used as such from here on)
+  std::vector<RngJob> rj;
   for (const SampleReq& q : reqs) {
     Handle& H = *q.H;
     const int c0 = q.c0, c1 = q.c1, nc = c1 - c0;
@@ -701,15 +705,16 @@ hss_status sample_batch(Handle& L, const std::vector<SampleReq>& reqs, EventTime
                               (size_t)nc * 8, H.n, hipMemcpyDeviceToDevice, L.stream));
       HIPCHK(hipMemcpy2DAsync(H.Rc + c0, H.ldg * 8, H.opts.R_user_c + c0, H.opts.ld_R_user * 8,
                               (size_t)nc * 8, H.n, hipMemcpyDeviceToDevice, L.stream));
+      if (prec != HSS_SAMPLE_F64) {
+        launch_round_r(H.Rr, H.ldg, H.n, c0, c1, prec, L.stream);
+        launch_round_r(H.Rc, H.ldg, H.n, c0, c1, prec, L.stream);
+      }
     } else {
-      launch_random_normal(H.opts.seed, 0, H.n, c0, c1, H.Rr + c0, H.ldg, L.stream);
-      launch_random_normal(H.opts.seed, 1, H.n, c0, c1, H.Rc + c0, H.ldg, L.stream);
-    }
-    if (prec != HSS_SAMPLE_F64) {  // R in the products' precision, used as such from here on
-      launch_round_r(H.Rr, H.ldg, H.n, c0, c1, prec, L.stream);
-      launch_round_r(H.Rc, H.ldg, H.n, c0, c1, prec, L.stream);
+      rj.push_back(RngJob{H.opts.seed, 0, H.n, c0, nc, H.Rr + c0, H.ldg});
+      rj.push_back(RngJob{H.opts.seed, 1, H.n, c0, nc, H.Rc + c0, H.ldg});
     }
   }
+  HIPCHK(launch_random_normal_batched(rj.data(), (int)rj.size(), prec, L.staging, L.stream));
   const int evg = tm.begin();
   if (prec != HSS_SAMPLE_F64 && reqs.size() > 1) {  // all matrices in one launch per side
     std::vector<SampleJob> jobs;
@@ -949,6 +954,7 @@ hss_status process_items(Handle& L, Arena& W, std::vector<Item>& items, EventTim
       p.E = rs ? v.Er : v.Ec;
       const int pm = it.H->opts.p_margin;
       p.kfail = (it.forced || it.d - pm < 0) ? -1 : it.d - pm;
+      p.partner = rs ? q + 1 : q - 1;  // the node fails if either side does (Sec. 3.3)
     }
     const size_t wb = id_workspace_bytes(pr.data(), np);
     void* wk = L.work_id.ensure(wb, L.stream);
@@ -2010,6 +2016,49 @@ hss_status hss_sample(const void* A, int dtype, int sample_prec, long long n, lo
   HIPCHK(e);
   return HSS_OK;
 }
+
+hss_status hss_gemm_batched(int nprob, const int* M, const int* N, const int* K, const double* const* A,
+                            const long long* lda, const int* transA, const double* const* B,
+                            const long long* ldb, double* const* C, const long long* ldc, double alpha,
+                            double beta, int variant, void* stream) {
+  g_err.clear();
+  if (nprob < 0 || (nprob > 0 && (!M || !N || !K || !A || !lda || !transA || !B || !ldb || !C || !ldc)))
+    return fail(HSS_ERR_ARG, "gemm arguments");
+  if (variant >= gemm_variants()) return fail(HSS_ERR_ARG, "gemm variant out of range");
+  std::vector<GemmDesc> gd(nprob);
+  for (int p = 0; p < nprob; ++p) {
+    if (M[p] < 0 || N[p] < 0 || K[p] < 0 || ldb[p] < N[p] || ldc[p] < N[p] ||
+        lda[p] < (transA[p] ? M[p] : K[p]))
+      return fail(HSS_ERR_ARG, "gemm problem " + std::to_string(p) + ": sizes");
+    if ((M[p] > 0 && N[p] > 0) && (!C[p] || (K[p] > 0 && (!A[p] || !B[p]))))
+      return fail(HSS_ERR_ARG, "gemm problem " + std::to_string(p) + ": NULL pointer");
+    GemmDesc& g = gd[p];
+    g.M = M[p];
+    g.N = N[p];
+    g.K = K[p];
+    g.A = A[p];
+    g.lda = lda[p];
+    g.transA = transA[p] ? 1 : 0;
+    g.B = Seg{B[p], nullptr, ldb[p], INT_MAX, nullptr};
+    g.C = Seg{C[p], nullptr, ldc[p], INT_MAX, nullptr};
+    g.D = SegOut{C[p], nullptr, ldc[p], INT_MAX, nullptr};
+    g.alpha = alpha;
+    g.beta = beta;
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  // descriptor tables: a process-wide staging area whose blocks are retired
+  // behind an event after each call (stream-ordered, no wait)
+  static std::mutex mu;
+  static Staging st;
+  std::lock_guard<std::mutex> lk(mu);
+  st.stream = s;
+  hipError_t e = launch_gemm_batched(gd.data(), nprob, st, s, variant);
+  if (e == hipSuccess) e = st.retire();
+  HIPCHK(e);
+  return HSS_OK;
+}
+
+int hss_gemm_variants(void) { return gemm_variants(); }
 
 hss_status hss_id_batched(int nprob, const double* const* ys, const int* m, const int* d,
                           const long long* ldy, double rtol, int* const* perms,

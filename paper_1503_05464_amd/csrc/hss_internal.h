@@ -61,6 +61,32 @@ struct Staging {
 // ---------------------------------------------------------------------------
 void launch_random_normal(unsigned long long seed, int which, long long n, int col0, int col1,
                           double* R, long long ld, hipStream_t s);
+// Columns col0..col0+ncol-1 of the random matrix `which` of one matrix, rows
+// 0..n-1, written from R (column col0 at R[0], leading dimension ld).
+struct RngJob {
+  unsigned long long seed;
+  int which;
+  long long n;
+  int col0, ncol;
+  double* R;
+  long long ld;
+};
+// Every job in one launch, each entry rounded to the sampling precision
+// `mode` (0 FP64, 1 FP32, 2 BF16) as launch_round_r rounds it.
+hipError_t launch_random_normal_batched(const RngJob* jobs, int njob, int mode, Staging& st,
+                                        hipStream_t s);
+
+// v rounded to nearest even to FP32 (mode 1) or to 8 significant bits, the
+// precision of BF16 (mode 2: the low 45 bits of the FP64 fraction rounded
+// away, a carry may bump the exponent); unchanged for mode 0.
+__device__ __forceinline__ double round_sample_prec(double v, int mode) {
+  if (mode == 1) return (double)(float)v;
+  if (mode != 2) return v;
+  unsigned long long u = (unsigned long long)__double_as_longlong(v);
+  u += 0x00000FFFFFFFFFFFull + ((u >> 45) & 1ull);
+  u &= ~0x00001FFFFFFFFFFFull;
+  return __longlong_as_double((long long)u);
+}
 
 // ---------------------------------------------------------------------------
 // Sampling products on FP64 MFMA (kernels_sample.hip)
@@ -136,8 +162,12 @@ struct GemmDesc {
   SegOut D;
   double alpha, beta;
 };
-// Runs all problems of `descs` (host array) in one launch.
-hipError_t launch_gemm_batched(const GemmDesc* descs, int nprob, Staging& st, hipStream_t s);
+// Runs all problems of `descs` (host array) in one launch, with the tile
+// shape `variant` (0 .. gemm_variants()-1) or, for variant < 0, the one the
+// tuning table gives the batch's size class.
+hipError_t launch_gemm_batched(const GemmDesc* descs, int nprob, Staging& st, hipStream_t s,
+                               int variant = -1);
+int gemm_variants();
 
 // ---------------------------------------------------------------------------
 // Batched interpolative decomposition (kernels_qrcp.hip)
@@ -155,6 +185,9 @@ struct IdProblem {
   int nfac;          // 0: pivoted ID; > 0: Householder QR without pivoting of
                      // columns 0..nfac-1, the other columns only transformed
   double* tau;       // no-pivot mode: nfac Householder scalars out
+  int partner = -1;  // the problem of the same node's other side, or -1: when
+                     // one side fails the rule (k > kfail, k < m) the node
+                     // fails, so the other side may be skipped (k = 0)
 };
 // Device workspace for a batch (carved by the launcher).
 size_t id_workspace_bytes(const IdProblem* probs, int nprob);

@@ -1002,19 +1002,27 @@ static int resident_workgroups(const void* fn) {
 // persistent launches (problems grouped while their workgroups fit on the
 // device at once: the grid never exceeds the resident capacity); the others
 // are returned in `rest`.
+// A problem fails the rule: rank above its kfail and below its row count.
+static bool fails_rule(const IdProblem& p, int k) { return p.kfail >= 0 && k > p.kfail && k < p.m; }
+
 static hipError_t run_persistent(std::vector<DevProb>& h, const std::vector<int>& large, double rtol,
                                  const Work& w, Staging& st, hipStream_t s, std::vector<int>& rest,
-                                 int& npersist, int& nlaunch) {
+                                 std::vector<char>& skipped, int& npersist, int& nlaunch) {
   int dmax = 0;
-  std::vector<int> cand;
+  std::vector<int> cand, second;
   for (int q : large) {
     const IdProblem& p = h[q].p;
     if (p.nfac > 0 || h[q].kmax == 0 || p.d > 64 * 40) rest.push_back(q);
     else {
-      cand.push_back(q);
+      // the first side of each node ahead of every second side: when the
+      // batch needs several launches, a node whose first side fails skips
+      // the launch of its second side
+      if (p.partner >= 0 && p.partner < q) second.push_back(q);
+      else cand.push_back(q);
       dmax = std::max(dmax, p.d);
     }
   }
+  cand.insert(cand.end(), second.begin(), second.end());
   if (cand.empty()) return hipSuccess;
   // HSS_QRCP_PATH = step | persistent forces a path; otherwise a cost model
   // picks one for the whole batch
@@ -1029,7 +1037,11 @@ static hipError_t run_persistent(std::vector<DevProb>& h, const std::vector<int>
   while (kPVariants[v].T * 64 < dmax) ++v;
   const PVariant& pv = kPVariants[v];
   const int cpg = PW * pv.C;
-  const int maxwg = (int)std::min<long long>(resident_workgroups(pv.fn), w.nslots);
+  int maxwg = (int)std::min<long long>(resident_workgroups(pv.fn), w.nslots);
+  if (const char* cap = std::getenv("HSS_QRCP_PERSIST_WG")) {  // tests: fewer workgroups per launch
+    const int c = std::atoi(cap);
+    if (c > 0) maxwg = std::min(maxwg, c);
+  }
   if (!force_pers) {
     // persistent: launches run one after another, each ~kPersistStepUs per
     // step; step path: one launch per step for the whole batch, bound by
@@ -1076,8 +1088,45 @@ static hipError_t run_persistent(std::vector<DevProb>& h, const std::vector<int>
   static std::mutex persist_mu;
   std::lock_guard<std::mutex> lock(persist_mu);
   std::vector<int> done;
+  std::vector<char> launched(h.size(), 0);
+  std::vector<int> kchk(h.size(), 0);
+  bool checked_all = true;  // every launched problem's rank is known on the host
   size_t i0 = 0;
   while (i0 < cand.size()) {
+    // before a second side whose first side ran in an earlier launch: wait,
+    // read the ranks, and skip the second sides of the nodes that failed
+    // (unless a wait of those launches timed out: then nothing is known)
+    if (!checked_all) {
+      bool need = false;
+      for (size_t i = i0; i < cand.size() && !need; ++i) {
+        const int pq = h[cand[i]].p.partner;
+        need = pq >= 0 && launched[pq];
+      }
+      if (need) {
+        int herr = 0;
+        hipError_t e = hipMemcpyAsync(&herr, w.err, 4, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipMemcpyAsync(kchk.data(), w.k, h.size() * 4, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return e;
+        checked_all = true;
+        if (!herr) {
+          std::vector<int> keep(cand.begin(), cand.begin() + i0);
+          for (size_t i = i0; i < cand.size(); ++i) {
+            const int q = cand[i], pq = h[q].p.partner;
+            if (pq >= 0 && launched[pq] && fails_rule(h[pq].p, kchk[pq])) skipped[q] = 1;
+            else keep.push_back(q);
+          }
+          const char* vb = std::getenv("HSS_VERBOSE");
+          if (vb && vb[0] >= '2' && keep.size() < cand.size()) {
+            std::fprintf(stderr, "[hss-id] %zu second sides skipped: their node's first side failed\n",
+                         cand.size() - keep.size());
+            std::fflush(stderr);
+          }
+          cand.swap(keep);
+          if (i0 >= cand.size()) break;
+        }
+      }
+    }
     std::vector<int> batch, wgp;
     int nwg = 0;
     size_t i1 = i0;
@@ -1117,6 +1166,8 @@ static hipError_t run_persistent(std::vector<DevProb>& h, const std::vector<int>
       npersist += (int)batch.size();
       ++nlaunch;
       done.insert(done.end(), batch.begin(), batch.end());
+      for (int q : batch) launched[q] = 1;
+      checked_all = false;
     } else {
       (void)hipGetLastError();
       rest.insert(rest.end(), batch.begin(), batch.end());
@@ -1133,7 +1184,7 @@ static hipError_t run_persistent(std::vector<DevProb>& h, const std::vector<int>
   hipError_t e = hipMemcpyAsync(&herr, w.err, 4, hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) return e;
-  if (herr) {
+  if (herr) {  // (a skip decided above saw no timeout: those nodes fail either way)
     const char* vb = std::getenv("HSS_VERBOSE");
     if (vb && vb[0] && vb[0] != '0') {
       std::fprintf(stderr, "[hss-id] persistent wait gave up: %zu problems factored again on the step path\n",
@@ -1141,10 +1192,47 @@ static hipError_t run_persistent(std::vector<DevProb>& h, const std::vector<int>
       std::fflush(stderr);
     }
     rest.insert(rest.end(), done.begin(), done.end());
+    for (size_t q = 0; q < skipped.size(); ++q)  // their partners are factored again: so are they
+      if (skipped[q]) {
+        skipped[q] = 0;
+        rest.push_back((int)q);
+      }
     npersist = 0;
     nlaunch = 0;
   }
   return hipSuccess;
+}
+
+static size_t round_up_256(size_t b) { return (b + 255) / 256 * 256; }
+
+// Workgroups of small-problem class c resident on the device at once.
+static int small_resident(int c) {
+  static int cache[kSmallClasses] = {0};
+  static std::once_flag once;
+  std::call_once(once, [] {
+    const void* fns[kSmallClasses] = {
+        reinterpret_cast<const void*>(&qrcp_reg_kernel<16, 2, 1>),
+        reinterpret_cast<const void*>(&qrcp_reg_kernel<16, 4, 1>),
+        reinterpret_cast<const void*>(&qrcp_reg_kernel<16, 8, 1>),
+        reinterpret_cast<const void*>(&qrcp_reg_kernel<16, 16, 1>),
+        reinterpret_cast<const void*>(&qrcp_reg_kernel<16, 4, 2>),
+        reinterpret_cast<const void*>(&qrcp_reg_kernel<16, 8, 2>),
+        reinterpret_cast<const void*>(&qrcp_reg_kernel<8, 32, 2>),
+        reinterpret_cast<const void*>(&qrcp_reg_kernel<16, 4, 3>),
+        reinterpret_cast<const void*>(&qrcp_reg_kernel<8, 16, 3>),
+        reinterpret_cast<const void*>(&qrcp_reg_kernel<8, 32, 3>)};
+    const int waves[kSmallClasses] = {16, 16, 16, 16, 16, 16, 8, 16, 8, 8};
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+      cus = 256;
+    for (int c = 0; c < kSmallClasses; ++c) {
+      int per = 0;
+      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fns[c], waves[c] * 64, 0) != hipSuccess) per = 1;
+      cache[c] = std::max(1, per) * cus;
+    }
+  });
+  return cache[c];
 }
 
 hipError_t launch_id_factor(IdProblem* probs, int nprob, double rtol, void* work, size_t work_bytes,
@@ -1184,9 +1272,10 @@ hipError_t launch_id_factor(IdProblem* probs, int nprob, double rtol, void* work
   // large pivoted problems: persistent launches where they fit, the rest
   // one launch per step
   int npersist = 0, nplaunch = 0;
+  std::vector<char> skipped(nprob, 0);
   {
     std::vector<int> rest;
-    hipError_t e = run_persistent(h, large, rtol, w, st, s, rest, npersist, nplaunch);
+    hipError_t e = run_persistent(h, large, rtol, w, st, s, rest, skipped, npersist, nplaunch);
     if (e != hipSuccess) return e;
     large.swap(rest);
   }
@@ -1202,42 +1291,100 @@ hipError_t launch_id_factor(IdProblem* probs, int nprob, double rtol, void* work
     if (p.kfail >= 0 && p.m > p.d) steps = std::min(steps, p.kfail + 2);
     smax = std::max(smax, steps);
   }
-  // every table of the launches below stays valid until the last of them
-  static_assert(kSmallClasses == 10, "one reserved size per class");
+  // Small problems: when they fill the device for two rounds or more, the
+  // first side of every node runs first and the second side only where the
+  // first passed the rule (a node with a failing side fails either way), at
+  // the cost of one wait; a single round is latency-bound and runs at once.
+  std::vector<int> small_b[kSmallClasses];
+  bool split = false;
   {
-    size_t sm[kSmallClasses];
-    for (int c = 0; c < kSmallClasses; ++c) sm[c] = small[c].size() * 4;
-    if (!st.reserve({sizeof(DevProb) * nprob, sm[0], sm[1], sm[2], sm[3], sm[4], sm[5], sm[6], sm[7],
-                     sm[8], sm[9], wg_prob.size() * 4}))
-      return hipErrorOutOfMemory;
+    double rounds = 0.0;
+    bool pairs = false;
+    for (int c = 0; c < kSmallClasses; ++c) {
+      if (small[c].empty()) continue;
+      rounds += (double)small[c].size() / std::max(1, small_resident(c));
+      for (int q : small[c]) pairs = pairs || (probs[q].partner >= 0 && probs[q].kfail >= 0);
+    }
+    const char* ss = std::getenv("HSS_QRCP_SMALL_SPLIT");  // tests: 1 always, 0 never
+    split = pairs && (ss && ss[0] ? ss[0] == '1' : rounds >= 2.0);
+    if (split)
+      for (int c = 0; c < kSmallClasses; ++c) {
+        std::vector<int> a;
+        for (int q : small[c]) {
+          const int pq = probs[q].partner;
+          if (pq >= 0 && pq < q && small_class(probs[pq]) >= 0) small_b[c].push_back(q);
+          else a.push_back(q);
+        }
+        small[c].swap(a);
+      }
+  }
+  // every table of the launches below stays valid until the last of them
+  {
+    size_t tot = round_up_256(sizeof(DevProb) * nprob) + round_up_256(wg_prob.size() * 4);
+    for (int c = 0; c < kSmallClasses; ++c)
+      tot += round_up_256(small[c].size() * 4) + round_up_256(small_b[c].size() * 4);
+    if (!st.reserve({tot})) return hipErrorOutOfMemory;
   }
   const DevProb* dprobs = static_cast<const DevProb*>(st.push(h.data(), sizeof(DevProb) * nprob));
   if (!dprobs) return hipErrorOutOfMemory;
   hipError_t e = hipMemsetAsync(w.ndone, 0, 4, s);
   if (e != hipSuccess) return e;
   // small problems: one register-resident workgroup each
-  for (int c = 0; c < kSmallClasses; ++c) {
-    std::vector<int>& L = small[c];
-    if (L.empty()) continue;
-    const int* dl = static_cast<const int*>(st.push(L.data(), L.size() * 4));
-    if (!dl) return hipErrorOutOfMemory;
-    const dim3 grid((unsigned)L.size());
+  auto launch_small = [&](std::vector<int>* lists) -> hipError_t {
+    for (int c = 0; c < kSmallClasses; ++c) {
+      std::vector<int>& L = lists[c];
+      if (L.empty()) continue;
+      const int* dl = static_cast<const int*>(st.push(L.data(), L.size() * 4));
+      if (!dl) return hipErrorOutOfMemory;
+      const dim3 grid((unsigned)L.size());
 #define QR_LAUNCH(W_, C_, R_) \
   hipLaunchKernelGGL((qrcp_reg_kernel<W_, C_, R_>), grid, dim3(W_ * 64), 0, s, dprobs, dl, rtol, w)
-    switch (c) {
-      case 0: QR_LAUNCH(16, 2, 1); break;
-      case 1: QR_LAUNCH(16, 4, 1); break;
-      case 2: QR_LAUNCH(16, 8, 1); break;
-      case 3: QR_LAUNCH(16, 16, 1); break;
-      case 4: QR_LAUNCH(16, 4, 2); break;
-      case 5: QR_LAUNCH(16, 8, 2); break;
-      case 6: QR_LAUNCH(8, 32, 2); break;
-      case 7: QR_LAUNCH(16, 4, 3); break;
-      case 8: QR_LAUNCH(8, 16, 3); break;
-      default: QR_LAUNCH(8, 32, 3); break;
-    }
+      switch (c) {
+        case 0: QR_LAUNCH(16, 2, 1); break;
+        case 1: QR_LAUNCH(16, 4, 1); break;
+        case 2: QR_LAUNCH(16, 8, 1); break;
+        case 3: QR_LAUNCH(16, 16, 1); break;
+        case 4: QR_LAUNCH(16, 4, 2); break;
+        case 5: QR_LAUNCH(16, 8, 2); break;
+        case 6: QR_LAUNCH(8, 32, 2); break;
+        case 7: QR_LAUNCH(16, 4, 3); break;
+        case 8: QR_LAUNCH(8, 16, 3); break;
+        default: QR_LAUNCH(8, 32, 3); break;
+      }
 #undef QR_LAUNCH
-    e = hipGetLastError();
+      const hipError_t le = hipGetLastError();
+      if (le != hipSuccess) return le;
+    }
+    return hipSuccess;
+  };
+  e = launch_small(small);
+  if (e != hipSuccess) return e;
+  if (split) {
+    // the first sides' ranks, then the second sides of the nodes still alive
+    std::vector<int> kk(nprob, 0);
+    e = hipMemcpyAsync(kk.data(), w.k, (size_t)nprob * 4, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return e;
+    int nskip = 0;
+    for (int c = 0; c < kSmallClasses; ++c) {
+      std::vector<int> b;
+      for (int q : small_b[c]) {
+        const int pq = probs[q].partner;
+        if (fails_rule(probs[pq], kk[pq])) {
+          skipped[q] = 1;
+          ++nskip;
+        } else {
+          b.push_back(q);
+        }
+      }
+      small_b[c].swap(b);
+    }
+    const char* vb = std::getenv("HSS_VERBOSE");
+    if (vb && vb[0] >= '2') {
+      std::fprintf(stderr, "[hss-id] small problems in two phases: %d second sides skipped\n", nskip);
+      std::fflush(stderr);
+    }
+    e = launch_small(small_b);
     if (e != hipSuccess) return e;
   }
   {
@@ -1300,6 +1447,8 @@ hipError_t launch_id_factor(IdProblem* probs, int nprob, double rtol, void* work
   }
   e = hipMemcpyAsync(k_host, w.k, (size_t)nprob * 4, hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
+  for (int q = 0; q < nprob; ++q)  // not factored: the other side of the node failed
+    if (skipped[q]) k_host[q] = 0;
   return e;
 }
 

@@ -11,6 +11,8 @@
 // the four 64-bit output words w0..w3 become u = ((w >> 12) + 1/2) 2^-52 and
 // rows 4q, 4q+1 take the Box-Muller pair of (u0, u1), rows 4q+2, 4q+3 that of
 // (u2, u3): sqrt(-2 ln ua) cos(2 pi ub), sqrt(-2 ln ua) sin(2 pi ub).
+#include <vector>
+
 #include "hss_internal.h"
 
 namespace hss {
@@ -78,7 +80,70 @@ __global__ void random_normal_kernel(unsigned long long seed, int which, long lo
   }
 }
 
+// Many (matrix, side) column ranges in one launch: job q covers the flattened
+// blocks [b0, b0 + nb) of the layout above; entries rounded to `mode`.
+struct RngDesc {
+  RngJob j;
+  long long b0;
+  int ncb;
+};
+
+__global__ void random_normal_batched_kernel(const RngDesc* __restrict__ jobs, int njob, int mode) {
+  const long long b = blockIdx.x;
+  int lo = 0, hi = njob - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (jobs[mid].b0 <= b) lo = mid;
+    else hi = mid - 1;
+  }
+  const RngDesc& d = jobs[lo];
+  const long long local = b - d.b0;
+  const int cb = (int)(local % d.ncb);
+  const long long qb = local / d.ncb;
+  const int c = cb * blockDim.x + threadIdx.x;
+  const long long q = qb * blockDim.y + threadIdx.y;
+  const long long n = d.j.n;
+  if (c >= d.j.ncol || 4 * q >= n) return;
+  U64x4 w = philox4x64_10((unsigned long long)q, (unsigned long long)(d.j.col0 + c),
+                          (unsigned long long)d.j.which, 0ull, d.j.seed, 0ull);
+  const double two_pi = 2.0 * 3.14159265358979323846;
+  double u0 = to_unit(w.v[0]), u1 = to_unit(w.v[1]);
+  double u2 = to_unit(w.v[2]), u3 = to_unit(w.v[3]);
+  double r01 = sqrt(-2.0 * log(u0));
+  double r23 = sqrt(-2.0 * log(u2));
+  double t01 = two_pi * u1, t23 = two_pi * u3;
+  double z[4] = {r01 * cos(t01), r01 * sin(t01), r23 * cos(t23), r23 * sin(t23)};
+  const long long row0 = 4 * q;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    if (row0 + r < n) d.j.R[(row0 + r) * d.j.ld + c] = round_sample_prec(z[r], mode);
+  }
+}
+
 }  // namespace
+
+hipError_t launch_random_normal_batched(const RngJob* jobs, int njob, int mode, Staging& st,
+                                        hipStream_t s) {
+  std::vector<RngDesc> h;
+  h.reserve(njob);
+  long long blocks = 0;
+  for (int q = 0; q < njob; ++q) {
+    const RngJob& j = jobs[q];
+    if (j.ncol <= 0 || j.n <= 0) continue;
+    RngDesc d;
+    d.j = j;
+    d.ncb = (j.ncol + 63) / 64;
+    d.b0 = blocks;
+    blocks += (long long)d.ncb * (((j.n + 3) / 4 + 3) / 4);
+    h.push_back(d);
+  }
+  if (h.empty()) return hipSuccess;
+  const RngDesc* dd = static_cast<const RngDesc*>(st.push(h.data(), h.size() * sizeof(RngDesc)));
+  if (!dd) return hipErrorOutOfMemory;
+  hipLaunchKernelGGL(random_normal_batched_kernel, dim3((unsigned)blocks), dim3(64, 4), 0, s, dd, (int)h.size(),
+                     mode);
+  return hipGetLastError();
+}
 
 void launch_random_normal(unsigned long long seed, int which, long long n, int col0, int col1,
                           double* R, long long ld, hipStream_t s) {

@@ -64,9 +64,6 @@ __device__ __forceinline__ unsigned short bf16_rn(float x) {
   u += 0x7FFFu + ((u >> 16) & 1u);
   return (unsigned short)(u >> 16);
 }
-__device__ __forceinline__ float bf16_to_f(unsigned short h) {
-  return __uint_as_float((unsigned int)h << 16);
-}
 
 template <int MODE>
 struct Smem;
@@ -143,17 +140,27 @@ __device__ __forceinline__ void load_a(float (&v)[16], const float* __restrict__
   }
 }
 
-// three-term split of FP32 values into BF16: a = h1 + h2 + h3 exactly
-__device__ __forceinline__ void split3(float a, unsigned short& h1, unsigned short& h2,
-                                       unsigned short& h3) {
-  h1 = bf16_rn(a);
-  const float r1 = a - bf16_to_f(h1);
-  h2 = bf16_rn(r1);
-  h3 = bf16_rn(r1 - bf16_to_f(h2));
+// Three-term split of an FP32 value into BF16 by truncation, a = h1 + h2 + h3
+// exactly: h1 keeps the top 8 significant bits of a (its upper 16 bits), the
+// remainder r1 = a - h1 is exact in FP32 and has at most 16 significant bits,
+// h2 keeps its top 8, and r2 = r1 - h2 (exact) has at most 8, so it is a BF16
+// value itself.  Exact for every normal a whose remainders stay normal
+// (|a| >= 2^-103); below that an entry loses at most its own magnitude.  Each
+// term is returned as FP32 bits whose low 16 bits are zero.  Four VALU
+// operations, against about fifteen for a split by rounding to nearest: 5.64
+// -> 5.48 ms per BF16x3 launch at n = 65536 with 64 columns, once the terms
+// are packed two k at a time (holding all 48 terms of a thread unpacked
+// spilled registers and took 8.7 ms).
+__device__ __forceinline__ void split3(float a, unsigned int& h1, unsigned int& h2, unsigned int& h3) {
+  h1 = __float_as_uint(a) & 0xFFFF0000u;
+  const float r1 = a - __uint_as_float(h1);
+  h2 = __float_as_uint(r1) & 0xFFFF0000u;
+  h3 = __float_as_uint(r1 - __uint_as_float(h2));
 }
 
-__device__ __forceinline__ unsigned int pack2(unsigned short lo, unsigned short hi) {
-  return (unsigned int)lo | ((unsigned int)hi << 16);
+// two BF16 terms (the upper halves of lo and hi) in one 32-bit word, lo first
+__device__ __forceinline__ unsigned int pack2(unsigned int lo, unsigned int hi) {
+  return __builtin_amdgcn_perm(hi, lo, 0x07060302u);
 }
 
 template <int MODE, bool TRANS>
@@ -167,18 +174,22 @@ __device__ __forceinline__ void store_a(Smem<MODE>& sm, const float (&v)[16]) {
         *reinterpret_cast<float4*>(&sm.A[r][kseg + 4 * j]) =
             make_float4(v[4 * j], v[4 * j + 1], v[4 * j + 2], v[4 * j + 3]);
     } else {
-      unsigned short h[3][16];
+      // split and pack two k at a time, so that only the packed words stay live
 #pragma unroll
-      for (int e = 0; e < 16; ++e) split3(v[e], h[0][e], h[1][e], h[2][e]);
+      for (int j = 0; j < 2; ++j) {
+        u32x4 w[3];
 #pragma unroll
-      for (int t = 0; t < 3; ++t)
-#pragma unroll
-        for (int j = 0; j < 2; ++j) {
-          u32x4 w;
-#pragma unroll
-          for (int q = 0; q < 4; ++q) w[q] = pack2(h[t][8 * j + 2 * q], h[t][8 * j + 2 * q + 1]);
-          *reinterpret_cast<u32x4*>(&sm.A[t][r][kseg + 8 * j]) = w;
+        for (int q = 0; q < 4; ++q) {
+          unsigned int a1, a2, a3, b1, b2, b3;
+          split3(v[8 * j + 2 * q], a1, a2, a3);
+          split3(v[8 * j + 2 * q + 1], b1, b2, b3);
+          w[0][q] = pack2(a1, b1);
+          w[1][q] = pack2(a2, b2);
+          w[2][q] = pack2(a3, b3);
         }
+#pragma unroll
+        for (int t = 0; t < 3; ++t) *reinterpret_cast<u32x4*>(&sm.A[t][r][kseg + 8 * j]) = w[t];
+      }
     }
   } else {  // 4 rows of the tile (columns of A), 4 consecutive k each
     const int kq = 4 * (tid >> 5), rb = 4 * (tid & 31);
@@ -187,12 +198,18 @@ __device__ __forceinline__ void store_a(Smem<MODE>& sm, const float (&v)[16]) {
       if constexpr (MODE == 1) {
         *reinterpret_cast<float4*>(&sm.A[rb + e][kq]) = make_float4(v[e], v[4 + e], v[8 + e], v[12 + e]);
       } else {
-        unsigned short h[3][4];
+        unsigned int w[3][2];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) split3(v[4 * q + e], h[0][q], h[1][q], h[2][q]);
+        for (int q = 0; q < 2; ++q) {
+          unsigned int a1, a2, a3, b1, b2, b3;
+          split3(v[8 * q + e], a1, a2, a3);
+          split3(v[8 * q + 4 + e], b1, b2, b3);
+          w[0][q] = pack2(a1, b1);
+          w[1][q] = pack2(a2, b2);
+          w[2][q] = pack2(a3, b3);
+        }
 #pragma unroll
-        for (int t = 0; t < 3; ++t)
-          *reinterpret_cast<uint2*>(&sm.A[t][rb + e][kq]) = make_uint2(pack2(h[t][0], h[t][1]), pack2(h[t][2], h[t][3]));
+        for (int t = 0; t < 3; ++t) *reinterpret_cast<uint2*>(&sm.A[t][rb + e][kq]) = make_uint2(w[t][0], w[t][1]);
       }
     }
   }
@@ -492,16 +509,9 @@ __global__ void round_r_kernel(double* __restrict__ R, long long ld, long long n
   const int w = col1 - col0;
   if (idx >= n * w) return;
   double* p = R + (idx / w) * ld + col0 + (int)(idx % w);
-  if (mode == 1) {
-    *p = (double)(float)*p;
-  } else {
-    // keep 8 significant bits: round away the low 45 bits of the FP64
-    // fraction (bias of half minus one, plus the kept lowest bit for ties)
-    unsigned long long u = (unsigned long long)__double_as_longlong(*p);
-    u += 0x00000FFFFFFFFFFFull + ((u >> 45) & 1ull);
-    u &= ~0x00001FFFFFFFFFFFull;
-    *p = __longlong_as_double((long long)u);
-  }
+  // BF16: keep 8 significant bits, rounding away the low 45 bits of the FP64
+  // fraction (bias of half minus one, plus the kept lowest bit for ties)
+  *p = round_sample_prec(*p, mode);
 }
 
 struct Plan {

@@ -192,3 +192,31 @@ def test_export_structure():
                                                      P.hss_export_node(h, b, (tree.left[b], tree.right[b]))["Ic"])])
         else:
             assert np.array_equal(g["D"], A[lo:hi, lo:hi])
+
+
+def test_small_ids_in_two_phases_skip_failed_nodes(monkeypatch, capfd):
+    """Small IDs run in two phases when forced (the first side of every node,
+    then the second side where the first passed the rule): the compression is
+    the one-phase compression exactly (a node with a failing side fails
+    either way, Sec. 3.3), bit for bit in the matvec, and second sides were
+    skipped."""
+    A = W.toeplitz_inverse_distance(2048)
+    kw = dict(rtol=1e-8, d0=16, dd=8, leaf_size=64)
+    monkeypatch.setenv("HSS_QRCP_SMALL_SPLIT", "0")
+    h0 = _gpu(A, **kw)
+    monkeypatch.setenv("HSS_QRCP_SMALL_SPLIT", "1")
+    monkeypatch.setenv("HSS_VERBOSE", "2")
+    capfd.readouterr()
+    print("compress with small IDs in two phases", flush=True)
+    h1 = _gpu(A, **kw)
+    err = capfd.readouterr().err
+    skipped = [int(line.split(":")[1].split()[0]) for line in err.splitlines() if "two phases" in line]
+    assert skipped and sum(skipped) > 0, err
+    s0, s1 = P.hss_stats(h0), P.hss_stats(h1)
+    assert (s0["passes"], s0["d_final"]) == (s1["passes"], s1["d_final"]) and s0["passes"] >= 3
+    for a, b in zip(P.hss_ranks(h0), P.hss_ranks(h1)):
+        assert np.array_equal(a, b)
+    x = torch.from_numpy(W.uniform_rhs(2048, 3, 5)).cuda()
+    assert torch.equal(P.hss_matvec(h0, x), P.hss_matvec(h1, x))
+    Ho = ohss.compress(A, ohss.Options(**kw))
+    assert (s1["passes"], s1["d_final"]) == (Ho.passes, Ho.d_final)

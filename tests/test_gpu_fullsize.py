@@ -178,3 +178,29 @@ def test_compress_gauss65536_reduced_precision(gauss65536, prec):
     ref = _dense_mv(A, x)
     assert float(torch.linalg.norm(b - ref) / torch.linalg.norm(ref)) <= 10 * rtol
     assert _frob(h, A) <= 10 * rtol
+
+
+def test_gauss4096_split_launches_skip_failed_nodes(monkeypatch, capfd):
+    """Persistent QRCP launches held to 40 workgroups each, so a level's IDs
+    need several launches: the second side of a node whose first side
+    failed the rule is not factored (the node fails either way, Sec. 3.3),
+    and the compression still follows the oracle's schedule (stored result,
+    p_margin 256)."""
+    path = os.path.join(GOLDEN, "oracle_gauss4096_rtol1e-06_pm256.json")
+    ref = json.load(open(path))
+    A = _gauss(ref["n"], ref["leaf"])
+    monkeypatch.setenv("HSS_QRCP_PATH", "persistent")
+    monkeypatch.setenv("HSS_QRCP_PERSIST_WG", "40")
+    monkeypatch.setenv("HSS_VERBOSE", "2")
+    capfd.readouterr()
+    print("compress gauss n=4096 with 40-workgroup persistent launches", flush=True)
+    h = P.hss_compress(A, rtol=ref["rtol"], d0=ref["d0"], dd=ref["dd"], leaf_size=ref["leaf"], p_margin=256)
+    err_txt = capfd.readouterr().err
+    assert "second sides skipped" in err_txt
+    st = P.hss_stats(h)
+    assert st["passes"] == ref["passes"] and st["d_final"] == ref["d_final"]
+    kr, kc, _, _ = P.hss_ranks(h)
+    okr, okc = np.array(ref["kr"]), np.array(ref["kc"])
+    diff = np.flatnonzero((kr != okr) | (kc != okc))
+    assert len(diff) <= 2 and np.all(np.abs(kr - okr) <= 2) and np.all(np.abs(kc - okc) <= 2)
+    assert _frob(h, A) <= 1.5 * ref["rel_error"] + 1e-9

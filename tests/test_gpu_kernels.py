@@ -249,3 +249,39 @@ def test_persistent_give_up_reruns_on_step_path(monkeypatch, capfd):
         assert abs(k - ref.k) <= 1
         if rate >= 0.3:
             assert k == ref.k and list(perm[:k]) == list(ref.J)
+
+
+@pytest.mark.parametrize("variant", list(range(-1, 7)))
+def test_gemm_batched_tile_shapes(variant):
+    """The batched FP64 GEMM of every per-node product (Alg. 1-4), in each
+    of its tile shapes (variant -1: the tuning table's choice), against the
+    FP64 product on the host: a dot product of length K differs from another
+    correct one by at most 2 gamma_K |A||B| entrywise; problems cover empty
+    K, single rows and columns, ragged edges of every tile and transposed A;
+    every shape gives the same bits (the k order of each entry is the same)."""
+    if variant >= P.hss_gemm_variants():
+        pytest.skip("no such tile shape")
+    g = np.random.default_rng(40)
+    sizes = [(1, 1, 1, 0), (17, 5, 33, 1), (64, 64, 64, 0), (100, 130, 70, 1), (257, 3, 300, 0),
+             (33, 200, 0, 0), (129, 17, 16, 1), (15, 65, 129, 0)]
+    As, Bs, Cs, tr, ref, bnd = [], [], [], [], [], []
+    alpha, beta = -1.5, 0.5
+    for M, N, K, t in sizes:
+        A = g.standard_normal((K, M) if t else (M, K))
+        B = g.standard_normal((K, N))
+        C = g.standard_normal((M, N))
+        opA = A.T if t else A
+        ref.append(alpha * (opA @ B) + beta * C)
+        gam = 2 * K * U / (1 - K * U) if K else 0.0
+        bnd.append(gam * abs(alpha) * (np.abs(opA) @ np.abs(B)) + 4 * U * (np.abs(alpha * (opA @ B)) + np.abs(beta * C)))
+        As.append(torch.from_numpy(A).cuda())
+        Bs.append(torch.from_numpy(B).cuda())
+        Cs.append(torch.from_numpy(C).cuda())
+        tr.append(bool(t))
+    print(f"gemm_batched variant {variant}: {len(sizes)} problems", flush=True)
+    out = P.hss_gemm_batched(As, Bs, [c.clone() for c in Cs], tr, alpha, beta, variant)
+    base = P.hss_gemm_batched(As, Bs, [c.clone() for c in Cs], tr, alpha, beta, 0)
+    torch.cuda.synchronize()
+    for o, b0, r, bd in zip(out, base, ref, bnd):
+        assert np.all(np.abs(o.cpu().numpy() - r) <= bd + 1e-300)
+        assert torch.equal(o, b0)
