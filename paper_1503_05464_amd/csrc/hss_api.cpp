@@ -1071,8 +1071,8 @@ hss_status process_items(Handle& L, Arena& W, std::vector<Item>& items, EventTim
   L.lgemm_bytes += gemm_bytes(gd);
   for (Item& it : items) node(it).cdone = it.d;
   tm.end(ev_level, 1);
-  HIPCHK(hipStreamSynchronize(L.stream));
-  L.staging.reset();
+  // no wait here: the next level's ID readback orders the host after this
+  // level, and the staging block is only reused once its readers have run
   return HSS_OK;
 }
 
