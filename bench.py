@@ -300,7 +300,8 @@ def run_batched(args) -> int:
     return 0
 
 
-def serve_measure(nreq: int, rate: float, workers: int, budget_frac: float = 0.8) -> dict:
+def serve_measure(nreq: int, rate: float, workers: int, budget_frac: float = 0.8,
+                  p_margins=(32, 192)) -> dict:
     """The serving workload: requests of compress + ULV factor + solve arrive
     as a Poisson process at `rate` per second (seed 6).  Each request draws
     its matrix from a pool of 16 pre-assembled matrices -- N log-uniform in
@@ -344,7 +345,11 @@ def serve_measure(nreq: int, rate: float, workers: int, budget_frac: float = 0.8
     # footprint counts its A, b and x as well as the library's buffers
     budget = int(budget_frac * torch.cuda.mem_get_info()[1])
     srv = P.HSSServer(hbm_budget=budget, max_batch=32, workers=workers)
-    kw0 = dict(d0=64, dd=32, d_max=1024, leaf_size=128, p_margin=32, sample_prec="bf16x3")
+    # p_margin by rtol: (for 1e-4, for 1e-6)
+    kw0 = dict(d0=64, dd=32, d_max=1024, leaf_size=128, sample_prec="bf16x3")
+
+    def pm(rt):
+        return int(p_margins[0] if rt >= 1e-5 else p_margins[1])
     print(f"[bench] serving {nreq} requests at {rate:g}/s", file=sys.stderr, flush=True)
     t_start = time.perf_counter()
     t_next = t_start
@@ -353,7 +358,7 @@ def serve_measure(nreq: int, rate: float, workers: int, budget_frac: float = 0.8
         t_next += gaps[i]
         while time.perf_counter() < t_next:
             time.sleep(max(0.0, min(0.001, t_next - time.perf_counter())))
-        tickets.append(srv.submit(pool[pick[i]], rhs[i], rtol=float(rtols[i]), **kw0))
+        tickets.append(srv.submit(pool[pick[i]], rhs[i], rtol=float(rtols[i]), p_margin=pm(rtols[i]), **kw0))
     t_submitted = time.perf_counter()
     infos, xs = [], []
     for i, t in enumerate(tickets):
@@ -388,7 +393,7 @@ def serve_measure(nreq: int, rate: float, workers: int, budget_frac: float = 0.8
         worst_rel_bound = max(worst_rel_bound, bwd / (10 * float(rtols[i])))
         detail.append({"n": int(A.shape[0]), "kernel": "log" if kinds[q] == 0 else "gauss",
                        "rtol": float(rtols[i]), "nrhs": int(nrhs[i]), "backward_error": bwd})
-        h = P.hss_compress(pool[q], rtol=float(rtols[i]), **kw0)
+        h = P.hss_compress(pool[q], rtol=float(rtols[i]), p_margin=pm(rtols[i]), **kw0)
         P.hss_factor(h)
         xa = P.hss_solve(h, rhs[i])
         worst_alone = max(worst_alone, float(torch.linalg.norm(x - xa) / torch.linalg.norm(xa)))
@@ -401,6 +406,7 @@ def serve_measure(nreq: int, rate: float, workers: int, budget_frac: float = 0.8
         "warmup": warm,
         "workers": workers,
         "hbm_budget_frac": budget_frac,
+        "p_margin": {"rtol 1e-4": int(p_margins[0]), "rtol 1e-6": int(p_margins[1])},
         "latency_s": {"p50": round(float(np.percentile(lat, 50)), 4), "p90": round(float(np.percentile(lat, 90)), 4),
                       "p99": round(float(np.percentile(lat, 99)), 4), "max": round(float(lat.max()), 4)},
         "throughput_req_s": round(thr, 2),
@@ -418,7 +424,8 @@ def serve_measure(nreq: int, rate: float, workers: int, budget_frac: float = 0.8
 def run_serve(args) -> int:
     """The serving workload on its own (see serve_measure); `value` is the
     p50 latency."""
-    res = serve_measure(args.serve_requests, float(args.serve_rate), args.serve_workers)
+    res = serve_measure(args.serve_requests, float(args.serve_rate), args.serve_workers,
+                        p_margins=tuple(int(v) for v in args.serve_p_margin.split(",")))
     out = {
         "metric": "HSS serving latency s (compress + ULV factor + solve per request), p50; p99 alongside",
         "value": res["latency_s"]["p50"],
@@ -435,7 +442,9 @@ def run_serve(args) -> int:
         "config": {
             "workload": f"serve: Poisson arrivals at {res['rate_req_s']:g}/s (seed 6), pool of 16 FP32 matrices "
                         "N log-uniform in [512, 32768] (log kernel on a circle or Gaussian kernel in 3-D), rtol in "
-                        "{1e-4, 1e-6}, nrhs in {1..64}, leaf 128, d0 64, dd 32, p_margin 32, BF16X3 sampling",
+                        "{1e-4, 1e-6}, nrhs in {1..64}, leaf 128, d0 64, dd 32, p_margin "
+                        f"{res['p_margin']['rtol 1e-4']} / {res['p_margin']['rtol 1e-6']} (rtol 1e-4 / 1e-6), "
+                        "BF16X3 sampling",
             "requests": res["requests"], "workers": res["workers"], "max_batch": 32,
             "hbm_budget": f"{int(100 * res['hbm_budget_frac'])}% of device memory",
         },
@@ -599,6 +608,8 @@ def main() -> int:
     ap.add_argument("--serve-requests", type=int, default=400, help="requests of the serve workload")
     ap.add_argument("--serve-rate", type=float, default=200.0, help="Poisson arrival rate of the serve workload")
     ap.add_argument("--serve-workers", type=int, default=4, help="worker threads (streams) of the server")
+    ap.add_argument("--serve-p-margin", default="32,192",
+                    help="p_margin of served requests at rtol 1e-4 and at rtol 1e-6")
     ap.add_argument("--rtol", type=float, default=None)
     ap.add_argument("--p-margin", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
