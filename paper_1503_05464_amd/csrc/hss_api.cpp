@@ -52,6 +52,11 @@ namespace {
 
 size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
+int verbose_level(const char* v) {
+  if (!v || !v[0] || v[0] == '0') return 0;
+  return (v[0] >= '1' && v[0] <= '9') ? v[0] - '0' : 1;
+}
+
 double now_ms() {
   return std::chrono::duration<double, std::milli>(
              std::chrono::steady_clock::now().time_since_epoch())
@@ -966,8 +971,25 @@ hss_status process_items(Handle& L, Arena& W, std::vector<Item>& items, EventTim
       L.k_host_cap = np * 2;
     }
     const int ev_id = tm.begin();
+    const double t_id0 = L.verbose >= 2 ? now_ms() : 0.0;
     HIPCHK(launch_id_factor(pr.data(), np, L.opts.rtol, wk, L.work_id.cap, L.k_host, L.staging,
                             L.stream));
+    if (L.verbose >= 2) {  // the factor call has read the ranks back: its work is done
+      int hmin = INT_MAX, hmax = 0, nfail = 0, mmax = 0;
+      for (size_t q = 0; q < idn.size(); ++q) {
+        const Item& it = items[idn[q]];
+        const Node& v = node(it);
+        hmin = std::min(hmin, v.height);
+        hmax = std::max(hmax, v.height);
+        mmax = std::max(mmax, std::max(v.mr, v.mc));
+        const int kf = it.d - it.H->opts.p_margin;
+        const int kr = L.k_host[2 * q], kc = L.k_host[2 * q + 1];
+        if (!it.forced && ((kr > kf && kr < v.mr) || (kc > kf && kc < v.mc))) ++nfail;
+      }
+      std::fprintf(stderr, "[hss] level h=%d..%d d=%d: %zu ID nodes (%d fail), max m %d: %.2f ms\n", hmin, hmax,
+                   items[0].d, idn.size(), nfail, mmax, now_ms() - t_id0);
+      std::fflush(stderr);
+    }
     L.staging.reset();
     for (int q = 0; q < np; ++q)  // Householder QR of d x m to k steps: about 4 d m k flops
       L.id_flops += 4.0 * (double)pr[q].d * (double)pr[q].m * (double)L.k_host[q];
@@ -1664,7 +1686,7 @@ hss_status hss_compress(const void* A, int dtype, long long n, long long lda,
   H.opts = o;
   {
     const char* v = std::getenv("HSS_VERBOSE");
-    H.verbose = v && v[0] && v[0] != '0';
+    H.verbose = verbose_level(v);
   }
   hss_status st = build_tree(H, n, tree, o.leaf_size);
   if (st == HSS_OK) st = compress_impl(H, A, lda);
@@ -1722,7 +1744,7 @@ hss_status hss::compress_batched(int nmat, const void* const* A, int dtype, cons
       Handle& H = hs[i]->h;
       H.dtype = dtype;
       H.opts = o;
-      H.verbose = v && v[0] && v[0] != '0';
+      H.verbose = verbose_level(v);
       if (share_arena) {  // one generator arena for the batch
         if (i == 0) H.gen->chunk = (size_t)64 << 20;
         else H.gen = hs[0]->h.gen;

@@ -113,7 +113,7 @@ struct Handle {
   bool converged = true;
   bool compressed = false;
   bool factored = false;
-  bool verbose = false;  // HSS_VERBOSE: one line per pass on stderr
+  int verbose = 0;  // HSS_VERBOSE: 1 = one line per pass on stderr, 2 = also one per level
   double t_total = 0, t_sample = 0, t_levels = 0, t_id = 0, t_sgemm = 0;
   int n_sgemm = 0;
   double sgemm_flops = 0, sgemm_bytes = 0;

@@ -68,7 +68,8 @@ struct Work {
   int* ndone;    // 1
   double* cand_v;  // 2 * tg: per-workgroup pivot candidates (step parity)
   int* cand_i;     // 2 * tg
-  double* cbuf;    // 2 * min(tg, kCandSlots) * ldcb: candidate columns (persistent path)
+  unsigned long long* cbuf;  // 2 * min(tg, kCandSlots) * 2 * ldcb: candidate columns as
+                             // tagged words (persistent path), zeroed before each launch
   long long ldcb;  // max d rounded up to a multiple of 512 (a whole column of registers)
   long long nslots;  // min(tg, kCandSlots): workgroups a persistent launch may have
   long long krec;    // max kmax: steps a persistent launch may publish
@@ -122,7 +123,7 @@ void carve(const IdProblem* probs, int nprob, void* base, Work& w, long long& tm
   w.cand_i = reinterpret_cast<int*>(take(2 * tg * 4));
   w.ldcb = ldcb_of(dm);
   w.nslots = std::min(tg, kCandSlots);
-  w.cbuf = reinterpret_cast<double*>(take(2 * w.nslots * w.ldcb * 8));
+  w.cbuf = reinterpret_cast<unsigned long long*>(take(2 * w.nslots * 2 * w.ldcb * 8));
   w.krec = km;
   w.rec = reinterpret_cast<unsigned long long*>(take(2 * w.nslots * km * 8));
   w.err = reinterpret_cast<int*>(take(4));
@@ -549,20 +550,25 @@ __global__ __launch_bounds__(ST) void id_step_kernel(const DevProb* __restrict__
 // values as the reflector and updates its own columns.  Per step, global
 // memory carries only the candidates and one column per workgroup.
 //
-// A record is two 64-bit words, each written and read whole (aligned 64-bit
-// device-scope accesses), in memory zeroed before the launch and written once
-// per launch: the norm with its sign bit flipped (never zero: norms are +0 or
-// more, or -1 for no candidate) and (step + 1) << 32 | index.  A reader takes
-// a record once both words are non-zero and the step matches, so one poll
-// returns the candidate.  A workgroup writes its record only after its column
-// stores have completed.  No read-modify-write atomics are used.  The record
-// store follows an agent-scope release fence and a reader that has taken its
-// records runs an agent-scope acquire fence, so the column values are ordered
-// before the record under the memory model, not only by the hardware's
-// in-order completion.  The wait for a record is bounded: a workgroup that
-// waits too long raises the error flag and leaves, and so does every
-// workgroup that sees the flag; the factorization is then reported as failed
-// and nothing is written back.
+// Every word that crosses workgroups carries the step it belongs to, so a
+// reader can tell a current word from a stale one by looking at the word
+// alone; no ordering between different words is needed, hence no fences
+// and no wait for stores to complete.  All such accesses are relaxed
+// agent-scope atomics on aligned 64-bit words in memory zeroed before the
+// launch (single-copy atomic, and coherent per location), and no
+// read-modify-write atomics are used.
+// - A record is two words written once per launch: the norm with its sign
+//   bit flipped (never zero: norms are +0 or more, or -1 for no candidate)
+//   and (step + 1) << 32 | index.  A reader takes a record once both words
+//   are non-zero and the step matches.
+// - A published column value is split into two words, (step + 1) << 32 |
+//   low 32 bits and (step + 1) << 32 | high 32 bits.  The column slots are
+//   double-buffered by step parity, so a slot still holding the step before
+//   last shows a different tag; the reader of the winner's column loads
+//   every row again until both tags match the step.
+// Every wait is bounded: a workgroup that waits too long raises the error
+// flag and leaves, and so does every workgroup that sees the flag; the
+// factorization is then reported as failed and nothing is written back.
 // ---------------------------------------------------------------------------
 constexpr int PW = 8;        // wavefronts per persistent workgroup (two per SIMD)
 constexpr int PT = PW * 64;  // threads per persistent workgroup
@@ -595,6 +601,8 @@ __global__ __launch_bounds__(PT) void qrcp_persist_kernel(const DevProb* __restr
   __shared__ double u[T * 64];
   __shared__ double rv[PW];
   __shared__ int ri[PW];
+  __shared__ double gv_s[PW];
+  __shared__ int gi_s[PW];
   __shared__ double s_best;
   __shared__ int s_p;
   __shared__ int s_ok;
@@ -633,7 +641,9 @@ __global__ __launch_bounds__(PT) void qrcp_persist_kernel(const DevProb* __restr
   if (tid == 0) s_ok = 1;
 
   // publish this workgroup's best column for step i: norm, index, and the
-  // row slices from i / 64 on (the reader masks rows below i)
+  // row slices from i / 64 on (the reader masks rows below i).  The owning
+  // wavefront writes the column and then the record (the first wavefront
+  // writes the record when the workgroup has no candidate left).
   auto publish = [&](int i) __attribute__((always_inline)) {  // y must stay in registers
     if (lane == 0) {
       rv[wave] = bv;
@@ -645,9 +655,15 @@ __global__ __launch_bounds__(PT) void qrcp_persist_kernel(const DevProb* __restr
 #pragma unroll
     for (int t = 1; t < PW; ++t) better(v, ix, rv[t], ri[t]);
     const long long slot = (long long)(i & 1) * nslot + blockIdx.x;
-    if (ix >= jb && ix < jb + C) {  // uniform: the owning wavefront writes
-      double* dst = w.cbuf + slot * ldcb + lane;
-      asm volatile("" : "+v"(dst));  // addresses formed here, not hoisted out of the step loop
+    const unsigned long long tag = (unsigned long long)(i + 1) << 32;
+    const bool own = ix >= jb && ix < jb + C;  // uniform within a wavefront
+    if (own) {
+      // uniform bases and one 32-bit lane offset, formed here (not hoisted
+      // out of the step loop as T live addresses)
+      char* blo = reinterpret_cast<char*>(w.cbuf + slot * 2 * ldcb);
+      char* bhi = reinterpret_cast<char*>(w.cbuf + slot * 2 * ldcb + ldcb);
+      unsigned vo = (unsigned)lane * 8u;
+      asm volatile("" : "+v"(vo));
       const int ti = i >> 6;
 #pragma unroll
       for (int c = 0; c < C; ++c) {
@@ -656,15 +672,16 @@ __global__ __launch_bounds__(PT) void qrcp_persist_kernel(const DevProb* __restr
         for (int g = 0; g < T / PG; ++g) {
           if (PG * g + PG <= ti) continue;
 #pragma unroll
-          for (int tt = 0; tt < PG; ++tt) st_dev(dst + 64 * (PG * g + tt), y[c][PG * g + tt]);
+          for (int tt = 0; tt < PG; ++tt) {
+            const unsigned off = vo + 512u * (unsigned)(PG * g + tt);
+            const unsigned long long b = (unsigned long long)__double_as_longlong(y[c][PG * g + tt]);
+            st_dev(reinterpret_cast<unsigned long long*>(blo + off), tag | (b & 0xffffffffull));
+            st_dev(reinterpret_cast<unsigned long long*>(bhi + off), tag | (b >> 32));
+          }
         }
       }
     }
-    __builtin_amdgcn_s_waitcnt(0);  // this thread's stores have completed
-    __syncthreads();                // ... and every other thread's
-    if (tid == 0) {
-      // the workgroup's column stores happen before the record (release)
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    if (lane == 0 && (own || (ix == INT_MAX && wave == 0))) {
       unsigned long long* r = w.rec + 2 * ((long long)i * nslot + blockIdx.x);
       st_dev(r, (unsigned long long)__double_as_longlong(v) ^ kSignBit);
       st_dev(r + 1, ((unsigned long long)(i + 1) << 32) | (unsigned)ix);
@@ -704,24 +721,19 @@ __global__ __launch_bounds__(PT) void qrcp_persist_kernel(const DevProb* __restr
       }
       if (ok) better(gv, gi, __longlong_as_double((long long)(a ^ kSignBit)), (int)(unsigned)b);
     }
-    // the publishers' columns are read after their records (acquire, by the
-    // wavefronts that polled them; the barrier below passes this on to the
-    // rest of the workgroup).  An acquire in every wavefront cost 1523 ms of
-    // IDs per gauss65536 compression against 909 ms in the polling ones, and
-    // the release above 75 ms more (837 ms with neither).
-    if (tid < ((dp.G + 63) & ~63)) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     if (!ok) s_ok = 0;
     wave_argmax(gv, gi);
-    // rv / ri: every thread read them in publish before its closing barrier
+    // gv_s / gi_s, not rv / ri: publish has no closing barrier, so another
+    // wavefront may still be reading rv / ri
     if (lane == 0) {
-      rv[wave] = gv;
-      ri[wave] = gi;
+      gv_s[wave] = gv;
+      gi_s[wave] = gi;
     }
     __syncthreads();
     if (tid == 0) {
-      double v = rv[0];
-      int ix = ri[0];
-      for (int t = 1; t < PW; ++t) better(v, ix, rv[t], ri[t]);
+      double v = gv_s[0];
+      int ix = gi_s[0];
+      for (int t = 1; t < PW; ++t) better(v, ix, gv_s[t], gi_s[t]);
       s_best = v;
       s_p = ix;
     }
@@ -735,22 +747,54 @@ __global__ __launch_bounds__(PT) void qrcp_persist_kernel(const DevProb* __restr
   for (int i = 0; i < dp.kmax; ++i) {
     if (!gather(i)) return;
     const double best = s_best;
-    const int p = s_p;
+    // uniform: a scalar base address for the winner's slot below
+    const int p = __builtin_amdgcn_readfirstlane(s_p);
     if (i == 0) nu0 = best;
     if (best <= 0.0 || best <= rtol * nu0) break;
     if (dp.p.kfail >= 0 && i > dp.p.kfail && m > d) break;
     const int gp = p / CPG;  // the workgroup that published column p
-    const double* xp = w.cbuf + ((long long)(i & 1) * nslot + dp.g0 + gp) * ldcb;
-    // the winner's rows i..d-1 into LDS (zero elsewhere), loads in flight together
+    const unsigned long long* xp = w.cbuf + ((long long)(i & 1) * nslot + dp.g0 + gp) * 2 * ldcb;
+    // the winner's rows i..d-1 into LDS (zero elsewhere), loads in flight
+    // together; a row whose words do not both carry this step's tag yet is
+    // loaded again (bounded)
+    {
+      const unsigned want = (unsigned)(i + 1);
+      unsigned long long wl[SU], wh[SU];
+      const char* xb = reinterpret_cast<const char*>(xp);
+      const char* xc = reinterpret_cast<const char*>(xp + ldcb);
+      // 32-bit byte offsets from the uniform bases: a scalar base plus one
+      // offset register per load, not a 64-bit address per load
+      auto at = [](const char* base, unsigned row) {
+        return reinterpret_cast<const unsigned long long*>(base + row * 8u);
+      };
 #pragma unroll
-    for (int t = 0; t < SU; ++t) {
-      const int r = tid + PT * t;
-      if (r >= T * 64) break;
-      const bool in = r >= i && r < d;
-      const double v = ld_dev(xp + (in ? r : i));
-      u[r] = in ? v : 0.0;
+      for (int t = 0; t < SU; ++t) {
+        const int r = tid + PT * t;
+        const unsigned rr = (r >= i && r < d) ? (unsigned)r : (unsigned)i;
+        wl[t] = ld_dev(at(xb, rr));
+        wh[t] = ld_dev(at(xc, rr));
+      }
+#pragma unroll
+      for (int t = 0; t < SU; ++t) {
+        const int r = tid + PT * t;
+        if (r >= T * 64) break;
+        const bool in = r >= i && r < d;
+        int spins = 0;
+        while (in && ((unsigned)(wl[t] >> 32) != want || (unsigned)(wh[t] >> 32) != want)) {
+          if ((++spins & 63) == 0 && (ld_dev(w.err) || spins >= kSpinLimit)) {
+            st_dev(w.err, 1);
+            s_ok = 0;
+            break;
+          }
+          __builtin_amdgcn_s_sleep(1);
+          wl[t] = ld_dev(at(xb, (unsigned)r));
+          wh[t] = ld_dev(at(xc, (unsigned)r));
+        }
+        u[r] = in ? __longlong_as_double((long long)((wh[t] << 32) | (wl[t] & 0xffffffffull))) : 0.0;
+      }
     }
     __syncthreads();
+    if (!s_ok) return;  // a wait timed out (flag raised for the whole problem)
     const double x0 = u[i];
     const double alpha = -copysign(best, x0);
     const double v0 = x0 - alpha;
@@ -949,7 +993,7 @@ size_t id_workspace_bytes(const IdProblem* probs, int nprob) {
   }
   const long long ns = std::min(tg, kCandSlots);
   return al(2 * tm * 8) + al(tm * 4) + al(tk * 8) + al(tk * 4) + 3 * al((size_t)nprob * 8) +
-         al(4) + al(2 * tg * 8) + al(2 * tg * 4) + al(2 * ns * ldcb_of(dm) * 8) + al(2 * ns * km * 8) +
+         al(4) + al(2 * tg * 8) + al(2 * tg * 4) + al(2 * ns * 2 * ldcb_of(dm) * 8) + al(2 * ns * km * 8) +
          al(4) + al(tw * 8) + 4096;
 }
 
@@ -1153,6 +1197,9 @@ static hipError_t run_persistent(std::vector<DevProb>& h, const std::vector<int>
     int kb = 1;  // the launch's records: steps 0..kb-1 of nwg workgroups, zeroed
     for (int q : batch) kb = std::max(kb, h[q].kmax);
     hipError_t e = hipMemsetAsync(w.rec, 0, (size_t)kb * nwg * 16, s);
+    // the launch's column slots (2 parities x nwg, two words per row): zero
+    // tags, so that nothing left by an earlier launch passes for this one's
+    if (e == hipSuccess) e = hipMemsetAsync(w.cbuf, 0, (size_t)2 * nwg * 2 * w.ldcb * 8, s);
     if (e == hipSuccess && done.empty()) e = hipMemsetAsync(w.err, 0, 4, s);
     if (e != hipSuccess) return e;
     Work wa = w;

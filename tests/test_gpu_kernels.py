@@ -116,12 +116,15 @@ def _slow_decay(d, m, seed, rate):
                                    [(900, 1100, 0.37, 15), (1000, 700, 0.0, 16)],
                                    [(700, 900, 0.37, 13), (650, 600, 0.0, 14)]], ids=["d2400", "d1000", "d700"])
 @pytest.mark.parametrize("path", ["auto", "persistent"])
-def test_id_batched_variant_problems(path, cases, monkeypatch):
+def test_id_batched_variant_problems(path, cases, monkeypatch, capfd):
     """The batch's largest d picks the persistent variant: above 2304 rows
     the one with the most rows per lane, at 1000 rows the 16-rows-per-lane
-    one, at 700 rows the 12-rows-per-lane one.  Same checks as below."""
+    one, at 700 rows the 12-rows-per-lane one.  Same checks as below, and
+    no bounded wait of a persistent launch gave up (the results would then
+    come from the per-step rerun)."""
     if path != "auto":
         monkeypatch.setenv("HSS_QRCP_PATH", path)
+    monkeypatch.setenv("HSS_VERBOSE", "1")
     rtol = 1e-6
     Ys, refs, mats = [], [], []
     for d, m, rate, seed in cases:
@@ -130,7 +133,9 @@ def test_id_batched_variant_problems(path, cases, monkeypatch):
         refs.append(interp.interpolative_decomposition(y, rtol))
         Ys.append(torch.from_numpy(np.ascontiguousarray(y.T)).cuda())
     print(f"id_batched variant: {len(cases)} problems, d max {max(c[0] for c in cases)}, path {path}", flush=True)
+    capfd.readouterr()
     got = P.hss_id_batched(Ys, rtol)
+    assert "persistent wait gave up" not in capfd.readouterr().err
     for (k, perm, E), ref, y, (d, m, rate, seed) in zip(got, refs, mats, cases):
         assert abs(k - ref.k) <= 1, (d, m, rate, k, ref.k)
         if rate >= 0.3:
@@ -185,16 +190,17 @@ def test_id_batched_tall_problems(path, tall_refs, monkeypatch):
 
 
 @pytest.mark.parametrize("path", ["auto", "step", "persistent"])
-def test_id_batched_large_problems(path, monkeypatch):
+def test_id_batched_large_problems(path, monkeypatch, capfd):
     """Problems on the large-problem paths (one launch per pivot step, or
     persistent launches with the columns in registers; "auto" lets the cost
     model choose): d up to 2100 rows, several workgroups per problem, more
     problems than are resident at once, and one full-rank factorization of 900
     pivot steps.  Pivots agree with the oracle while the norms are well
     separated; everywhere the rank agrees and the ID reproduces Y to its
-    tolerance."""
+    tolerance; no bounded wait of a persistent launch gave up."""
     if path != "auto":
         monkeypatch.setenv("HSS_QRCP_PATH", path)
+    monkeypatch.setenv("HSS_VERBOSE", "1")
     rtol = 1e-6
     cases = [(2100, 1100, 0.37, 1), (2100, 1100, 0.37, 2), (2100, 1100, 0.37, 3),
              (2100, 1100, 0.37, 4), (2100, 1100, 0.37, 5), (1000, 900, 0.0, 6),
@@ -206,7 +212,9 @@ def test_id_batched_large_problems(path, monkeypatch):
         refs.append(interp.interpolative_decomposition(y, rtol))
         Ys.append(torch.from_numpy(np.ascontiguousarray(y.T)).cuda())
     print(f"id_batched large: {len(cases)} problems, path {path}", flush=True)
+    capfd.readouterr()
     got = P.hss_id_batched(Ys, rtol)
+    assert "persistent wait gave up" not in capfd.readouterr().err
     for (k, perm, E), ref, y, (d, m, rate, seed) in zip(got, refs, mats, cases):
         assert abs(k - ref.k) <= 1, (d, m, rate, k, ref.k)
         if rate >= 0.3:  # separated norms: the same pivots and interpolation matrix
