@@ -75,6 +75,8 @@ struct Work {
   long long krec;    // max kmax: steps a persistent launch may publish
   unsigned long long* rec;  // 2 * nslots * kmax: one published candidate record per
                             // workgroup and step, zeroed before each persistent launch
+  long long rstride = 0;    // records per workgroup in a launch (its largest kmax): the
+                            // records of workgroup g are rec[2 (g rstride + step) ...]
   int* err;        // 1: a wait for a candidate timed out (persistent path)
   int give_up = 0; // nonzero: every wait gives up at once (tests of the rerun)
   double* W;     // sum(m * d)
@@ -543,9 +545,9 @@ __global__ __launch_bounds__(ST) void id_step_kernel(const DevProb* __restrict__
 // zero, so no row needs a bounds test inside the step loop).  Two
 // wavefronts share each SIMD and every value lives in architectural
 // registers.  After each step the workgroup publishes its best remaining
-// column: the values go to a column slot of its own (double-buffered by step
-// parity), then norm and index go to a 16-byte record of its own for that
-// step.  Every workgroup of the problem waits for the G records of the step,
+// column: norm and index go to a 16-byte record of its own for that step,
+// the values to a column slot of its own (double-buffered by step parity).
+// Every workgroup of the problem waits for the G records of the step,
 // reduces the same candidates the same way, reads the winner's published
 // values as the reflector and updates its own columns.  Per step, global
 // memory carries only the candidates and one column per workgroup.
@@ -561,11 +563,10 @@ __global__ __launch_bounds__(ST) void id_step_kernel(const DevProb* __restrict__
 //   bit flipped (never zero: norms are +0 or more, or -1 for no candidate)
 //   and (step + 1) << 32 | index.  A reader takes a record once both words
 //   are non-zero and the step matches.
-// - A published column value is split into two words, (step + 1) << 32 |
-//   low 32 bits and (step + 1) << 32 | high 32 bits.  The column slots are
-//   double-buffered by step parity, so a slot still holding the step before
-//   last shows a different tag; the reader of the winner's column loads
-//   every row again until both tags match the step.
+// - A column value is written as two words, (step + 1) << 32 | low 32 bits
+//   and (step + 1) << 32 | high 32 bits, so a slot still holding an earlier
+//   step's column shows a different tag; a reader loads every row again
+//   until both tags match the step.
 // Every wait is bounded: a workgroup that waits too long raises the error
 // flag and leaves, and so does every workgroup that sees the flag; the
 // factorization is then reported as failed and nothing is written back.
@@ -603,8 +604,6 @@ __global__ __launch_bounds__(PT) void qrcp_persist_kernel(const DevProb* __restr
   __shared__ int ri[PW];
   __shared__ double gv_s[PW];
   __shared__ int gi_s[PW];
-  __shared__ double s_best;
-  __shared__ int s_p;
   __shared__ int s_ok;
 
   const int q = wg_prob[blockIdx.x];
@@ -640,10 +639,15 @@ __global__ __launch_bounds__(PT) void qrcp_persist_kernel(const DevProb* __restr
   }
   if (tid == 0) s_ok = 1;
 
-  // publish this workgroup's best column for step i: norm, index, and the
-  // row slices from i / 64 on (the reader masks rows below i).  The owning
-  // wavefront writes the column and then the record (the first wavefront
-  // writes the record when the workgroup has no candidate left).
+  // publish this workgroup's best column for step i: norm and index in a
+  // record, and the row slices from i / 64 on (the reader masks rows below
+  // i).  The owning wavefront writes the record and then the column (the
+  // first wavefront writes the record when the workgroup has no candidate
+  // left): the record does not queue behind the column's stores, and the
+  // readers need the column only after they have reduced all records (7.8
+  // against 8.7 us per step on two 1664 x 2686 problems).  Writing only the
+  // winner's column, after the exchange, took longer (9.3 us per step): the
+  // records arrived 1 us sooner, the column 2 us later.
   auto publish = [&](int i) __attribute__((always_inline)) {  // y must stay in registers
     if (lane == 0) {
       rv[wave] = bv;
@@ -654,16 +658,21 @@ __global__ __launch_bounds__(PT) void qrcp_persist_kernel(const DevProb* __restr
     int ix = ri[0];
 #pragma unroll
     for (int t = 1; t < PW; ++t) better(v, ix, rv[t], ri[t]);
-    const long long slot = (long long)(i & 1) * nslot + blockIdx.x;
-    const unsigned long long tag = (unsigned long long)(i + 1) << 32;
     const bool own = ix >= jb && ix < jb + C;  // uniform within a wavefront
+    if (lane == 0 && (own || (ix == INT_MAX && wave == 0))) {
+      unsigned long long* r = w.rec + 2 * ((long long)blockIdx.x * w.rstride + i);
+      st_dev(r, (unsigned long long)__double_as_longlong(v) ^ kSignBit);
+      st_dev(r + 1, ((unsigned long long)(i + 1) << 32) | (unsigned)ix);
+    }
     if (own) {
       // uniform bases and one 32-bit lane offset, formed here (not hoisted
       // out of the step loop as T live addresses)
+      const long long slot = (long long)(i & 1) * nslot + blockIdx.x;
       char* blo = reinterpret_cast<char*>(w.cbuf + slot * 2 * ldcb);
       char* bhi = reinterpret_cast<char*>(w.cbuf + slot * 2 * ldcb + ldcb);
       unsigned vo = (unsigned)lane * 8u;
       asm volatile("" : "+v"(vo));
+      const unsigned long long tag = (unsigned long long)(i + 1) << 32;
       const int ti = i >> 6;
 #pragma unroll
       for (int c = 0; c < C; ++c) {
@@ -681,16 +690,16 @@ __global__ __launch_bounds__(PT) void qrcp_persist_kernel(const DevProb* __restr
         }
       }
     }
-    if (lane == 0 && (own || (ix == INT_MAX && wave == 0))) {
-      unsigned long long* r = w.rec + 2 * ((long long)i * nslot + blockIdx.x);
-      st_dev(r, (unsigned long long)__double_as_longlong(v) ^ kSignBit);
-      st_dev(r + 1, ((unsigned long long)(i + 1) << 32) | (unsigned)ix);
-    }
   };
 
   // wait for the problem's G candidates of step i; false on a timeout
-  auto gather = [&](int i) __attribute__((always_inline)) -> bool {
-    const unsigned long long* recs = w.rec + 2 * ((long long)i * nslot + dp.g0);
+  auto gather = [&](int i, double& best, int& p) __attribute__((always_inline)) -> bool {
+    // workgroup-major records: the G records of one step lie in G different
+    // cache lines (and memory channels), not packed into a few lines that
+    // every poller of the problem would hit (2.5 us from the last record to
+    // its readers with packed records, against a 0.5 us one-way latency)
+    const unsigned long long* recs = w.rec + 2 * ((long long)dp.g0 * w.rstride + i);
+    const long long rs2 = 2 * w.rstride;
     const unsigned long long want = (unsigned long long)(i + 1);
     double gv = -1.0;
     int gi = INT_MAX;
@@ -702,9 +711,10 @@ __global__ __launch_bounds__(PT) void qrcp_persist_kernel(const DevProb* __restr
     for (int t = tid; t < dp.G && ok; t += PT) {
       int spins = 0;
       unsigned long long a, b;
+      const unsigned long long* rt = recs + (long long)t * rs2;
       while (true) {
-        a = ld_dev(recs + 2 * t);
-        b = ld_dev(recs + 2 * t + 1);
+        a = ld_dev(rt);
+        b = ld_dev(rt + 1);
         if (a != 0 && (b >> 32) == want) break;
         if ((++spins & 63) == 0) {
           if (ld_dev(w.err)) {
@@ -730,14 +740,13 @@ __global__ __launch_bounds__(PT) void qrcp_persist_kernel(const DevProb* __restr
       gi_s[wave] = gi;
     }
     __syncthreads();
-    if (tid == 0) {
-      double v = gv_s[0];
-      int ix = gi_s[0];
-      for (int t = 1; t < PW; ++t) better(v, ix, gv_s[t], gi_s[t]);
-      s_best = v;
-      s_p = ix;
-    }
-    __syncthreads();
+    // every thread reduces the PW wavefront results itself (no second barrier)
+    double v = gv_s[0];
+    int ix = gi_s[0];
+#pragma unroll
+    for (int t = 1; t < PW; ++t) better(v, ix, gv_s[t], gi_s[t]);
+    best = v;
+    p = ix;
     return s_ok != 0;
   };
 
@@ -745,10 +754,11 @@ __global__ __launch_bounds__(PT) void qrcp_persist_kernel(const DevProb* __restr
   double nu0 = 0.0;
   int k = 0;
   for (int i = 0; i < dp.kmax; ++i) {
-    if (!gather(i)) return;
-    const double best = s_best;
+    double best;
+    int p;
+    if (!gather(i, best, p)) return;
     // uniform: a scalar base address for the winner's slot below
-    const int p = __builtin_amdgcn_readfirstlane(s_p);
+    p = __builtin_amdgcn_readfirstlane(p);
     if (i == 0) nu0 = best;
     if (best <= 0.0 || best <= rtol * nu0) break;
     if (dp.p.kfail >= 0 && i > dp.p.kfail && m > d) break;
@@ -756,7 +766,10 @@ __global__ __launch_bounds__(PT) void qrcp_persist_kernel(const DevProb* __restr
     const unsigned long long* xp = w.cbuf + ((long long)(i & 1) * nslot + dp.g0 + gp) * 2 * ldcb;
     // the winner's rows i..d-1 into LDS (zero elsewhere), loads in flight
     // together; a row whose words do not both carry this step's tag yet is
-    // loaded again (bounded)
+    // loaded again (bounded).  LDS receives the Householder vector
+    // v = x - alpha e_i unscaled: row i holds v0 = x0 - alpha, formed by the
+    // thread that loads it (alpha = -sign(x0) ||x||, so sign(v0) = sign(x0)
+    // and every thread recovers alpha from v0).
     {
       const unsigned want = (unsigned)(i + 1);
       unsigned long long wl[SU], wh[SU];
@@ -790,23 +803,17 @@ __global__ __launch_bounds__(PT) void qrcp_persist_kernel(const DevProb* __restr
           wl[t] = ld_dev(at(xb, (unsigned)r));
           wh[t] = ld_dev(at(xc, (unsigned)r));
         }
-        u[r] = in ? __longlong_as_double((long long)((wh[t] << 32) | (wl[t] & 0xffffffffull))) : 0.0;
+        const double x = __longlong_as_double((long long)((wh[t] << 32) | (wl[t] & 0xffffffffull)));
+        u[r] = in ? (r == i ? x + copysign(best, x) : x) : 0.0;
       }
     }
     __syncthreads();
     if (!s_ok) return;  // a wait timed out (flag raised for the whole problem)
-    const double x0 = u[i];
-    const double alpha = -copysign(best, x0);
-    const double v0 = x0 - alpha;
-    const double tau = -v0 / alpha;
-    const double inv_v0 = 1.0 / v0;
-    __syncthreads();  // x0 read before row i is rewritten
-#pragma unroll
-    for (int t = 0; t < SU; ++t) {
-      const int r = tid + PT * t;
-      if (r >= T * 64) break;
-      u[r] = (r == i) ? 1.0 : u[r] * inv_v0;
-    }
+    // u is only read from here until the next step's loads, which come after
+    // the barriers of publish and gather
+    const double v0 = u[i];
+    const double alpha = -copysign(best, v0);
+    const double beta = -1.0 / (alpha * v0);  // H = I - beta v v^T
     if (p >= jb && p < jb + C) {
       sel |= 1u << (p - jb);
       // the owner marks its column: the same wavefront wrote its -1, and
@@ -817,7 +824,6 @@ __global__ __launch_bounds__(PT) void qrcp_persist_kernel(const DevProb* __restr
       w.alpha[dp.aoff + i] = alpha;
       w.piv[dp.aoff + i] = p;
     }
-    __syncthreads();
     // rows below i are finished: groups of slices below i/64 are skipped,
     // and u is zero on the finished rows of the groups that run.  The C
     // columns go through each phase together, so their dependency chains
@@ -843,7 +849,7 @@ __global__ __launch_bounds__(PT) void qrcp_persist_kernel(const DevProb* __restr
 #pragma unroll
     for (int c = 0; c < C; ++c) {
       const bool live = !((sel >> c) & 1u) && jb + c < m;  // pivots stay as they are
-      f[c] = live ? tau * f[c] : 0.0;
+      f[c] = live ? beta * f[c] : 0.0;
     }
     // norms of the rows below i: slice i/64 counts the lanes past i only
     double s2[C];
@@ -1194,7 +1200,7 @@ static hipError_t run_persistent(std::vector<DevProb>& h, const std::vector<int>
     const DevProb* dprobs = static_cast<const DevProb*>(st.push(h.data(), sizeof(DevProb) * h.size()));
     const int* dwg = static_cast<const int*>(st.push(wgp.data(), wgp.size() * 4));
     if (!dprobs || !dwg) return hipErrorOutOfMemory;
-    int kb = 1;  // the launch's records: steps 0..kb-1 of nwg workgroups, zeroed
+    int kb = 1;  // the launch's records: steps 0..kb-1 of nwg workgroups (kb apart), zeroed
     for (int q : batch) kb = std::max(kb, h[q].kmax);
     hipError_t e = hipMemsetAsync(w.rec, 0, (size_t)kb * nwg * 16, s);
     // the launch's column slots (2 parities x nwg, two words per row): zero
@@ -1203,6 +1209,7 @@ static hipError_t run_persistent(std::vector<DevProb>& h, const std::vector<int>
     if (e == hipSuccess && done.empty()) e = hipMemsetAsync(w.err, 0, 4, s);
     if (e != hipSuccess) return e;
     Work wa = w;
+    wa.rstride = kb;
     {
       const char* gu = std::getenv("HSS_QRCP_GIVE_UP");
       wa.give_up = (gu && gu[0] && gu[0] != '0') ? 1 : 0;
