@@ -134,13 +134,49 @@ void carve(const IdProblem* probs, int nprob, void* base, Work& w, long long& tm
 
 // wavefront sums of N values at once: butterfly over lanes, the first four
 // levels by DPP (quad permutes, then half-row and row mirrors), the last two
-// by cross-row shuffles.  Every lane ends with the same sums.
+// across rows by gfx950's v_permlane16_swap / v_permlane32_swap (register
+// swaps between the rows of two registers, no LDS crossbar).  Every lane
+// ends with the same sums.
 template <int CTRL>
 __device__ __forceinline__ double dpp_d(double v) {
   const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
   const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
   return __hiloint2double(hi, lo);
 }
+// A lane's own value and that of its partner across 16 lanes (W = 16: rows
+// 0 <-> 1, 2 <-> 3) or 32 lanes (W = 32: the two halves), in an order that
+// depends on the lane: swapping the rows of two copies of v leaves one copy
+// with the even rows (lower half) twice and the other with the odd rows
+// (upper half) twice.
+template <int W>
+__device__ __forceinline__ void cross_pair(double v, double& a, double& b) {
+  unsigned alo = (unsigned)__double2loint(v), ahi = (unsigned)__double2hiint(v);
+  unsigned blo = alo, bhi = ahi;
+  if (W == 16) {
+    const auto l = __builtin_amdgcn_permlane16_swap(alo, blo, false, false);
+    const auto h = __builtin_amdgcn_permlane16_swap(ahi, bhi, false, false);
+    alo = l[0], blo = l[1], ahi = h[0], bhi = h[1];
+  } else {
+    const auto l = __builtin_amdgcn_permlane32_swap(alo, blo, false, false);
+    const auto h = __builtin_amdgcn_permlane32_swap(ahi, bhi, false, false);
+    alo = l[0], blo = l[1], ahi = h[0], bhi = h[1];
+  }
+  a = __hiloint2double((int)ahi, (int)alo);
+  b = __hiloint2double((int)bhi, (int)blo);
+}
+template <int W>
+__device__ __forceinline__ void cross_pair_i(int v, int& a, int& b) {
+  unsigned x = (unsigned)v, y = x;
+  const auto r = W == 16 ? __builtin_amdgcn_permlane16_swap(x, y, false, false)
+                         : __builtin_amdgcn_permlane32_swap(x, y, false, false);
+  a = (int)r[0];
+  b = (int)r[1];
+}
+// The last two levels either by cross-row shuffles (ds_bpermute, through the
+// LDS crossbar) or by the permlane swaps (VALU).  The swaps serve the
+// persistent kernel (IDs 484 -> 471 ms per gauss65536 compression); the
+// reduction-heavy small-problem kernel runs 40 % slower with them and keeps
+// the shuffles.
 template <int N>
 __device__ __forceinline__ void wave_sum_n(double (&v)[N]) {
 #pragma unroll
@@ -155,6 +191,30 @@ __device__ __forceinline__ void wave_sum_n(double (&v)[N]) {
   for (int c = 0; c < N; ++c) v[c] += __shfl_xor(v[c], 16, 64);
 #pragma unroll
   for (int c = 0; c < N; ++c) v[c] += __shfl_xor(v[c], 32, 64);
+}
+template <int N>
+__device__ __forceinline__ void wave_sum_n_pl(double (&v)[N]) {
+#pragma unroll
+  for (int c = 0; c < N; ++c) v[c] += dpp_d<0xB1>(v[c]);
+#pragma unroll
+  for (int c = 0; c < N; ++c) v[c] += dpp_d<0x4E>(v[c]);
+#pragma unroll
+  for (int c = 0; c < N; ++c) v[c] += dpp_d<0x141>(v[c]);
+#pragma unroll
+  for (int c = 0; c < N; ++c) v[c] += dpp_d<0x140>(v[c]);
+  // own + partner in either order: the same sum (addition commutes)
+#pragma unroll
+  for (int c = 0; c < N; ++c) {
+    double a, b;
+    cross_pair<16>(v[c], a, b);
+    v[c] = a + b;
+  }
+#pragma unroll
+  for (int c = 0; c < N; ++c) {
+    double a, b;
+    cross_pair<32>(v[c], a, b);
+    v[c] = a + b;
+  }
 }
 
 // wavefront sum of one value, by the same butterfly (four DPP levels, two
@@ -186,6 +246,23 @@ __device__ __forceinline__ void wave_argmax(double& bv, int& bi) {
   better(bv, bi, __shfl_xor(bv, 16, 64), __shfl_xor(bi, 16, 64));
   better(bv, bi, __shfl_xor(bv, 32, 64), __shfl_xor(bi, 32, 64));
 }
+__device__ __forceinline__ void wave_argmax_pl(double& bv, int& bi) {
+  better(bv, bi, dpp_d<0xB1>(bv), dpp_i<0xB1>(bi));
+  better(bv, bi, dpp_d<0x4E>(bv), dpp_i<0x4E>(bi));
+  better(bv, bi, dpp_d<0x141>(bv), dpp_i<0x141>(bi));
+  better(bv, bi, dpp_d<0x140>(bv), dpp_i<0x140>(bi));
+  // across rows: the better of {own, partner} in either order (a total order)
+  double av, cv;
+  int ai, ci;
+  cross_pair<16>(bv, av, cv);
+  cross_pair_i<16>(bi, ai, ci);
+  bv = av, bi = ai;
+  better(bv, bi, cv, ci);
+  cross_pair<32>(bv, av, cv);
+  cross_pair_i<32>(bi, ai, ci);
+  bv = av, bi = ai;
+  better(bv, bi, cv, ci);
+}
 
 // ---------------------------------------------------------------------------
 // small problems: one workgroup, matrix in registers
@@ -199,8 +276,6 @@ __global__ __launch_bounds__(RW * 64) void qrcp_reg_kernel(const DevProb* __rest
   __shared__ int step_s[RW * CPW];
   __shared__ double red_v[RW];
   __shared__ int red_i[RW];
-  __shared__ double s_best;
-  __shared__ int s_p;
 
   const int q = list[blockIdx.x];
   const DevProb dp = probs[q];
@@ -241,17 +316,15 @@ __global__ __launch_bounds__(RW * 64) void qrcp_reg_kernel(const DevProb* __rest
       red_i[wave] = bi;
     }
     __syncthreads();
-    if (tid == 0) {
-      double v = red_v[0];
-      int ix = red_i[0];
-      for (int q2 = 1; q2 < RW; ++q2) better(v, ix, red_v[q2], red_i[q2]);
-      s_best = v;
-      s_p = ix;
-    }
-    __syncthreads();
+    // every thread reduces the RW wavefront results (no second barrier);
+    // red_v / red_i are written again only after this step's later barriers
+    double sb = red_v[0];
+    int sp = red_i[0];
+#pragma unroll
+    for (int q2 = 1; q2 < RW; ++q2) better(sb, sp, red_v[q2], red_i[q2]);
     const bool nopiv = P.nfac > 0;
-    const double best = nopiv ? nrm_s[i] : s_best;
-    const int p = nopiv ? i : s_p;
+    const double best = nopiv ? nrm_s[i] : sb;
+    const int p = nopiv ? i : sp;
     if (i == 0) nu0 = best;
     if (!nopiv && (best <= 0.0 || best <= rtol * nu0)) break;
     if (!nopiv && P.kfail >= 0 && i > P.kfail && m > d) break;
@@ -732,7 +805,7 @@ __global__ __launch_bounds__(PT) void qrcp_persist_kernel(const DevProb* __restr
       if (ok) better(gv, gi, __longlong_as_double((long long)(a ^ kSignBit)), (int)(unsigned)b);
     }
     if (!ok) s_ok = 0;
-    wave_argmax(gv, gi);
+    wave_argmax_pl(gv, gi);
     // gv_s / gi_s, not rv / ri: publish has no closing barrier, so another
     // wavefront may still be reading rv / ri
     if (lane == 0) {
@@ -844,7 +917,7 @@ __global__ __launch_bounds__(PT) void qrcp_persist_kernel(const DevProb* __restr
         for (int c = 0; c < C; ++c) f[c] = fma(ut, y[c][t], f[c]);
       }
     }
-    wave_sum_n<C>(f);
+    wave_sum_n_pl<C>(f);
     asm volatile("" ::: "memory");  // u is read again below rather than kept in registers
 #pragma unroll
     for (int c = 0; c < C; ++c) {
@@ -873,7 +946,7 @@ __global__ __launch_bounds__(PT) void qrcp_persist_kernel(const DevProb* __restr
         }
       }
     }
-    wave_sum_n<C>(s2);
+    wave_sum_n_pl<C>(s2);
     bv = -1.0;
     bi = INT_MAX;
 #pragma unroll
