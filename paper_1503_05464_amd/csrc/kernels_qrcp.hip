@@ -80,6 +80,8 @@ struct Work {
   int* err;        // 1: a wait for a candidate timed out (persistent path)
   int give_up = 0; // nonzero: every wait gives up at once (tests of the rerun)
   double* W;     // sum(m * d)
+  double* W2;    // sum(m * d) of the problems factored in place without pivoting:
+                 // their persistent launches write here, then copy back
 };
 
 size_t al(size_t b) { return (b + 255) / 256 * 256; }
@@ -93,6 +95,15 @@ long long ldcb_of(long long dmax) { return (dmax + 511) / 512 * 512; }
 int kmax_of(const IdProblem& p) {
   const int k = std::min(p.m, p.d);
   return p.nfac > 0 ? std::min(p.nfac, k) : k;
+}
+
+// a problem factored without pivoting in place (W == Y, the ULV's LQ)
+static bool is_inplace_nopiv(const IdProblem& p) { return p.nfac > 0 && p.W != nullptr && p.W == p.Y; }
+static long long inplace_nopiv_doubles(const IdProblem* probs, int nprob) {
+  long long t = 0;
+  for (int q = 0; q < nprob; ++q)
+    if (is_inplace_nopiv(probs[q])) t += (long long)probs[q].m * probs[q].d;
+  return t;
 }
 
 void carve(const IdProblem* probs, int nprob, void* base, Work& w, long long& tm, long long& tk,
@@ -130,6 +141,7 @@ void carve(const IdProblem* probs, int nprob, void* base, Work& w, long long& tm
   w.rec = reinterpret_cast<unsigned long long*>(take(2 * w.nslots * km * 8));
   w.err = reinterpret_cast<int*>(take(4));
   w.W = reinterpret_cast<double*>(take(tw * 8));
+  w.W2 = reinterpret_cast<double*>(take(inplace_nopiv_doubles(probs, nprob) * 8));
 }
 
 // wavefront sums of N values at once: butterfly over lanes, the first four
@@ -684,6 +696,14 @@ __global__ __launch_bounds__(PT) void qrcp_persist_kernel(const DevProb* __restr
   const int m = dp.p.m, d = dp.p.d;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const bool leader = ((int)blockIdx.x == dp.g0 && tid == 0);
+  // no pivoting (Householder QR of the first nfac columns, the others only
+  // transformed): step i's pivot is column i, the only candidate published.
+  // Every workgroup still publishes a record every step and waits for all
+  // of them: that exchange keeps the workgroups within one step of each
+  // other, which the double-buffered column slots need (an owner of
+  // consecutive columns would otherwise run ahead and overwrite a slot that
+  // a slower workgroup has yet to read).
+  const bool nopiv = dp.p.nfac > 0;
   constexpr int CPG = PW * C;  // columns per workgroup
   const int jb = (blockIdx.x - dp.g0) * CPG + wave * C;
   int* __restrict__ step = w.step + dp.off;
@@ -706,7 +726,7 @@ __global__ __launch_bounds__(PT) void qrcp_persist_kernel(const DevProb* __restr
       y[c][t] = v;
       s = fma(v, v, s);
     }
-    if (j < m) better(bv, bi, sqrt(wave_sum(s)), j);
+    if (nopiv ? j == 0 : j < m) better(bv, bi, sqrt(wave_sum(s)), j);
     if (j < m && lane == 0) step[j] = -1;
     asm volatile("" ::: "memory");  // one column's loads in flight at a time
   }
@@ -833,8 +853,8 @@ __global__ __launch_bounds__(PT) void qrcp_persist_kernel(const DevProb* __restr
     // uniform: a scalar base address for the winner's slot below
     p = __builtin_amdgcn_readfirstlane(p);
     if (i == 0) nu0 = best;
-    if (best <= 0.0 || best <= rtol * nu0) break;
-    if (dp.p.kfail >= 0 && i > dp.p.kfail && m > d) break;
+    if (!nopiv && (best <= 0.0 || best <= rtol * nu0)) break;
+    if (!nopiv && dp.p.kfail >= 0 && i > dp.p.kfail && m > d) break;
     const int gp = p / CPG;  // the workgroup that published column p
     const unsigned long long* xp = w.cbuf + ((long long)(i & 1) * nslot + dp.g0 + gp) * 2 * ldcb;
     // the winner's rows i..d-1 into LDS (zero elsewhere), loads in flight
@@ -886,7 +906,8 @@ __global__ __launch_bounds__(PT) void qrcp_persist_kernel(const DevProb* __restr
     // the barriers of publish and gather
     const double v0 = u[i];
     const double alpha = -copysign(best, v0);
-    const double beta = -1.0 / (alpha * v0);  // H = I - beta v v^T
+    // H = I - beta v v^T (a zero column, only without pivoting: H = I)
+    const double beta = best > 0.0 ? -1.0 / (alpha * v0) : 0.0;
     if (p >= jb && p < jb + C) {
       sel |= 1u << (p - jb);
       // the owner marks its column: the same wavefront wrote its -1, and
@@ -951,7 +972,7 @@ __global__ __launch_bounds__(PT) void qrcp_persist_kernel(const DevProb* __restr
     bi = INT_MAX;
 #pragma unroll
     for (int c = 0; c < C; ++c)
-      if (!((sel >> c) & 1u) && jb + c < m) better(bv, bi, sqrt(s2[c]), jb + c);
+      if (nopiv ? jb + c == i + 1 : (!((sel >> c) & 1u) && jb + c < m)) better(bv, bi, sqrt(s2[c]), jb + c);
     k = i + 1;
     if (i + 1 < dp.kmax) publish(i + 1);
   }
@@ -1073,7 +1094,7 @@ size_t id_workspace_bytes(const IdProblem* probs, int nprob) {
   const long long ns = std::min(tg, kCandSlots);
   return al(2 * tm * 8) + al(tm * 4) + al(tk * 8) + al(tk * 4) + 3 * al((size_t)nprob * 8) +
          al(4) + al(2 * tg * 8) + al(2 * tg * 4) + al(2 * ns * 2 * ldcb_of(dm) * 8) + al(2 * ns * km * 8) +
-         al(4) + al(tw * 8) + 4096;
+         al(4) + al(tw * 8) + al(inplace_nopiv_doubles(probs, nprob) * 8) + 4096;
 }
 
 // Register-resident classes (wavefronts, columns per wavefront, rows per
@@ -1133,9 +1154,22 @@ static hipError_t run_persistent(std::vector<DevProb>& h, const std::vector<int>
                                  std::vector<char>& skipped, int& npersist, int& nlaunch) {
   int dmax = 0;
   std::vector<int> cand, second;
+  // problems factored in place without pivoting write to W2 (a rerun after
+  // a timed-out wait needs the input untouched) and are copied back after
+  std::vector<long long> off2(h.size(), -1);
+  std::vector<double*> w_orig(h.size(), nullptr);
+  std::vector<long long> ld_orig(h.size(), 0);
+  {
+    long long o = 0;
+    for (size_t q = 0; q < h.size(); ++q)
+      if (is_inplace_nopiv(h[q].p)) {
+        off2[q] = o;
+        o += (long long)h[q].p.m * h[q].p.d;
+      }
+  }
   for (int q : large) {
     const IdProblem& p = h[q].p;
-    if (p.nfac > 0 || h[q].kmax == 0 || p.d > 64 * 40) rest.push_back(q);
+    if (h[q].kmax == 0 || p.d > 64 * 40) rest.push_back(q);
     else {
       // the first side of each node ahead of every second side: when the
       // batch needs several launches, a node whose first side fails skips
@@ -1266,6 +1300,12 @@ static hipError_t run_persistent(std::vector<DevProb>& h, const std::vector<int>
       for (int t = 0; t < G; ++t) wgp.push_back(q);
       nwg += G;
       batch.push_back(q);
+      if (off2[q] >= 0 && !w_orig[q]) {  // in place without pivoting: write to W2
+        w_orig[q] = h[q].p.W;
+        ld_orig[q] = h[q].p.ldw;
+        h[q].p.W = w.W2 + off2[q];
+        h[q].p.ldw = h[q].p.d;
+      }
     }
     i0 = i1;
     if (batch.empty()) continue;
@@ -1304,7 +1344,25 @@ static hipError_t run_persistent(std::vector<DevProb>& h, const std::vector<int>
       h[q].G = 0;
     }
   }
-  if (done.empty()) return hipSuccess;
+  // the in-place problems back to their own W: those launched and finished
+  // are copied there (on a timeout their untouched inputs are factored
+  // again in place, as are problems whose launch failed)
+  auto restore = [&](bool copy) -> hipError_t {
+    for (size_t q = 0; q < h.size(); ++q) {
+      if (!w_orig[q]) continue;
+      if (copy && launched[q]) {
+        const hipError_t ce =
+            hipMemcpy2DAsync(w_orig[q], (size_t)ld_orig[q] * 8, h[q].p.W, (size_t)h[q].p.ldw * 8,
+                             (size_t)h[q].p.d * 8, (size_t)h[q].p.m, hipMemcpyDeviceToDevice, s);
+        if (ce != hipSuccess) return ce;
+      }
+      h[q].p.W = w_orig[q];
+      h[q].p.ldw = ld_orig[q];
+      w_orig[q] = nullptr;
+    }
+    return hipSuccess;
+  };
+  if (done.empty()) return restore(false);
   // a wait that timed out (workgroups not all resident at once): the inputs
   // are untouched, so the per-step path factors those problems again
   int herr = 0;
@@ -1327,7 +1385,7 @@ static hipError_t run_persistent(std::vector<DevProb>& h, const std::vector<int>
     npersist = 0;
     nlaunch = 0;
   }
-  return hipSuccess;
+  return restore(herr == 0);
 }
 
 static size_t round_up_256(size_t b) { return (b + 255) / 256 * 256; }

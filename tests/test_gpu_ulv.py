@@ -45,15 +45,25 @@ CASES = {
 }
 
 
+@pytest.mark.parametrize("path", ["auto", "step", "persistent"])
 @pytest.mark.parametrize("case", sorted(CASES))
-def test_ulv_on_oracle_generators(case):
+def test_ulv_on_oracle_generators(case, path, monkeypatch, capfd):
+    """The LQ factorizations of the ULV factor (Householder QR without
+    pivoting) on each large-problem path: one launch per step, or the
+    persistent kernel (which writes to a workspace and copies back, and must
+    not give up its bounded waits)."""
+    if path != "auto":
+        monkeypatch.setenv("HSS_QRCP_PATH", path)
+    monkeypatch.setenv("HSS_VERBOSE", "1")
     make, kw = CASES[case]
     A = make()
     Ho = ohss.compress(A, ohss.Options(**kw))
     F = oulv.factor(Ho)
     h = _import(Ho)
-    print(f"ulv {case}: n={A.shape[0]}", flush=True)
+    print(f"ulv {case}: n={A.shape[0]}, path {path}", flush=True)
+    capfd.readouterr()
     P.hss_factor(h)
+    assert "persistent wait gave up" not in capfd.readouterr().err
     cond = np.linalg.cond(ohss.to_dense(Ho))
     for nrhs in (1, 3):
         b = W.normal_rhs(A.shape[0], nrhs, 7)
@@ -108,8 +118,9 @@ def test_compress_factor_solve_circle16384():
     assert float(torch.linalg.norm(r)) / (anorm * float(torch.linalg.norm(x))) <= 10 * cfg["rtol"]
 
 
+@pytest.mark.parametrize("path", ["auto", "step", "persistent"])
 @pytest.mark.parametrize("n", [1500, 3000])
-def test_large_root_lu(n):
+def test_large_root_lu(n, path, monkeypatch, capfd):
     """A matrix without low-rank structure (random plus a diagonal shift):
     the off-diagonal ranks are full, so the root block has about n rows and
     its partial-pivoting LU takes the register panel kernel with one, two
@@ -117,11 +128,16 @@ def test_large_root_lu(n):
     solve must reproduce x with the accuracy of a dense LU."""
     g = np.random.default_rng(n)
     A = torch.from_numpy(g.standard_normal((n, n)) / np.sqrt(n) + 3.0 * np.eye(n)).cuda()
-    print(f"large root LU: n={n}", flush=True)
+    print(f"large root LU: n={n}, path {path}", flush=True)
     h = P.hss_compress(A, rtol=1e-13, d0=n // 2 + 128, dd=64, d_max=n + 256, leaf_size=n // 4, p_margin=16)
     st = P.hss_stats(h)
     assert st["converged"]
+    if path != "auto":  # the factor's QRs (leaves of n/4 rows: the large-problem paths)
+        monkeypatch.setenv("HSS_QRCP_PATH", path)
+    monkeypatch.setenv("HSS_VERBOSE", "1")
+    capfd.readouterr()
     P.hss_factor(h)
+    assert "persistent wait gave up" not in capfd.readouterr().err
     xs = torch.from_numpy(g.uniform(-1, 1, (n, 3))).cuda()
     b = A @ xs
     x = P.hss_solve(h, b)
