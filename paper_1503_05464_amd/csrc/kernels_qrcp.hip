@@ -415,6 +415,198 @@ __global__ __launch_bounds__(RW * 64) void qrcp_reg_kernel(const DevProb* __rest
 }
 
 // ---------------------------------------------------------------------------
+// small problems, 16 lanes per column: one workgroup of eight wavefronts per
+// problem.  Each 16-lane row of a wavefront holds one column (lane l16 of
+// the row has rows l16, l16 + 16, ..., R16 per column), so a wavefront holds
+// four columns per group and CG groups.  A column's dot products and norms
+// are sums over its 16 lanes -- four DPP levels that serve the four columns
+// of a group at once -- instead of over 64 lanes per column (the reductions
+// were the bulk of the instructions of a step).  Column j of group g is
+// 4 (g RW + wave) + row.  Two barriers per step: the pivot candidates come
+// from the norms in registers, and the reflector goes through LDS.
+// ---------------------------------------------------------------------------
+template <int N>
+__device__ __forceinline__ void row16_sum_n(double (&v)[N]) {
+#pragma unroll
+  for (int c = 0; c < N; ++c) v[c] += dpp_d<0xB1>(v[c]);  // quad_perm [1,0,3,2]
+#pragma unroll
+  for (int c = 0; c < N; ++c) v[c] += dpp_d<0x4E>(v[c]);  // quad_perm [2,3,0,1]
+#pragma unroll
+  for (int c = 0; c < N; ++c) v[c] += dpp_d<0x141>(v[c]);  // row_half_mirror
+#pragma unroll
+  for (int c = 0; c < N; ++c) v[c] += dpp_d<0x140>(v[c]);  // row_mirror
+}
+
+template <int CG, int R16>
+__global__ __launch_bounds__(512) void qrcp_reg16_kernel(const DevProb* __restrict__ probs,
+                                                        const int* __restrict__ list, double rtol, Work w) {
+  constexpr int RW = 8, NC = 4 * RW * CG;  // wavefronts, columns held
+  __shared__ double xcol[R16 * 16];
+  __shared__ double nrm_s[NC];
+  __shared__ int step_s[NC];
+  __shared__ double red_v[RW];
+  __shared__ int red_i[RW];
+
+  const int q = list[blockIdx.x];
+  const DevProb dp = probs[q];
+  const IdProblem& P = dp.p;
+  const int m = P.m, d = P.d;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int l16 = lane & 15, rq = lane >> 4;
+  const bool nopiv = P.nfac > 0;
+
+  double y[CG][R16];
+  double nv[CG];
+  {
+    double s[CG];
+#pragma unroll
+    for (int g = 0; g < CG; ++g) {
+      const int j = 4 * (g * RW + wave) + rq;
+      s[g] = 0.0;
+#pragma unroll
+      for (int t = 0; t < R16; ++t) {
+        const int r = l16 + 16 * t;
+        const double v = (j < m && r < d) ? P.Y[(long long)j * P.ldy + r] : 0.0;
+        y[g][t] = v;
+        s[g] = fma(v, v, s[g]);
+      }
+    }
+    row16_sum_n<CG>(s);
+#pragma unroll
+    for (int g = 0; g < CG; ++g) {
+      const int j = 4 * (g * RW + wave) + rq;
+      nv[g] = sqrt(s[g]);
+      if (l16 == 0 && j < m) {
+        nrm_s[j] = nv[g];
+        step_s[j] = -1;
+      }
+    }
+  }
+  unsigned sel = 0;  // groups whose column (of this lane's row) is a pivot
+  const int kmax = dp.kmax;
+  double nu0 = 0.0;
+  int k = 0;
+  __syncthreads();
+  for (int i = 0; i < kmax; ++i) {
+    // pivot candidates from the norms in registers: this row's columns, then
+    // across the four rows of the wavefront, then across wavefronts
+    double bv = -1.0;
+    int bi = INT_MAX;
+#pragma unroll
+    for (int g = 0; g < CG; ++g) {
+      const int j = 4 * (g * RW + wave) + rq;
+      if (j < m && !((sel >> g) & 1u)) better(bv, bi, nv[g], j);
+    }
+    better(bv, bi, __shfl_xor(bv, 16, 64), __shfl_xor(bi, 16, 64));
+    better(bv, bi, __shfl_xor(bv, 32, 64), __shfl_xor(bi, 32, 64));
+    if (lane == 0) {
+      red_v[wave] = bv;
+      red_i[wave] = bi;
+    }
+    __syncthreads();
+    double sb = red_v[0];
+    int sp = red_i[0];
+#pragma unroll
+    for (int w2 = 1; w2 < RW; ++w2) better(sb, sp, red_v[w2], red_i[w2]);
+    const double best = nopiv ? nrm_s[i] : sb;
+    const int p = nopiv ? i : sp;
+    if (i == 0) nu0 = best;
+    if (!nopiv && (best <= 0.0 || best <= rtol * nu0)) break;
+    if (!nopiv && P.kfail >= 0 && i > P.kfail && m > d) break;
+    // the pivot column's owner: wavefront (p / 4) % RW, group (p / 4) / RW, row p % 4
+    const int wp = (p >> 2) % RW, gp = (p >> 2) / RW, rp = p & 3;
+    if (wave == wp && rq == rp) {
+#pragma unroll
+      for (int g = 0; g < CG; ++g)
+        if (g == gp) {
+#pragma unroll
+          for (int t = 0; t < R16; ++t) xcol[l16 + 16 * t] = y[g][t];
+          sel |= 1u << g;
+        }
+      if (l16 == 0) step_s[p] = i;
+    }
+    __syncthreads();
+    const double x0 = xcol[i];
+    const bool zero = !(best > 0.0);
+    const double alpha = zero ? 0.0 : -copysign(best, x0);
+    const double v0 = x0 - alpha;
+    const double tau = zero ? 0.0 : -v0 / alpha;
+    const double inv_v0 = zero ? 0.0 : 1.0 / v0;
+    double uu[R16];
+#pragma unroll
+    for (int t = 0; t < R16; ++t) {
+      const int r = l16 + 16 * t;
+      uu[t] = (r < d && r > i) ? xcol[r] * inv_v0 : (r == i ? 1.0 : 0.0);
+    }
+    if (!nopiv && wave == wp && rq == rp) {  // R_ii of the pivot column
+#pragma unroll
+      for (int g = 0; g < CG; ++g)
+        if (g == gp) {
+#pragma unroll
+          for (int t = 0; t < R16; ++t)
+            if (l16 + 16 * t == i) y[g][t] = alpha;
+        }
+    }
+    if (tid == 0) {
+      w.alpha[dp.aoff + i] = alpha;
+      w.piv[dp.aoff + i] = p;
+    }
+    // H applied to the live columns, all groups' sums together
+    double f[CG];
+#pragma unroll
+    for (int g = 0; g < CG; ++g) {
+      f[g] = 0.0;
+#pragma unroll
+      for (int t = 0; t < R16; ++t) f[g] = fma(uu[t], y[g][t], f[g]);
+    }
+    row16_sum_n<CG>(f);
+    double s2[CG];
+#pragma unroll
+    for (int g = 0; g < CG; ++g) {
+      const int j = 4 * (g * RW + wave) + rq;
+      const bool live = j < m && !((sel >> g) & 1u);
+      const double fg = live ? tau * f[g] : 0.0;
+      s2[g] = 0.0;
+#pragma unroll
+      for (int t = 0; t < R16; ++t) {
+        const int r = l16 + 16 * t;
+        const double v = fma(-fg, uu[t], y[g][t]);
+        y[g][t] = v;
+        if (r > i && r < d) s2[g] = fma(v, v, s2[g]);
+      }
+    }
+    row16_sum_n<CG>(s2);
+#pragma unroll
+    for (int g = 0; g < CG; ++g) {
+      const int j = 4 * (g * RW + wave) + rq;
+      if (j < m && !((sel >> g) & 1u)) {
+        nv[g] = sqrt(s2[g]);
+        if (l16 == 0) nrm_s[j] = nv[g];
+      }
+    }
+    k = i + 1;
+    // no closing barrier: xcol, red_v and nrm_s are written next only after
+    // the next step's first barrier, which every thread reaches only once
+    // done with this step
+  }
+  // write back the R data and the pivot steps
+  __syncthreads();
+  int* step = w.step + dp.off;
+#pragma unroll
+  for (int g = 0; g < CG; ++g) {
+    const int j = 4 * (g * RW + wave) + rq;
+    if (j >= m) continue;
+#pragma unroll
+    for (int t = 0; t < R16; ++t) {
+      const int r = l16 + 16 * t;
+      if (r < d) P.W[(long long)j * P.ldw + r] = y[g][t];
+    }
+    if (l16 == 0) step[j] = step_s[j];
+  }
+  if (tid == 0) w.k[q] = k;
+}
+
+// ---------------------------------------------------------------------------
 // large problems: one launch per pivot step
 //
 // Workgroup g of a problem owns columns g*SW .. g*SW+SW-1, one per
@@ -1396,17 +1588,17 @@ static int small_resident(int c) {
   static std::once_flag once;
   std::call_once(once, [] {
     const void* fns[kSmallClasses] = {
-        reinterpret_cast<const void*>(&qrcp_reg_kernel<16, 2, 1>),
-        reinterpret_cast<const void*>(&qrcp_reg_kernel<16, 4, 1>),
-        reinterpret_cast<const void*>(&qrcp_reg_kernel<16, 8, 1>),
-        reinterpret_cast<const void*>(&qrcp_reg_kernel<16, 16, 1>),
-        reinterpret_cast<const void*>(&qrcp_reg_kernel<16, 4, 2>),
-        reinterpret_cast<const void*>(&qrcp_reg_kernel<16, 8, 2>),
+        reinterpret_cast<const void*>(&qrcp_reg16_kernel<1, 4>),
+        reinterpret_cast<const void*>(&qrcp_reg16_kernel<2, 4>),
+        reinterpret_cast<const void*>(&qrcp_reg16_kernel<4, 4>),
+        reinterpret_cast<const void*>(&qrcp_reg16_kernel<8, 4>),
+        reinterpret_cast<const void*>(&qrcp_reg16_kernel<2, 8>),
+        reinterpret_cast<const void*>(&qrcp_reg16_kernel<4, 8>),
         reinterpret_cast<const void*>(&qrcp_reg_kernel<8, 32, 2>),
-        reinterpret_cast<const void*>(&qrcp_reg_kernel<16, 4, 3>),
+        reinterpret_cast<const void*>(&qrcp_reg16_kernel<2, 12>),
         reinterpret_cast<const void*>(&qrcp_reg_kernel<8, 16, 3>),
         reinterpret_cast<const void*>(&qrcp_reg_kernel<8, 32, 3>)};
-    const int waves[kSmallClasses] = {16, 16, 16, 16, 16, 16, 8, 16, 8, 8};
+    const int waves[kSmallClasses] = {8, 8, 8, 8, 8, 8, 8, 8, 8, 8};
     int dev = 0, cus = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
@@ -1522,21 +1714,28 @@ hipError_t launch_id_factor(IdProblem* probs, int nprob, double rtol, void* work
       const int* dl = static_cast<const int*>(st.push(L.data(), L.size() * 4));
       if (!dl) return hipErrorOutOfMemory;
       const dim3 grid((unsigned)L.size());
-#define QR_LAUNCH(W_, C_, R_) \
+#define QR_LAUNCH(G_, R_) \
+  hipLaunchKernelGGL((qrcp_reg16_kernel<G_, R_>), grid, dim3(512), 0, s, dprobs, dl, rtol, w)
+#define QR_LAUNCH64(W_, C_, R_) \
   hipLaunchKernelGGL((qrcp_reg_kernel<W_, C_, R_>), grid, dim3(W_ * 64), 0, s, dprobs, dl, rtol, w)
+      // 16 lanes per column: (column groups, rows per lane) = 32 G columns,
+      // 16 R rows; the three largest classes, whose 16-lane form would
+      // spill registers, keep 64 lanes per column (W wavefronts, C columns
+      // per wavefront, R rows per lane)
       switch (c) {
-        case 0: QR_LAUNCH(16, 2, 1); break;
-        case 1: QR_LAUNCH(16, 4, 1); break;
-        case 2: QR_LAUNCH(16, 8, 1); break;
-        case 3: QR_LAUNCH(16, 16, 1); break;
-        case 4: QR_LAUNCH(16, 4, 2); break;
-        case 5: QR_LAUNCH(16, 8, 2); break;
-        case 6: QR_LAUNCH(8, 32, 2); break;
-        case 7: QR_LAUNCH(16, 4, 3); break;
-        case 8: QR_LAUNCH(8, 16, 3); break;
-        default: QR_LAUNCH(8, 32, 3); break;
+        case 0: QR_LAUNCH(1, 4); break;
+        case 1: QR_LAUNCH(2, 4); break;
+        case 2: QR_LAUNCH(4, 4); break;
+        case 3: QR_LAUNCH(8, 4); break;
+        case 4: QR_LAUNCH(2, 8); break;
+        case 5: QR_LAUNCH(4, 8); break;
+        case 6: QR_LAUNCH64(8, 32, 2); break;
+        case 7: QR_LAUNCH(2, 12); break;
+        case 8: QR_LAUNCH64(8, 16, 3); break;
+        default: QR_LAUNCH64(8, 32, 3); break;
       }
 #undef QR_LAUNCH
+#undef QR_LAUNCH64
       const hipError_t le = hipGetLastError();
       if (le != hipSuccess) return le;
     }
