@@ -441,6 +441,8 @@ template <int CG, int R16>
 __global__ __launch_bounds__(512) void qrcp_reg16_kernel(const DevProb* __restrict__ probs,
                                                         const int* __restrict__ list, double rtol, Work w) {
   constexpr int RW = 8, NC = 4 * RW * CG;  // wavefronts, columns held
+  constexpr int SB = CG < 4 ? CG : 4;      // groups whose sums are taken together
+  static_assert(CG % SB == 0, "whole sub-batches");
   __shared__ double xcol[R16 * 16];
   __shared__ double nrm_s[NC];
   __shared__ int step_s[NC];
@@ -455,30 +457,37 @@ __global__ __launch_bounds__(512) void qrcp_reg16_kernel(const DevProb* __restri
   const int l16 = lane & 15, rq = lane >> 4;
   const bool nopiv = P.nfac > 0;
 
+  // this lane's best candidate of the step to come: the norms are folded in
+  // as soon as they are known, not kept per column
+  double bv = -1.0;
+  int bi = INT_MAX;
   double y[CG][R16];
-  double nv[CG];
-  {
-    double s[CG];
 #pragma unroll
-    for (int g = 0; g < CG; ++g) {
-      const int j = 4 * (g * RW + wave) + rq;
-      s[g] = 0.0;
+  for (int g0 = 0; g0 < CG; g0 += SB) {
+    double s[SB];
+#pragma unroll
+    for (int gg = 0; gg < SB; ++gg) {
+      const int g = g0 + gg, j = 4 * (g * RW + wave) + rq;
+      s[gg] = 0.0;
 #pragma unroll
       for (int t = 0; t < R16; ++t) {
         const int r = l16 + 16 * t;
         const double v = (j < m && r < d) ? P.Y[(long long)j * P.ldy + r] : 0.0;
         y[g][t] = v;
-        s[g] = fma(v, v, s[g]);
+        s[gg] = fma(v, v, s[gg]);
       }
     }
-    row16_sum_n<CG>(s);
+    row16_sum_n<SB>(s);
 #pragma unroll
-    for (int g = 0; g < CG; ++g) {
-      const int j = 4 * (g * RW + wave) + rq;
-      nv[g] = sqrt(s[g]);
-      if (l16 == 0 && j < m) {
-        nrm_s[j] = nv[g];
-        step_s[j] = -1;
+    for (int gg = 0; gg < SB; ++gg) {
+      const int j = 4 * ((g0 + gg) * RW + wave) + rq;
+      if (j < m) {
+        const double nv = sqrt(s[gg]);
+        better(bv, bi, nv, j);
+        if (l16 == 0) {
+          nrm_s[j] = nv;
+          step_s[j] = -1;
+        }
       }
     }
   }
@@ -486,17 +495,8 @@ __global__ __launch_bounds__(512) void qrcp_reg16_kernel(const DevProb* __restri
   const int kmax = dp.kmax;
   double nu0 = 0.0;
   int k = 0;
-  __syncthreads();
   for (int i = 0; i < kmax; ++i) {
-    // pivot candidates from the norms in registers: this row's columns, then
-    // across the four rows of the wavefront, then across wavefronts
-    double bv = -1.0;
-    int bi = INT_MAX;
-#pragma unroll
-    for (int g = 0; g < CG; ++g) {
-      const int j = 4 * (g * RW + wave) + rq;
-      if (j < m && !((sel >> g) & 1u)) better(bv, bi, nv[g], j);
-    }
+    // candidates across the four rows of the wavefront, then across wavefronts
     better(bv, bi, __shfl_xor(bv, 16, 64), __shfl_xor(bi, 16, 64));
     better(bv, bi, __shfl_xor(bv, 32, 64), __shfl_xor(bi, 32, 64));
     if (lane == 0) {
@@ -538,50 +538,48 @@ __global__ __launch_bounds__(512) void qrcp_reg16_kernel(const DevProb* __restri
       const int r = l16 + 16 * t;
       uu[t] = (r < d && r > i) ? xcol[r] * inv_v0 : (r == i ? 1.0 : 0.0);
     }
-    if (!nopiv && wave == wp && rq == rp) {  // R_ii of the pivot column
-#pragma unroll
-      for (int g = 0; g < CG; ++g)
-        if (g == gp) {
-#pragma unroll
-          for (int t = 0; t < R16; ++t)
-            if (l16 + 16 * t == i) y[g][t] = alpha;
-        }
-    }
     if (tid == 0) {
       w.alpha[dp.aoff + i] = alpha;
       w.piv[dp.aoff + i] = p;
     }
-    // H applied to the live columns, all groups' sums together
-    double f[CG];
+    // H applied to the live columns, SB groups' sums at a time; their new
+    // norms become the next step's candidates
+    bv = -1.0;
+    bi = INT_MAX;
 #pragma unroll
-    for (int g = 0; g < CG; ++g) {
-      f[g] = 0.0;
+    for (int g0 = 0; g0 < CG; g0 += SB) {
+      double f[SB];
 #pragma unroll
-      for (int t = 0; t < R16; ++t) f[g] = fma(uu[t], y[g][t], f[g]);
-    }
-    row16_sum_n<CG>(f);
-    double s2[CG];
+      for (int gg = 0; gg < SB; ++gg) {
+        f[gg] = 0.0;
 #pragma unroll
-    for (int g = 0; g < CG; ++g) {
-      const int j = 4 * (g * RW + wave) + rq;
-      const bool live = j < m && !((sel >> g) & 1u);
-      const double fg = live ? tau * f[g] : 0.0;
-      s2[g] = 0.0;
-#pragma unroll
-      for (int t = 0; t < R16; ++t) {
-        const int r = l16 + 16 * t;
-        const double v = fma(-fg, uu[t], y[g][t]);
-        y[g][t] = v;
-        if (r > i && r < d) s2[g] = fma(v, v, s2[g]);
+        for (int t = 0; t < R16; ++t) f[gg] = fma(uu[t], y[g0 + gg][t], f[gg]);
       }
-    }
-    row16_sum_n<CG>(s2);
+      row16_sum_n<SB>(f);
+      double s2[SB];
 #pragma unroll
-    for (int g = 0; g < CG; ++g) {
-      const int j = 4 * (g * RW + wave) + rq;
-      if (j < m && !((sel >> g) & 1u)) {
-        nv[g] = sqrt(s2[g]);
-        if (l16 == 0) nrm_s[j] = nv[g];
+      for (int gg = 0; gg < SB; ++gg) {
+        const int g = g0 + gg, j = 4 * (g * RW + wave) + rq;
+        const bool live = j < m && !((sel >> g) & 1u);
+        const double fg = live ? tau * f[gg] : 0.0;
+        s2[gg] = 0.0;
+#pragma unroll
+        for (int t = 0; t < R16; ++t) {
+          const int r = l16 + 16 * t;
+          const double v = fma(-fg, uu[t], y[g][t]);
+          y[g][t] = v;
+          if (r > i && r < d) s2[gg] = fma(v, v, s2[gg]);
+        }
+      }
+      row16_sum_n<SB>(s2);
+#pragma unroll
+      for (int gg = 0; gg < SB; ++gg) {
+        const int g = g0 + gg, j = 4 * (g * RW + wave) + rq;
+        if (j < m && !((sel >> g) & 1u)) {
+          const double nv = sqrt(s2[gg]);
+          better(bv, bi, nv, j);
+          if (l16 == 0) nrm_s[j] = nv;
+        }
       }
     }
     k = i + 1;
@@ -589,19 +587,22 @@ __global__ __launch_bounds__(512) void qrcp_reg16_kernel(const DevProb* __restri
     // the next step's first barrier, which every thread reaches only once
     // done with this step
   }
-  // write back the R data and the pivot steps
+  // write back the R data and the pivot steps; a pivot's own row (its
+  // step) gets R_ii = alpha, which the step loop leaves out of the registers
   __syncthreads();
   int* step = w.step + dp.off;
 #pragma unroll
   for (int g = 0; g < CG; ++g) {
     const int j = 4 * (g * RW + wave) + rq;
     if (j >= m) continue;
+    const int sj = step_s[j];
+    const double aj = (!nopiv && sj >= 0 && sj < k) ? w.alpha[dp.aoff + sj] : 0.0;
 #pragma unroll
     for (int t = 0; t < R16; ++t) {
       const int r = l16 + 16 * t;
-      if (r < d) P.W[(long long)j * P.ldw + r] = y[g][t];
+      if (r < d) P.W[(long long)j * P.ldw + r] = (!nopiv && sj >= 0 && sj < k && r == sj) ? aj : y[g][t];
     }
-    if (l16 == 0) step[j] = step_s[j];
+    if (l16 == 0) step[j] = sj;
   }
   if (tid == 0) w.k[q] = k;
 }
@@ -1596,7 +1597,7 @@ static int small_resident(int c) {
         reinterpret_cast<const void*>(&qrcp_reg16_kernel<4, 8>),
         reinterpret_cast<const void*>(&qrcp_reg_kernel<8, 32, 2>),
         reinterpret_cast<const void*>(&qrcp_reg16_kernel<2, 12>),
-        reinterpret_cast<const void*>(&qrcp_reg_kernel<8, 16, 3>),
+        reinterpret_cast<const void*>(&qrcp_reg16_kernel<4, 12>),
         reinterpret_cast<const void*>(&qrcp_reg_kernel<8, 32, 3>)};
     const int waves[kSmallClasses] = {8, 8, 8, 8, 8, 8, 8, 8, 8, 8};
     int dev = 0, cus = 0;
@@ -1719,9 +1720,9 @@ hipError_t launch_id_factor(IdProblem* probs, int nprob, double rtol, void* work
 #define QR_LAUNCH64(W_, C_, R_) \
   hipLaunchKernelGGL((qrcp_reg_kernel<W_, C_, R_>), grid, dim3(W_ * 64), 0, s, dprobs, dl, rtol, w)
       // 16 lanes per column: (column groups, rows per lane) = 32 G columns,
-      // 16 R rows; the three largest classes, whose 16-lane form would
-      // spill registers, keep 64 lanes per column (W wavefronts, C columns
-      // per wavefront, R rows per lane)
+      // 16 R rows; the two largest classes, whose 16-lane form would spill
+      // registers inside the step loop, keep 64 lanes per column (W
+      // wavefronts, C columns per wavefront, R rows per lane)
       switch (c) {
         case 0: QR_LAUNCH(1, 4); break;
         case 1: QR_LAUNCH(2, 4); break;
@@ -1731,7 +1732,7 @@ hipError_t launch_id_factor(IdProblem* probs, int nprob, double rtol, void* work
         case 5: QR_LAUNCH(4, 8); break;
         case 6: QR_LAUNCH64(8, 32, 2); break;
         case 7: QR_LAUNCH(2, 12); break;
-        case 8: QR_LAUNCH64(8, 16, 3); break;
+        case 8: QR_LAUNCH(4, 12); break;
         default: QR_LAUNCH64(8, 32, 3); break;
       }
 #undef QR_LAUNCH
