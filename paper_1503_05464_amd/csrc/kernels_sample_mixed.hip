@@ -24,13 +24,13 @@
 // BF16 planes on the way in), so that a lane reads its eight k values for
 // one MFMA operand in a single 16-byte access: lane l takes
 // k = 8 (l / 16) + e, e < 8, of row l % 16 -- the same k for A and R, which is
-// all the product needs.  A is written to LDS in packed pieces: in the plain
-// product a thread holds 16 consecutive k of one row; in the transposed
-// product it loads a 4 x 4 block of A so that it holds 4 consecutive k of
-// each of its 4 rows of the tile.  R comes from a transposed copy in the
-// products' precision (R^T: columns of R contiguous, zero-padded to whole
-// slices and tiles), made once per call, from which every wavefront loads
-// its operands directly.  The output layout of both MFMAs (checked on the
+// all the product needs.  A is written to LDS in packed pieces: a thread
+// holds 4 consecutive k of each of 4 rows of the tile, loaded as four rows
+// of 4 k (plain product; eight consecutive lanes cover a row of the slice)
+// or as a 4 x 4 block of A (transposed product).  R comes from a transposed
+// copy in the products' precision (R^T: columns of R contiguous, zero-padded
+// to whole slices and tiles), made once per call; its slice passes through
+// LDS beside A's.  The output layout of both MFMAs (checked on the
 // device): lane l, register r -> row 4 (l / 16) + r, column l % 16.  The
 // single-matrix kernel is held to 168 registers so that three workgroups
 // share a CU, and K is split to fill two whole rounds of them.
@@ -70,10 +70,12 @@ struct Smem;
 template <>
 struct alignas(16) Smem<1> {  // FP32
   float A[BM][AP1];
+  float R[BN][AP1];  // R^T slice: column c of R, k contiguous
 };
 template <>
 struct alignas(16) Smem<2> {  // BF16 x 3
   unsigned short A[3][BM][AP2];
+  unsigned short R[BN][AP2];
 };
 
 template <int MODE>
@@ -87,9 +89,14 @@ struct RtType<2> {
   typedef unsigned short T;
 };
 
-// This thread's 16 entries of the A slice.  NN: row i0 + tid/2, k = k0 +
-// 16 (tid % 2) + e.  TN (element (i, k) is A[k][i]): k = k0 + 4 (tid / 32) + q,
-// i = i0 + 4 (tid % 32) + e, stored in v[4 q + e].
+// This thread's 16 entries of the A slice, stored in v[4 q + e].  NN: row
+// i0 + 32 q + tid / 8, k = k0 + 4 (tid % 8) + e, so that eight consecutive
+// lanes read one row's 128 bytes of the slice in one instruction (with two
+// lanes per row, each reading 64 bytes in four instructions, the loads of a
+// wavefront touched 32 rows per instruction and A streamed at 3.8 TB/s
+// against 7.1 TB/s).  TN (element (i, k) is A[k][i]): k = k0 + 4 (tid / 32)
+// + q, i = i0 + 4 (tid % 32) + e.  Either way the thread holds 4 consecutive
+// k of each of 4 rows of the tile.
 template <bool TRANS>
 __device__ __forceinline__ void load_a(float (&v)[16], const float* __restrict__ A, long long lda,
                                        int n, int i0, int k0, int kend,
@@ -97,24 +104,26 @@ __device__ __forceinline__ void load_a(float (&v)[16], const float* __restrict__
                                        bool need_mask) {
   const int tid = threadIdx.x;
   if (!TRANS) {
-    const int row = i0 + (tid >> 1), col = k0 + (tid & 1) * 16;
-    if (row < n && col + 16 <= kend && vec_ok) {
-      const u32x4* p = reinterpret_cast<const u32x4*>(A + (long long)row * lda + col);
+    const int rb = i0 + (tid >> 3), col = k0 + 4 * (tid & 7);
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const u32x4 w = __builtin_nontemporal_load(p + q);
+    for (int q = 0; q < 4; ++q) {
+      const int row = rb + 32 * q;
+      if (row < n && col + 4 <= kend && vec_ok) {
+        const u32x4 w = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(A + (long long)row * lda + col));
 #pragma unroll
         for (int e = 0; e < 4; ++e) v[4 * q + e] = __uint_as_float(w[e]);
-      }
-    } else {
+      } else {
 #pragma unroll
-      for (int e = 0; e < 16; ++e)
-        v[e] = (row < n && col + e < kend) ? A[(long long)row * lda + col + e] : 0.0f;
+        for (int e = 0; e < 4; ++e)
+          v[4 * q + e] = (row < n && col + e < kend) ? A[(long long)row * lda + col + e] : 0.0f;
+      }
     }
     if (need_mask) {
 #pragma unroll
-      for (int e = 0; e < 16; ++e)
-        if (row < n && col + e < n && leaf_of[row] == leaf_of[col + e]) v[e] = 0.0f;
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+          if (rb + 32 * q < n && col + e < n && leaf_of[rb + 32 * q] == leaf_of[col + e]) v[4 * q + e] = 0.0f;
     }
   } else {
     const int kb = k0 + 4 * (tid >> 5), ib = i0 + 4 * (tid & 31);
@@ -163,32 +172,43 @@ __device__ __forceinline__ unsigned int pack2(unsigned int lo, unsigned int hi) 
   return __builtin_amdgcn_perm(hi, lo, 0x07060302u);
 }
 
+// Position of k offset kk (a multiple of 4) in row `row` of the A slice in
+// LDS: the 16-byte pieces of a row (four in a BF16 plane, eight in FP32) are
+// permuted by bits 4.. of the row.  In the transposed product the 32 lanes
+// of a store write rows 4 apart, which without the permutation fall on a
+// quarter of the LDS banks (a modelled 16 passes per store instead of 4
+// for BF16 and 8 for FP32); the reads of a 16-row MFMA block see the same
+// permutation in every row, so they stay conflict-free.
+template <int MODE>
+__device__ __forceinline__ int swz(int row, int kk) {
+  if constexpr (MODE == 2) return (((kk >> 3) ^ ((row >> 4) & 3)) << 3) | (kk & 7);
+  else return (((kk >> 2) ^ ((row >> 4) & 7)) << 2) | (kk & 3);
+}
+
 template <int MODE, bool TRANS>
 __device__ __forceinline__ void store_a(Smem<MODE>& sm, const float (&v)[16]) {
   const int tid = threadIdx.x;
-  if (!TRANS) {  // one row, 16 consecutive k
-    const int r = tid >> 1, kseg = (tid & 1) * 16;
-    if constexpr (MODE == 1) {
+  if (!TRANS) {  // rows 32 q + tid / 8, k = 4 (tid % 8) + e
+    const int rb = tid >> 3, kq = 4 * (tid & 7);
 #pragma unroll
-      for (int j = 0; j < 4; ++j)
-        *reinterpret_cast<float4*>(&sm.A[r][kseg + 4 * j]) =
-            make_float4(v[4 * j], v[4 * j + 1], v[4 * j + 2], v[4 * j + 3]);
-    } else {
-      // split and pack two k at a time, so that only the packed words stay live
+    for (int q = 0; q < 4; ++q) {
+      if constexpr (MODE == 1) {
+        *reinterpret_cast<float4*>(&sm.A[rb + 32 * q][swz<1>(rb + 32 * q, kq)]) =
+            make_float4(v[4 * q], v[4 * q + 1], v[4 * q + 2], v[4 * q + 3]);
+      } else {
+        unsigned int w[3][2];
 #pragma unroll
-      for (int j = 0; j < 2; ++j) {
-        u32x4 w[3];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
+        for (int h = 0; h < 2; ++h) {
           unsigned int a1, a2, a3, b1, b2, b3;
-          split3(v[8 * j + 2 * q], a1, a2, a3);
-          split3(v[8 * j + 2 * q + 1], b1, b2, b3);
-          w[0][q] = pack2(a1, b1);
-          w[1][q] = pack2(a2, b2);
-          w[2][q] = pack2(a3, b3);
+          split3(v[4 * q + 2 * h], a1, a2, a3);
+          split3(v[4 * q + 2 * h + 1], b1, b2, b3);
+          w[0][h] = pack2(a1, b1);
+          w[1][h] = pack2(a2, b2);
+          w[2][h] = pack2(a3, b3);
         }
 #pragma unroll
-        for (int t = 0; t < 3; ++t) *reinterpret_cast<u32x4*>(&sm.A[t][r][kseg + 8 * j]) = w[t];
+        for (int t = 0; t < 3; ++t)
+          *reinterpret_cast<uint2*>(&sm.A[t][rb + 32 * q][swz<2>(rb + 32 * q, kq)]) = make_uint2(w[t][0], w[t][1]);
       }
     }
   } else {  // 4 rows of the tile (columns of A), 4 consecutive k each
@@ -196,7 +216,7 @@ __device__ __forceinline__ void store_a(Smem<MODE>& sm, const float (&v)[16]) {
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
       if constexpr (MODE == 1) {
-        *reinterpret_cast<float4*>(&sm.A[rb + e][kq]) = make_float4(v[e], v[4 + e], v[8 + e], v[12 + e]);
+        *reinterpret_cast<float4*>(&sm.A[rb + e][swz<1>(rb + e, kq)]) = make_float4(v[e], v[4 + e], v[8 + e], v[12 + e]);
       } else {
         unsigned int w[3][2];
 #pragma unroll
@@ -209,40 +229,39 @@ __device__ __forceinline__ void store_a(Smem<MODE>& sm, const float (&v)[16]) {
           w[2][q] = pack2(a3, b3);
         }
 #pragma unroll
-        for (int t = 0; t < 3; ++t) *reinterpret_cast<uint2*>(&sm.A[t][rb + e][kq]) = make_uint2(w[t][0], w[t][1]);
+        for (int t = 0; t < 3; ++t)
+          *reinterpret_cast<uint2*>(&sm.A[t][rb + e][swz<2>(rb + e, kq)]) = make_uint2(w[t][0], w[t][1]);
       }
     }
   }
 }
 
-// R^T operands of a wavefront for one slice: column c (of R) and k = k0 + lk
-// + e, e < 8, for its two 16-column blocks
+// This thread's piece of the R^T slice (columns c0 .. c0 + 63 of R, k0 ..
+// k0 + 31): column c0 + tid / 4, k = k0 + 8 (tid % 4) + e, e < 8 -- 16 bytes
+// in BF16, 32 in FP32, four consecutive lanes reading one column's slice.
+// The workgroup stages the slice in LDS once for its four wavefronts (each
+// loading its own operands from R^T read twice as many bytes, in pieces
+// scattered over 16 columns per instruction).
 template <int MODE>
-struct BFrag;
-template <>
-struct BFrag<1> {
-  float b[2][8];
-};
-template <>
-struct BFrag<2> {
-  bf16x8 b[2];
+struct RPiece {
+  u32x4 w[MODE == 1 ? 2 : 1];
 };
 
 template <int MODE>
-__device__ __forceinline__ void load_b(BFrag<MODE>& f, const typename RtType<MODE>::T* __restrict__ Rt,
-                                       long long ldrt, int cbase, int k0, int lr, int lk) {
+__device__ __forceinline__ void load_r(RPiece<MODE>& f, const typename RtType<MODE>::T* __restrict__ Rt,
+                                       long long ldrt, int c0, int k0) {
+  const int tid = threadIdx.x;
+  const u32x4* p = reinterpret_cast<const u32x4*>(Rt + (long long)(c0 + (tid >> 2)) * ldrt + k0 + 8 * (tid & 3));
 #pragma unroll
-  for (int nb = 0; nb < 2; ++nb) {
-    const typename RtType<MODE>::T* p = Rt + (long long)(cbase + nb * 16 + lr) * ldrt + k0 + lk;
-    if constexpr (MODE == 1) {
-      const float4 x = *reinterpret_cast<const float4*>(p);
-      const float4 y = *reinterpret_cast<const float4*>(p + 4);
-      f.b[nb][0] = x.x; f.b[nb][1] = x.y; f.b[nb][2] = x.z; f.b[nb][3] = x.w;
-      f.b[nb][4] = y.x; f.b[nb][5] = y.y; f.b[nb][6] = y.z; f.b[nb][7] = y.w;
-    } else {
-      f.b[nb] = *reinterpret_cast<const bf16x8*>(p);
-    }
-  }
+  for (int h = 0; h < (MODE == 1 ? 2 : 1); ++h) f.w[h] = p[h];
+}
+
+template <int MODE>
+__device__ __forceinline__ void store_r(Smem<MODE>& sm, const RPiece<MODE>& f) {
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int h = 0; h < (MODE == 1 ? 2 : 1); ++h)
+    *reinterpret_cast<u32x4*>(&sm.R[tid >> 2][8 * (tid & 3) + 4 * h]) = f.w[h];
 }
 
 // One 128 x 64 tile of S (rows i0.., columns c0..) over k in [kbeg, kend),
@@ -284,12 +303,13 @@ __device__ __forceinline__ void sample_tile(Smem<MODE>& sm, const float* __restr
     }
 
   float va[16];
-  BFrag<MODE> fb, fn;
+  RPiece<MODE> rp;
   int k0 = kbeg;
   if (k0 < kend) {
     load_a<TRANS>(va, A, lda, n, i0, k0, kend, leaf_of, vec_a, mask_for(k0));
-    load_b<MODE>(fb, Rt, ldrt, cbase, k0, lr, lk);
+    load_r<MODE>(rp, Rt, ldrt, c0, k0);
     store_a<MODE, TRANS>(sm, va);
+    store_r<MODE>(sm, rp);
   }
   __syncthreads();
   int since = 0;  // k values accumulated in FP32 since the last carry
@@ -297,35 +317,47 @@ __device__ __forceinline__ void sample_tile(Smem<MODE>& sm, const float* __restr
     const int kn = k0 + BK;
     if (kn < kend) {
       load_a<TRANS>(va, A, lda, n, i0, kn, kend, leaf_of, vec_a, mask_for(kn));
-      load_b<MODE>(fn, Rt, ldrt, cbase, kn, lr, lk);
+      load_r<MODE>(rp, Rt, ldrt, c0, kn);
     }
     if constexpr (MODE == 1) {
+      float b[2][8];
+#pragma unroll
+      for (int nb = 0; nb < 2; ++nb) {
+        const float4 x = *reinterpret_cast<const float4*>(&sm.R[wn * 32 + nb * 16 + lr][lk]);
+        const float4 y = *reinterpret_cast<const float4*>(&sm.R[wn * 32 + nb * 16 + lr][lk + 4]);
+        b[nb][0] = x.x; b[nb][1] = x.y; b[nb][2] = x.z; b[nb][3] = x.w;
+        b[nb][4] = y.x; b[nb][5] = y.y; b[nb][6] = y.z; b[nb][7] = y.w;
+      }
 #pragma unroll
       for (int mb = 0; mb < 4; ++mb) {
-        const float4 x = *reinterpret_cast<const float4*>(&sm.A[wm * 64 + mb * 16 + lr][lk]);
-        const float4 y = *reinterpret_cast<const float4*>(&sm.A[wm * 64 + mb * 16 + lr][lk + 4]);
+        const int row = wm * 64 + mb * 16 + lr;
+        const float4 x = *reinterpret_cast<const float4*>(&sm.A[row][swz<1>(row, lk)]);
+        const float4 y = *reinterpret_cast<const float4*>(&sm.A[row][swz<1>(row, lk + 4)]);
         const float a[8] = {x.x, x.y, x.z, x.w, y.x, y.y, y.z, y.w};
 #pragma unroll
         for (int e = 0; e < 8; ++e)
 #pragma unroll
           for (int nb = 0; nb < 2; ++nb)
-            acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[e], fb.b[nb][e], acc[mb][nb], 0, 0, 0);
+            acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[e], b[nb][e], acc[mb][nb], 0, 0, 0);
       }
     } else {
       // multiplying wavefronts issue first (5.72 -> 5.62 ms per launch; the
       // FP32 mode runs slower with it: 6.71 -> 6.87 ms)
+      bf16x8 b[2];
+#pragma unroll
+      for (int nb = 0; nb < 2; ++nb) b[nb] = *reinterpret_cast<const bf16x8*>(&sm.R[wn * 32 + nb * 16 + lr][lk]);
       __builtin_amdgcn_s_setprio(1);
 #pragma unroll
       for (int t = 0; t < 3; ++t) {
         bf16x8 a[4];
 #pragma unroll
         for (int mb = 0; mb < 4; ++mb)
-          a[mb] = *reinterpret_cast<const bf16x8*>(&sm.A[t][wm * 64 + mb * 16 + lr][lk]);
+          a[mb] = *reinterpret_cast<const bf16x8*>(&sm.A[t][wm * 64 + mb * 16 + lr][swz<2>(wm * 64 + mb * 16 + lr, lk)]);
 #pragma unroll
         for (int mb = 0; mb < 4; ++mb)
 #pragma unroll
           for (int nb = 0; nb < 2; ++nb)
-            acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[mb], fb.b[nb], acc[mb][nb], 0, 0, 0);
+            acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[mb], b[nb], acc[mb][nb], 0, 0, 0);
       }
       __builtin_amdgcn_s_setprio(0);
     }
@@ -344,7 +376,7 @@ __device__ __forceinline__ void sample_tile(Smem<MODE>& sm, const float* __restr
     __syncthreads();
     if (kn < kend) {
       store_a<MODE, TRANS>(sm, va);
-      fb = fn;
+      store_r<MODE>(sm, rp);
     }
     __syncthreads();
   }
