@@ -79,6 +79,8 @@ struct Node {
   //   rows r+kc..        W_b Q^T: columns 0..r-1 are W_b Q_t^T, r.. Dt.
   double* Z = nullptr;
   double* tau = nullptr;  // r Householder scalars
+  double* Yq = nullptr;   // the r reflectors as a dense Y (md x r, ld r), made once by the factor
+  double* Tq = nullptr;   // triangular factors of Y's blocks of 64 reflectors (64 x 64 each)
 };
 
 struct Handle {

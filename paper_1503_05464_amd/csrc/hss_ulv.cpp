@@ -165,42 +165,47 @@ hss_status apply_q_blocked(Handle& H, const std::vector<ReflDesc>& rd, hipStream
     rmax = std::max(rmax, d.r);
     mmax = std::max(mmax, d.m);
   }
+  // Y and T made by the factor (every descriptor has them) or here
+  bool pre = true;
+  for (const ReflDesc& d : rd) pre = pre && d.Y && d.T;
   const long long og = tot;
-  tot += (long long)nbtot * 64 * 64;
-  const long long ot = tot;
-  tot += (long long)nbtot * 64 * 64;
+  if (!pre) tot += 2LL * nbtot * 64 * 64;
   double* ws = static_cast<double*>(H.work_misc.ensure((size_t)tot * 8 + 8, s));
   if (!ws) return set_error(HSS_ERR_ALLOC, "reflector workspace");
-  auto Y = [&](size_t p) { return ws + oy[p]; };
-  auto Gb = [&](size_t p, int b) { return ws + og + (long long)(ob[p] + b) * 64 * 64; };
-  auto Tb = [&](size_t p, int b) { return ws + ot + (long long)(ob[p] + b) * 64 * 64; };
-  std::vector<ReflYDesc> yd(np);
-  for (size_t p = 0; p < np; ++p) yd[p] = ReflYDesc{rd[p].Z, rd[p].ldz, Y(p), rd[p].r, rd[p].m};
-  HIPCHK(launch_refl_y(yd.data(), (int)np, rmax, mmax, H.staging, s));
-  // G_b = Y_b^T Y_b, then T_b
-  std::vector<GemmDesc> gd;
-  std::vector<LarftDesc> ld;
-  for (size_t p = 0; p < np; ++p) {
-    const ReflDesc& d = rd[p];
-    for (int b = 0; b < nb[p]; ++b) {
-      const int i0 = 64 * b, kb = std::min(64, d.r - i0);
-      const double* yb = Y(p) + (long long)i0 * d.r + i0;
-      GemmDesc g{};
-      g.M = g.N = kb;
-      g.K = d.m - i0;
-      g.A = yb;
-      g.lda = d.r;
-      g.transA = 1;
-      g.B = seg(yb, d.r);
-      g.D = out(Gb(p, b), 64);
-      g.alpha = 1.0;
-      g.beta = 0.0;
-      gd.push_back(g);
-      ld.push_back(LarftDesc{Gb(p, b), d.tau + i0, Tb(p, b), kb});
+  auto Y = [&](size_t p) -> const double* { return pre ? rd[p].Y : ws + oy[p]; };
+  auto Tb = [&](size_t p, int b) -> const double* {
+    return pre ? rd[p].T + (long long)b * 64 * 64 : ws + og + (long long)(nbtot + ob[p] + b) * 64 * 64;
+  };
+  if (!pre) {
+    std::vector<ReflYDesc> yd(np);
+    for (size_t p = 0; p < np; ++p) yd[p] = ReflYDesc{rd[p].Z, rd[p].ldz, ws + oy[p], rd[p].r, rd[p].m};
+    HIPCHK(launch_refl_y(yd.data(), (int)np, rmax, mmax, H.staging, s));
+    // G_b = Y_b^T Y_b, then T_b
+    std::vector<GemmDesc> gd;
+    std::vector<LarftDesc> ld;
+    for (size_t p = 0; p < np; ++p) {
+      const ReflDesc& d = rd[p];
+      for (int b = 0; b < nb[p]; ++b) {
+        const int i0 = 64 * b, kb = std::min(64, d.r - i0);
+        const double* yb = Y(p) + (long long)i0 * d.r + i0;
+        double* gb = ws + og + (long long)(ob[p] + b) * 64 * 64;
+        GemmDesc g{};
+        g.M = g.N = kb;
+        g.K = d.m - i0;
+        g.A = yb;
+        g.lda = d.r;
+        g.transA = 1;
+        g.B = seg(yb, d.r);
+        g.D = out(gb, 64);
+        g.alpha = 1.0;
+        g.beta = 0.0;
+        gd.push_back(g);
+        ld.push_back(LarftDesc{gb, d.tau + i0, const_cast<double*>(Tb(p, b)), kb});
+      }
     }
+    HIPCHK(launch_gemm_batched(gd.data(), (int)gd.size(), H.staging, s));
+    HIPCHK(launch_larft(ld.data(), (int)ld.size(), H.staging, s));
   }
-  HIPCHK(launch_gemm_batched(gd.data(), (int)gd.size(), H.staging, s));
-  HIPCHK(launch_larft(ld.data(), (int)ld.size(), H.staging, s));
   for (int step = 0; step < nbmax; ++step) {
     std::vector<GemmDesc> g1, g2, g3;
     for (size_t p = 0; p < np; ++p) {
@@ -288,6 +293,61 @@ void merged_D(const Handle& H, int t, double* Dm, std::vector<GemmDesc>& gd) {
   g.B = seg(a.Z + (long long)ra * ma + ra, ma);
   g.D = out(Dm + (long long)a.kr * md, md);
   if (g.M && g.N) gd.push_back(g);
+}
+
+// Once per factorization: every node's reflectors as a dense Y and the
+// triangular factors T of its blocks of 64 (compact WY), which every solve
+// applies (they depend on the factors only).
+hss_status prepare_q(Handle& H, hipStream_t s) {
+  std::vector<Node>& nd = H.nodes;
+  std::vector<ReflYDesc> yd;
+  std::vector<GemmDesc> gd;
+  std::vector<LarftDesc> ld;
+  long long gtot = 0;
+  int rmax = 0, mmax = 0;
+  for (size_t t = 1; t < nd.size(); ++t) {
+    Node& u = nd[t];
+    const int md = md_of(u), r = md - u.kr;
+    if (r <= 0) continue;
+    const int nb = (r + 63) / 64;
+    u.Yq = static_cast<double*>(H.gen->alloc((size_t)md * r * 8));
+    u.Tq = static_cast<double*>(H.gen->alloc((size_t)nb * 64 * 64 * 8));
+    if (!u.Yq || !u.Tq) return set_error(HSS_ERR_ALLOC, "ULV reflector blocks");
+    yd.push_back(ReflYDesc{u.Z, md, u.Yq, r, md});
+    rmax = std::max(rmax, r);
+    mmax = std::max(mmax, md);
+    gtot += (long long)nb * 64 * 64;
+  }
+  if (yd.empty()) return HSS_OK;
+  double* G = static_cast<double*>(H.work_misc.ensure((size_t)gtot * 8 + 8, s));
+  if (!G) return set_error(HSS_ERR_ALLOC, "reflector workspace");
+  HIPCHK(launch_refl_y(yd.data(), (int)yd.size(), rmax, mmax, H.staging, s));
+  long long go = 0;
+  for (size_t t = 1; t < nd.size(); ++t) {
+    const Node& u = nd[t];
+    const int md = md_of(u), r = md - u.kr;
+    if (r <= 0) continue;
+    for (int b = 0; b < (r + 63) / 64; ++b) {  // G_b = Y_b^T Y_b, then T_b
+      const int i0 = 64 * b, kb = std::min(64, r - i0);
+      const double* yb = u.Yq + (long long)i0 * r + i0;
+      GemmDesc g{};
+      g.M = g.N = kb;
+      g.K = md - i0;
+      g.A = yb;
+      g.lda = r;
+      g.transA = 1;
+      g.B = seg(yb, r);
+      g.D = out(G + go, 64);
+      g.alpha = 1.0;
+      g.beta = 0.0;
+      gd.push_back(g);
+      ld.push_back(LarftDesc{G + go, u.tau + i0, u.Tq + (long long)b * 64 * 64, kb});
+      go += 64 * 64;
+    }
+  }
+  HIPCHK(launch_gemm_batched(gd.data(), (int)gd.size(), H.staging, s));
+  HIPCHK(launch_larft(ld.data(), (int)ld.size(), H.staging, s));
+  return HSS_OK;
 }
 
 hss_status factor_impl(Handle& H, hipStream_t s) {
@@ -455,6 +515,7 @@ hss_status factor_impl(Handle& H, hipStream_t s) {
       HIPCHK(launch_gemm_batched(&g, 1, H.staging, s));
     }
   }
+  CHK(prepare_q(H, s));
   int info = 0;
   HIPCHK(hipMemcpyAsync(&info, H.root_info, 4, hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
@@ -666,7 +727,7 @@ hss_status solve_impl(Handle& H, int nrhs, const double* b, long long ldb, doubl
           const long long ldd = u.leaf() ? ldx : nrhs;
           if (r) gd.push_back(copy_desc(r, nrhs, seg(Tp(c), nrhs), out(dst, ldd)));
           if (u.kr) gd.push_back(copy_desc(u.kr, nrhs, seg(xt + part, nrhs), out(dst + (long long)r * ldd, ldd)));
-          if (r) rd.push_back(ReflDesc{u.Z, mu, u.tau, r, mu, dst, ldd, nrhs, 1});
+          if (r) rd.push_back(ReflDesc{u.Z, mu, u.tau, r, mu, dst, ldd, nrhs, 1, u.Yq, u.Tq});
         }
       }
       HIPCHK(launch_gemm_batched(gd.data(), (int)gd.size(), H.staging, s));

@@ -31,6 +31,8 @@ struct ReflDesc {    // V <- H_0 ... H_{r-1} V (transpose = 1), reflectors in ro
   long long ldv;
   int nrhs;
   int transpose;
+  const double* Y = nullptr;  // precomputed dense Y and block factors T (both or
+  const double* T = nullptr;  // neither): then Z is not read
 };
 
 // Blocked application of reflectors (compact WY form): the reflector

@@ -14,6 +14,8 @@ namespace hss {
 namespace {
 
 constexpr int NT = 256;
+// widest batch of right-hand sides solved by tri_wave_kernel
+constexpr int kTriWaveMaxRhs = 64;
 
 // Wavefront argmax of (|value|, row) for the pivot search: the larger value,
 // the lower row on ties.  Butterfly of four DPP levels (quad permutes, then
@@ -103,6 +105,50 @@ __global__ __launch_bounds__(NT) void tri_block_kernel(const TriDesc* __restrict
     if (r < nb) g.X[(long long)r * g.ldx + col] = x[r];
 }
 
+// The value lane l of the wavefront holds, in every lane (l uniform).
+__device__ __forceinline__ double lane_bcast(double v, int l) {
+  const long long b = __double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)b, l);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// The same block solve for few right-hand sides: one wavefront per column,
+// lane r holding x[r].  Column c of T is applied once x[c] is final, which
+// is then read from its lane by all others, so a column takes nb dependent
+// steps across the wavefront instead of nb^2 / 2 in one thread (the
+// arithmetic, and so the rounding, is that of the kernel above).  Four
+// columns per workgroup (grid y).
+__global__ __launch_bounds__(NT) void tri_wave_kernel(const TriDesc* __restrict__ d) {
+  __shared__ double T[64][65];
+  constexpr int CPB = NT / 64;
+  const TriDesc g = d[blockIdx.x];
+  const int nb = g.nb;
+  if ((int)blockIdx.y * CPB >= g.nrhs) return;
+  for (int e = threadIdx.x; e < 64 * 64; e += NT) {
+    const int r = e >> 6, c = e & 63;
+    T[r][c] = (r < nb && c < nb && !(g.unit && r == c)) ? g.T[(long long)r * g.ldt + c] : (r == c ? 1.0 : 0.0);
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63;
+  const int col = blockIdx.y * CPB + (threadIdx.x >> 6);
+  if (col >= g.nrhs) return;
+  double* xp = g.X + (long long)(lane < nb ? lane : 0) * g.ldx + col;
+  double x = lane < nb ? *xp : 0.0;
+  if (g.lower) {
+    for (int c = 0; c < nb; ++c) {
+      const double xc = lane_bcast(x, c) / T[c][c];
+      x = lane == c ? xc : (lane > c ? fma(-T[lane][c], xc, x) : x);
+    }
+  } else {
+    for (int c = nb - 1; c >= 0; --c) {
+      const double xc = lane_bcast(x, c) / T[c][c];
+      x = lane == c ? xc : (lane < c ? fma(-T[lane][c], xc, x) : x);
+    }
+  }
+  if (lane < nb) *xp = x;
+}
+
 // Y = [u_0 .. u_{r-1}] (m x r, row-major, ld r) with u_i = (0.., 1, Z[i][i+1..m-1]):
 // 64 x 64 tiles transposed through LDS, so both Z rows and Y rows are read
 // and written contiguously.  grid: (ceil(m/64) * ceil(rmax/64), problems).
@@ -131,24 +177,29 @@ __global__ __launch_bounds__(NT) void refl_y_kernel(const ReflYDesc* __restrict_
 // Forward triangular factor of a block of kb reflectors, H_0 ... H_{kb-1} =
 // I - Y T Y^T: T[j][j] = tau_j, T[0:j, j] = -tau_j T[0:j, 0:j] G[0:j, j] with
 // G = Y^T Y.  One workgroup of 64 threads per block; thread l owns row l.
+// G and tau are staged in LDS first (rows of G read contiguously), so the
+// serial recurrence reads LDS only; T is upper triangular and zero below the
+// diagonal, so every thread sums over all p < j and the loop is uniform.
 __global__ __launch_bounds__(64) void larft_kernel(const LarftDesc* __restrict__ d) {
   __shared__ double T[64][65];
+  __shared__ double G[64][65];
+  __shared__ double tau[64];
   const LarftDesc g = d[blockIdx.x];
-  const int l = threadIdx.x;
+  const int l = threadIdx.x, kb = g.kb;
+  for (int r = 0; r < kb; ++r) G[r][l] = l < kb ? g.G[(long long)r * 64 + l] : 0.0;
+  tau[l] = l < kb ? g.tau[l] : 0.0;
   for (int c = 0; c < 64; ++c) T[l][c] = 0.0;
   __syncthreads();
-  for (int j = 0; j < g.kb; ++j) {
-    const double tj = g.tau[j];
+  for (int j = 0; j < kb; ++j) {
     double s = 0.0;
-    if (l < j)
-      for (int p = l; p < j; ++p) s = fma(T[l][p], g.G[(long long)p * 64 + j], s);
+    for (int p = 0; p < j; ++p) s = fma(T[l][p], G[p][j], s);
     __syncthreads();
-    if (l < j) T[l][j] = -tj * s;
-    if (l == j) T[j][j] = tj;
+    if (l < j) T[l][j] = -tau[j] * s;
+    if (l == j) T[j][j] = tau[j];
     __syncthreads();
   }
-  if (l < g.kb)
-    for (int c = 0; c < g.kb; ++c) g.T[(long long)l * 64 + c] = T[l][c];
+  if (l < kb)
+    for (int c = 0; c < kb; ++c) g.T[(long long)l * 64 + c] = T[l][c];
 }
 
 // Unblocked partial-pivoting LU of the panel A[j0:n, j0:j0+nb] (row-major,
@@ -411,7 +462,10 @@ hipError_t launch_tri_block(const TriDesc* d, int nd, Staging& st, hipStream_t s
   for (int i = 0; i < nd; ++i) cmax = d[i].nrhs > cmax ? d[i].nrhs : cmax;
   const TriDesc* dd = static_cast<const TriDesc*>(st.push(d, sizeof(TriDesc) * nd));
   if (!dd) return hipErrorOutOfMemory;
-  hipLaunchKernelGGL(tri_block_kernel, dim3(nd, (cmax + NT - 1) / NT), dim3(NT), 0, s, dd);
+  if (cmax <= kTriWaveMaxRhs)
+    hipLaunchKernelGGL(tri_wave_kernel, dim3(nd, (cmax + 3) / 4), dim3(NT), 0, s, dd);
+  else
+    hipLaunchKernelGGL(tri_block_kernel, dim3(nd, (cmax + NT - 1) / NT), dim3(NT), 0, s, dd);
   return hipGetLastError();
 }
 
