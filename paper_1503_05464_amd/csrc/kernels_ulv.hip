@@ -265,8 +265,10 @@ __global__ __launch_bounds__(1024) void lu_panel_kernel(double* __restrict__ A, 
   }
 }
 
-// The same panel factorization with the panel's rows split over the 1024
-// threads (thread t owns rows j0 + t + 1024 k, k < R) and the columns taken
+// The same panel factorization with the panel's rows split over NTH threads
+// (thread t owns rows j0 + t + NTH k, k < R; panels of at most 512 rows take
+// 256 threads: 184 against about 300 us per 64-column panel of 230 rows,
+// while 128 and 64 threads were slower again) and the columns taken
 // eight at a time: a sub-panel of 8 columns lives in registers while its
 // pivots are chosen (largest magnitude, lowest row on ties), its rows are
 // interchanged (through LDS, and in global memory for the panel's other
@@ -275,12 +277,13 @@ __global__ __launch_bounds__(1024) void lu_panel_kernel(double* __restrict__ A, 
 // the rows below, with the multipliers still in registers.
 constexpr int LW = 8;  // sub-panel width
 
-template <int R>
-__global__ __launch_bounds__(1024) void lu_panel_reg_kernel(double* __restrict__ A, long long ld, int n,
-                                                           int j0, int nb, int* __restrict__ piv,
-                                                           int* __restrict__ info) {
-  __shared__ double rv[16];
-  __shared__ int ri[16];
+template <int R, int NTH = 1024>
+__global__ __launch_bounds__(NTH) void lu_panel_reg_kernel(double* __restrict__ A, long long ld, int n,
+                                                          int j0, int nb, int* __restrict__ piv,
+                                                          int* __restrict__ info) {
+  constexpr int NW = NTH / 64;  // wavefronts
+  __shared__ double rv[NW];
+  __shared__ int ri[NW];
   __shared__ int s_p;
   __shared__ double xr[2][LW];
   __shared__ double ub[LW][64];
@@ -291,7 +294,7 @@ __global__ __launch_bounds__(1024) void lu_panel_reg_kernel(double* __restrict__
     double a[R][LW];
 #pragma unroll
     for (int k = 0; k < R; ++k) {
-      const int r = j0 + tid + 1024 * k;
+      const int r = j0 + tid + NTH * k;
 #pragma unroll
       for (int q = 0; q < LW; ++q) a[k][q] = (r >= c0 && r < n && q < w) ? A[(long long)r * ld + c0 + q] : 0.0;
     }
@@ -301,7 +304,7 @@ __global__ __launch_bounds__(1024) void lu_panel_reg_kernel(double* __restrict__
       int bi = INT_MAX;
 #pragma unroll
       for (int k = 0; k < R; ++k) {
-        const int r = j0 + tid + 1024 * k;
+        const int r = j0 + tid + NTH * k;
         double x = 0.0;
 #pragma unroll
         for (int q = 0; q < LW; ++q)
@@ -320,7 +323,7 @@ __global__ __launch_bounds__(1024) void lu_panel_reg_kernel(double* __restrict__
       if (tid == 0) {
         double v = rv[0];
         int ix = ri[0];
-        for (int q = 1; q < 16; ++q)
+        for (int q = 1; q < NW; ++q)
           if (rv[q] > v || (rv[q] == v && ri[q] < ix)) {
             v = rv[q];
             ix = ri[q];
@@ -333,14 +336,14 @@ __global__ __launch_bounds__(1024) void lu_panel_reg_kernel(double* __restrict__
       const int p = s_p;
       // rows col and p: exchange the sub-panel part through LDS
       const int oc = col - j0, op = p - j0;
-      const bool own_c = (oc & 1023) == tid, own_p = (op & 1023) == tid;
+      const bool own_c = oc % NTH == tid, own_p = op % NTH == tid;
       if (own_c || own_p) {
 #pragma unroll
         for (int k = 0; k < R; ++k) {
-          if (own_c && (oc >> 10) == k)
+          if (own_c && oc / NTH == k)
 #pragma unroll
             for (int q = 0; q < LW; ++q) xr[0][q] = a[k][q];
-          if (own_p && (op >> 10) == k)
+          if (own_p && op / NTH == k)
 #pragma unroll
             for (int q = 0; q < LW; ++q) xr[1][q] = a[k][q];
         }
@@ -358,10 +361,10 @@ __global__ __launch_bounds__(1024) void lu_panel_reg_kernel(double* __restrict__
       if (p != col && (own_c || own_p)) {
 #pragma unroll
         for (int k = 0; k < R; ++k) {
-          if (own_c && (oc >> 10) == k)
+          if (own_c && oc / NTH == k)
 #pragma unroll
             for (int q = 0; q < LW; ++q) a[k][q] = xr[1][q];
-          if (own_p && (op >> 10) == k)
+          if (own_p && op / NTH == k)
 #pragma unroll
             for (int q = 0; q < LW; ++q) a[k][q] = xr[0][q];
         }
@@ -371,7 +374,7 @@ __global__ __launch_bounds__(1024) void lu_panel_reg_kernel(double* __restrict__
       const double inv = (d != 0.0) ? 1.0 / d : 0.0;
 #pragma unroll
       for (int k = 0; k < R; ++k) {
-        const int r = j0 + tid + 1024 * k;
+        const int r = j0 + tid + NTH * k;
         if (r > col && r < n) {
           double l = 0.0;
 #pragma unroll
@@ -389,7 +392,7 @@ __global__ __launch_bounds__(1024) void lu_panel_reg_kernel(double* __restrict__
     // the sub-panel back to global memory
 #pragma unroll
     for (int k = 0; k < R; ++k) {
-      const int r = j0 + tid + 1024 * k;
+      const int r = j0 + tid + NTH * k;
       if (r >= c0 && r < n)
 #pragma unroll
         for (int q = 0; q < LW; ++q)
@@ -412,7 +415,7 @@ __global__ __launch_bounds__(1024) void lu_panel_reg_kernel(double* __restrict__
     // rows below: A[r][q] -= L[r][c0..c0+w) U[c0..c0+w)[q]
 #pragma unroll
     for (int k = 0; k < R; ++k) {
-      const int r = j0 + tid + 1024 * k;
+      const int r = j0 + tid + NTH * k;
       if (r >= q0 && r < n) {
         double* ar = A + (long long)r * ld;
         for (int t = 0; t < nr; ++t) {
@@ -495,8 +498,12 @@ hipError_t launch_lu_panel(double* A, long long ld, int n, int j0, int nb, int* 
     hipLaunchKernelGGL(lu_panel_reg_kernel<4>, dim3(1), dim3(1024), 0, s, A, ld, n, j0, nb, piv, info);
   else if (rows > 1024)
     hipLaunchKernelGGL(lu_panel_reg_kernel<2>, dim3(1), dim3(1024), 0, s, A, ld, n, j0, nb, piv, info);
-  else
+  else if (rows > 512)
     hipLaunchKernelGGL(lu_panel_reg_kernel<1>, dim3(1), dim3(1024), 0, s, A, ld, n, j0, nb, piv, info);
+  else if (rows > 256)
+    hipLaunchKernelGGL((lu_panel_reg_kernel<2, 256>), dim3(1), dim3(256), 0, s, A, ld, n, j0, nb, piv, info);
+  else
+    hipLaunchKernelGGL((lu_panel_reg_kernel<1, 256>), dim3(1), dim3(256), 0, s, A, ld, n, j0, nb, piv, info);
   return hipGetLastError();
 }
 
