@@ -59,13 +59,14 @@ bool same_opts(const Req& a, const Req& b) {
 
 // Device bytes a compress request holds while it runs: its inputs and
 // outputs (A, b, x), the compression's random matrices, samples and local
-// samples (about 8 n d_max doubles), the generators and ULV factors (a few
-// n x leaf blocks), the solve workspace and slack.
+// samples (about 8 n d_max doubles), the generators and ULV factors with the
+// solve's compact-WY reflector blocks (a few n x leaf blocks), the solve
+// workspace and slack.
 long long compress_footprint(long long n, long long lda, int dtype, int nrhs, const hss_opts& o) {
   const long long ldg = (o.d_max + 7) / 8 * 8;
   const long long a_bytes = n * lda * (dtype == HSS_F32 ? 4 : 8);
   const long long rhs_bytes = 2LL * n * nrhs * 8;
-  return a_bytes + rhs_bytes + 8LL * n * ldg * 8 + 6LL * n * std::max(o.leaf_size, 1) * 8 +
+  return a_bytes + rhs_bytes + 8LL * n * ldg * 8 + 8LL * n * std::max(o.leaf_size, 1) * 8 +
          4LL * n * nrhs * 8 + (64LL << 20);
 }
 
