@@ -65,7 +65,7 @@ def test_ulv_on_oracle_generators(case, path, monkeypatch, capfd):
     P.hss_factor(h)
     assert "persistent wait gave up" not in capfd.readouterr().err
     cond = np.linalg.cond(ohss.to_dense(Ho))
-    for nrhs in (1, 3, 300):  # few columns: one wavefront each; 300: one thread each
+    for nrhs in (1, 3, 64, 300):  # up to 64 columns: one wavefront each; 300: one thread each
         b = W.normal_rhs(A.shape[0], nrhs, 7)
         ref = oulv.solve(F, b)
         got = P.hss_solve(h, torch.from_numpy(b).cuda()).cpu().numpy()
