@@ -279,11 +279,17 @@ __device__ __forceinline__ void wave_argmax_pl(double& bv, int& bi) {
 // ---------------------------------------------------------------------------
 // small problems: one workgroup, matrix in registers
 // ---------------------------------------------------------------------------
-template <int RW, int CPW, int RPL>
+// NOPIV: every problem of the launch factors without pivoting (step i's
+// pivot is column i).  Then no candidate is searched and no norm kept but
+// the pivot column's own, which its wavefront forms from its registers (in
+// the order the pivoted path forms it); the reflector goes through LDS
+// buffers alternating by step, so a step needs one barrier.
+template <int RW, int CPW, int RPL, bool NOPIV = false>
 __global__ __launch_bounds__(RW * 64) void qrcp_reg_kernel(const DevProb* __restrict__ probs,
                                                           const int* __restrict__ list, double rtol,
                                                           Work w) {
-  __shared__ double xcol[RPL * 64];
+  __shared__ double xcol[NOPIV ? 2 : 1][RPL * 64];
+  __shared__ double pn_s[2];
   __shared__ double nrm_s[RW * CPW];
   __shared__ int step_s[RW * CPW];
   __shared__ double red_v[RW];
@@ -307,9 +313,9 @@ __global__ __launch_bounds__(RW * 64) void qrcp_reg_kernel(const DevProb* __rest
       y[c][t] = v;
       s = fma(v, v, s);
     }
-    s = wave_sum(s);
+    if constexpr (!NOPIV) s = wave_sum(s);
     if (lane == 0 && j < m) {
-      nrm_s[j] = sqrt(s);
+      if constexpr (!NOPIV) nrm_s[j] = sqrt(s);
       step_s[j] = -1;
     }
   }
@@ -317,6 +323,63 @@ __global__ __launch_bounds__(RW * 64) void qrcp_reg_kernel(const DevProb* __rest
   const int kmax = dp.kmax;
   double nu0 = 0.0;
   int k = 0;
+  if constexpr (NOPIV) {
+    for (int i = 0; i < kmax; ++i) {
+      const int wp = i % RW, cp = i / RW, b = i & 1;
+      if (wave == wp) {  // the pivot column: reflector source and its norm below row i
+        double sn = 0.0;
+#pragma unroll
+        for (int c = 0; c < CPW; ++c)
+          if (c == cp) {
+#pragma unroll
+            for (int t = 0; t < RPL; ++t) {
+              const int r = lane + 64 * t;
+              xcol[b][r] = y[c][t];
+              if (r >= i && r < d) sn = fma(y[c][t], y[c][t], sn);
+            }
+          }
+        sn = wave_sum(sn);
+        if (lane == 0) {
+          pn_s[b] = sqrt(sn);
+          step_s[i] = i;
+        }
+      }
+      __syncthreads();
+      const double best = pn_s[b];
+      const double x0 = xcol[b][i];
+      const bool zero = !(best > 0.0);
+      const double alpha = zero ? 0.0 : -copysign(best, x0);
+      const double v0 = x0 - alpha;
+      const double tau = zero ? 0.0 : -v0 / alpha;
+      const double inv_v0 = zero ? 0.0 : 1.0 / v0;
+      double uu[RPL];
+#pragma unroll
+      for (int t = 0; t < RPL; ++t) {
+        const int r = lane + 64 * t;
+        uu[t] = (r < d && r > i) ? xcol[b][r] * inv_v0 : (r == i ? 1.0 : 0.0);
+      }
+      if (tid == 0) {
+        w.alpha[dp.aoff + i] = alpha;
+        w.piv[dp.aoff + i] = i;
+      }
+      // the columns after the pivot (the earlier ones are finished)
+#pragma unroll
+      for (int c = 0; c < CPW; ++c) {
+        const int j = wave + RW * c;
+        if (j >= m || j <= i) continue;
+        double dot = 0.0;
+#pragma unroll
+        for (int t = 0; t < RPL; ++t) dot = fma(uu[t], y[c][t], dot);
+        const double f = tau * wave_sum(dot);
+#pragma unroll
+        for (int t = 0; t < RPL; ++t) y[c][t] = fma(-f, uu[t], y[c][t]);
+      }
+      k = i + 1;
+      // no closing barrier: the next step writes the other buffer, and the
+      // one after it this buffer only once every wavefront has passed the
+      // next step's barrier, i.e. finished reading here
+    }
+  } else {
   for (int i = 0; i < kmax; ++i) {
     double bv = -1.0;
     int bi = INT_MAX;
@@ -346,12 +409,12 @@ __global__ __launch_bounds__(RW * 64) void qrcp_reg_kernel(const DevProb* __rest
       for (int c = 0; c < CPW; ++c)
         if (c == cp) {
 #pragma unroll
-          for (int t = 0; t < RPL; ++t) xcol[lane + 64 * t] = y[c][t];
+          for (int t = 0; t < RPL; ++t) xcol[0][lane + 64 * t] = y[c][t];
         }
     }
     if (tid == 0) step_s[p] = i;
     __syncthreads();
-    const double x0 = xcol[i];
+    const double x0 = xcol[0][i];
     const bool zero = !(best > 0.0);
     const double alpha = zero ? 0.0 : -copysign(best, x0);
     const double v0 = x0 - alpha;
@@ -361,7 +424,7 @@ __global__ __launch_bounds__(RW * 64) void qrcp_reg_kernel(const DevProb* __rest
 #pragma unroll
     for (int t = 0; t < RPL; ++t) {
       const int r = lane + 64 * t;
-      uu[t] = (r < d && r > i) ? xcol[r] * inv_v0 : (r == i ? 1.0 : 0.0);
+      uu[t] = (r < d && r > i) ? xcol[0][r] * inv_v0 : (r == i ? 1.0 : 0.0);
     }
     if (wave == wp && !nopiv) {
 #pragma unroll
@@ -398,6 +461,8 @@ __global__ __launch_bounds__(RW * 64) void qrcp_reg_kernel(const DevProb* __rest
     k = i + 1;
     __syncthreads();
   }
+  }
+  __syncthreads();  // step_s complete before the write-back
   // write back the R data and the pivot steps
   int* step = w.step + dp.off;
 #pragma unroll
@@ -1715,10 +1780,18 @@ hipError_t launch_id_factor(IdProblem* probs, int nprob, double rtol, void* work
       const int* dl = static_cast<const int*>(st.push(L.data(), L.size() * 4));
       if (!dl) return hipErrorOutOfMemory;
       const dim3 grid((unsigned)L.size());
+      // a list of factorizations without pivoting only (the ULV factor's);
+      // HSS_REG_NOPIV=0 keeps them on the pivoting kernel (tests compare)
+      const char* nv = std::getenv("HSS_REG_NOPIV");
+      bool nopiv_list = !(nv && nv[0] == '0');
+      for (int q : L) nopiv_list = nopiv_list && probs[q].nfac > 0;
 #define QR_LAUNCH(G_, R_) \
   hipLaunchKernelGGL((qrcp_reg16_kernel<G_, R_>), grid, dim3(512), 0, s, dprobs, dl, rtol, w)
-#define QR_LAUNCH64(W_, C_, R_) \
-  hipLaunchKernelGGL((qrcp_reg_kernel<W_, C_, R_>), grid, dim3(W_ * 64), 0, s, dprobs, dl, rtol, w)
+#define QR_LAUNCH64(W_, C_, R_)                                                                        \
+  if (nopiv_list)                                                                                      \
+    hipLaunchKernelGGL((qrcp_reg_kernel<W_, C_, R_, true>), grid, dim3(W_ * 64), 0, s, dprobs, dl, rtol, w); \
+  else                                                                                                 \
+    hipLaunchKernelGGL((qrcp_reg_kernel<W_, C_, R_>), grid, dim3(W_ * 64), 0, s, dprobs, dl, rtol, w)
       // 16 lanes per column: (column groups, rows per lane) = 32 G columns,
       // 16 R rows; the two largest classes, whose 16-lane form would spill
       // registers inside the step loop, keep 64 lanes per column (W

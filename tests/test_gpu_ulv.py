@@ -142,3 +142,23 @@ def test_large_root_lu(n, path, monkeypatch, capfd):
     b = A @ xs
     x = P.hss_solve(h, b)
     assert float(torch.linalg.norm(x - xs) / torch.linalg.norm(xs)) < 1e-9
+
+
+def test_nopiv_register_kernel_matches_pivoting_kernel(monkeypatch):
+    """The circle16384 factor runs LQs of up to 128 rows and 129-256 columns
+    on the 64-lane register kernel.  Its specialization for factorizations
+    without pivoting (one barrier per step, no candidate search) must give
+    the same factor as the pivoting kernel run in its no-pivot mode: the
+    solves of two identical compressions agree bit for bit."""
+    cfg = W.CONFIGS["circle16384"]
+    pts = W.circle_points(cfg["n"], cfg["point_seed"])
+    A = W.device_kernel_matrix("log", pts, torch.float64, torch.device("cuda:0"))
+    b = torch.from_numpy(W.normal_rhs(cfg["n"], 3, 11)).cuda()
+    xs = []
+    for flag in ("0", "1"):
+        monkeypatch.setenv("HSS_REG_NOPIV", flag)
+        print(f"circle16384 factor, HSS_REG_NOPIV={flag}", flush=True)
+        h = P.hss_compress(A, rtol=cfg["rtol"], d0=cfg["d0"], dd=cfg["dd"], leaf_size=cfg["leaf"])
+        P.hss_factor(h)
+        xs.append(P.hss_solve(h, b))
+    assert torch.equal(xs[0], xs[1])
