@@ -287,6 +287,7 @@ __global__ __launch_bounds__(NTH) void lu_panel_reg_kernel(double* __restrict__ 
   __shared__ int s_p;
   __shared__ double xr[2][LW];
   __shared__ double ub[LW][64];
+  __shared__ double l11[LW][LW];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int j1 = j0 + nb;
   for (int c0 = j0; c0 < j1; c0 += LW) {
@@ -389,7 +390,7 @@ __global__ __launch_bounds__(NTH) void lu_panel_reg_kernel(double* __restrict__ 
       }
       __syncthreads();  // xr is rewritten by the next column
     }
-    // the sub-panel back to global memory
+    // the sub-panel back to global memory, and its unit-lower L11 into LDS
 #pragma unroll
     for (int k = 0; k < R; ++k) {
       const int r = j0 + tid + NTH * k;
@@ -397,33 +398,52 @@ __global__ __launch_bounds__(NTH) void lu_panel_reg_kernel(double* __restrict__ 
 #pragma unroll
         for (int q = 0; q < LW; ++q)
           if (q < w) A[(long long)r * ld + c0 + q] = a[k][q];
+      if (r >= c0 && r < c0 + w)
+#pragma unroll
+        for (int q = 0; q < LW; ++q) l11[r - c0][q] = a[k][q];
     }
     const int q0 = c0 + w, nr = j1 - q0;  // the panel's columns to the right
     if (nr <= 0) break;
     __syncthreads();
-    // U rows c0..c0+w-1 of those columns: unit-lower solve with L11, one column per thread
+    // U rows c0..c0+w-1 of those columns: unit-lower solve with L11, one
+    // column per thread, its w entries loaded together
     if (tid < nr) {
       const int q = q0 + tid;
-      for (int i = 0; i < w; ++i) {
-        double x = A[(long long)(c0 + i) * ld + q];
-        for (int k = 0; k < i; ++k) x = fma(-A[(long long)(c0 + i) * ld + c0 + k], ub[k][tid], x);
-        A[(long long)(c0 + i) * ld + q] = x;
-        ub[i][tid] = x;  // this thread's column: read back by it only until the barrier
+      double x[LW];
+#pragma unroll
+      for (int i = 0; i < LW; ++i) x[i] = i < w ? A[(long long)(c0 + i) * ld + q] : 0.0;
+#pragma unroll
+      for (int i = 0; i < LW; ++i) {
+#pragma unroll
+        for (int k = 0; k < i; ++k) x[i] = fma(-l11[i][k], x[k], x[i]);
+        if (i < w) {
+          A[(long long)(c0 + i) * ld + q] = x[i];
+          ub[i][tid] = x[i];
+        }
       }
     }
     __syncthreads();
-    // rows below: A[r][q] -= L[r][c0..c0+w) U[c0..c0+w)[q]
+    // rows below: A[r][q] -= L[r][c0..c0+w) U[c0..c0+w)[q], CH columns at a
+    // time with their loads in flight together (a column at a time, each
+    // load waited for the previous update)
+    constexpr int CH = R >= 4 ? 4 : 8;  // four rows per thread: registers
 #pragma unroll
     for (int k = 0; k < R; ++k) {
       const int r = j0 + tid + NTH * k;
       if (r >= q0 && r < n) {
-        double* ar = A + (long long)r * ld;
-        for (int t = 0; t < nr; ++t) {
-          double x = ar[q0 + t];
+        double* ar = A + (long long)r * ld + q0;
+        for (int t0 = 0; t0 < nr; t0 += CH) {
+          double x[CH];
 #pragma unroll
-          for (int i = 0; i < LW; ++i)
-            if (i < w) x = fma(-a[k][i], ub[i][t], x);
-          ar[q0 + t] = x;
+          for (int e = 0; e < CH; ++e) x[e] = t0 + e < nr ? ar[t0 + e] : 0.0;
+#pragma unroll
+          for (int e = 0; e < CH; ++e)
+#pragma unroll
+            for (int i = 0; i < LW; ++i)
+              if (i < w) x[e] = fma(-a[k][i], ub[i][t0 + e], x[e]);
+#pragma unroll
+          for (int e = 0; e < CH; ++e)
+            if (t0 + e < nr) ar[t0 + e] = x[e];
         }
       }
     }
