@@ -502,13 +502,17 @@ __device__ __forceinline__ void row16_sum_n(double (&v)[N]) {
   for (int c = 0; c < N; ++c) v[c] += dpp_d<0x140>(v[c]);  // row_mirror
 }
 
-template <int CG, int R16>
+// NOPIV: as for the 64-lane kernel, a launch of factorizations without
+// pivoting only: no candidates, the pivot column's norm formed by its row of
+// lanes, reflector buffers alternating by step, one barrier per step.
+template <int CG, int R16, bool NOPIV = false>
 __global__ __launch_bounds__(512) void qrcp_reg16_kernel(const DevProb* __restrict__ probs,
                                                         const int* __restrict__ list, double rtol, Work w) {
   constexpr int RW = 8, NC = 4 * RW * CG;  // wavefronts, columns held
   constexpr int SB = CG < 4 ? CG : 4;      // groups whose sums are taken together
   static_assert(CG % SB == 0, "whole sub-batches");
-  __shared__ double xcol[R16 * 16];
+  __shared__ double xcol[NOPIV ? 2 : 1][R16 * 16];
+  __shared__ double pn_s[2];
   __shared__ double nrm_s[NC];
   __shared__ int step_s[NC];
   __shared__ double red_v[RW];
@@ -542,17 +546,17 @@ __global__ __launch_bounds__(512) void qrcp_reg16_kernel(const DevProb* __restri
         s[gg] = fma(v, v, s[gg]);
       }
     }
-    row16_sum_n<SB>(s);
+    if constexpr (!NOPIV) row16_sum_n<SB>(s);
 #pragma unroll
     for (int gg = 0; gg < SB; ++gg) {
       const int j = 4 * ((g0 + gg) * RW + wave) + rq;
       if (j < m) {
-        const double nv = sqrt(s[gg]);
-        better(bv, bi, nv, j);
-        if (l16 == 0) {
-          nrm_s[j] = nv;
-          step_s[j] = -1;
+        if constexpr (!NOPIV) {
+          const double nv = sqrt(s[gg]);
+          better(bv, bi, nv, j);
+          if (l16 == 0) nrm_s[j] = nv;
         }
+        if (l16 == 0) step_s[j] = -1;
       }
     }
   }
@@ -560,6 +564,70 @@ __global__ __launch_bounds__(512) void qrcp_reg16_kernel(const DevProb* __restri
   const int kmax = dp.kmax;
   double nu0 = 0.0;
   int k = 0;
+  if constexpr (NOPIV) {
+    for (int i = 0; i < kmax; ++i) {
+      const int wp = (i >> 2) % RW, gp = (i >> 2) / RW, rp = i & 3, b = i & 1;
+      if (wave == wp && rq == rp) {  // the pivot column's row of lanes
+        double sn[1] = {0.0};
+#pragma unroll
+        for (int g = 0; g < CG; ++g)
+          if (g == gp) {
+#pragma unroll
+            for (int t = 0; t < R16; ++t) {
+              const int r = l16 + 16 * t;
+              xcol[b][r] = y[g][t];
+              if (r >= i && r < d) sn[0] = fma(y[g][t], y[g][t], sn[0]);
+            }
+          }
+        row16_sum_n<1>(sn);
+        if (l16 == 0) {
+          pn_s[b] = sqrt(sn[0]);
+          step_s[i] = i;
+        }
+      }
+      __syncthreads();
+      const double best = pn_s[b];
+      const double x0 = xcol[b][i];
+      const bool zero = !(best > 0.0);
+      const double alpha = zero ? 0.0 : -copysign(best, x0);
+      const double v0 = x0 - alpha;
+      const double tau = zero ? 0.0 : -v0 / alpha;
+      const double inv_v0 = zero ? 0.0 : 1.0 / v0;
+      double uu[R16];
+#pragma unroll
+      for (int t = 0; t < R16; ++t) {
+        const int r = l16 + 16 * t;
+        uu[t] = (r < d && r > i) ? xcol[b][r] * inv_v0 : (r == i ? 1.0 : 0.0);
+      }
+      if (tid == 0) {
+        w.alpha[dp.aoff + i] = alpha;
+        w.piv[dp.aoff + i] = i;
+      }
+      // the columns after the pivot, SB groups' sums at a time
+#pragma unroll
+      for (int g0 = 0; g0 < CG; g0 += SB) {
+        double f[SB];
+#pragma unroll
+        for (int gg = 0; gg < SB; ++gg) {
+          f[gg] = 0.0;
+#pragma unroll
+          for (int t = 0; t < R16; ++t) f[gg] = fma(uu[t], y[g0 + gg][t], f[gg]);
+        }
+        row16_sum_n<SB>(f);
+#pragma unroll
+        for (int gg = 0; gg < SB; ++gg) {
+          const int g = g0 + gg, j = 4 * (g * RW + wave) + rq;
+          const double fg = (j < m && j > i) ? tau * f[gg] : 0.0;
+#pragma unroll
+          for (int t = 0; t < R16; ++t) y[g][t] = fma(-fg, uu[t], y[g][t]);
+        }
+      }
+      k = i + 1;
+      // no closing barrier: the next step writes the other buffers, and the
+      // one after it these only once every wavefront has passed the next
+      // step's barrier
+    }
+  } else {
   for (int i = 0; i < kmax; ++i) {
     // candidates across the four rows of the wavefront, then across wavefronts
     better(bv, bi, __shfl_xor(bv, 16, 64), __shfl_xor(bi, 16, 64));
@@ -585,13 +653,13 @@ __global__ __launch_bounds__(512) void qrcp_reg16_kernel(const DevProb* __restri
       for (int g = 0; g < CG; ++g)
         if (g == gp) {
 #pragma unroll
-          for (int t = 0; t < R16; ++t) xcol[l16 + 16 * t] = y[g][t];
+          for (int t = 0; t < R16; ++t) xcol[0][l16 + 16 * t] = y[g][t];
           sel |= 1u << g;
         }
       if (l16 == 0) step_s[p] = i;
     }
     __syncthreads();
-    const double x0 = xcol[i];
+    const double x0 = xcol[0][i];
     const bool zero = !(best > 0.0);
     const double alpha = zero ? 0.0 : -copysign(best, x0);
     const double v0 = x0 - alpha;
@@ -601,7 +669,7 @@ __global__ __launch_bounds__(512) void qrcp_reg16_kernel(const DevProb* __restri
 #pragma unroll
     for (int t = 0; t < R16; ++t) {
       const int r = l16 + 16 * t;
-      uu[t] = (r < d && r > i) ? xcol[r] * inv_v0 : (r == i ? 1.0 : 0.0);
+      uu[t] = (r < d && r > i) ? xcol[0][r] * inv_v0 : (r == i ? 1.0 : 0.0);
     }
     if (tid == 0) {
       w.alpha[dp.aoff + i] = alpha;
@@ -651,6 +719,7 @@ __global__ __launch_bounds__(512) void qrcp_reg16_kernel(const DevProb* __restri
     // no closing barrier: xcol, red_v and nrm_s are written next only after
     // the next step's first barrier, which every thread reaches only once
     // done with this step
+  }
   }
   // write back the R data and the pivot steps; a pivot's own row (its
   // step) gets R_ii = alpha, which the step loop leaves out of the registers
@@ -1785,8 +1854,11 @@ hipError_t launch_id_factor(IdProblem* probs, int nprob, double rtol, void* work
       const char* nv = std::getenv("HSS_REG_NOPIV");
       bool nopiv_list = !(nv && nv[0] == '0');
       for (int q : L) nopiv_list = nopiv_list && probs[q].nfac > 0;
-#define QR_LAUNCH(G_, R_) \
-  hipLaunchKernelGGL((qrcp_reg16_kernel<G_, R_>), grid, dim3(512), 0, s, dprobs, dl, rtol, w)
+#define QR_LAUNCH(G_, R_)                                                                           \
+  if (nopiv_list)                                                                                   \
+    hipLaunchKernelGGL((qrcp_reg16_kernel<G_, R_, true>), grid, dim3(512), 0, s, dprobs, dl, rtol, w); \
+  else                                                                                              \
+    hipLaunchKernelGGL((qrcp_reg16_kernel<G_, R_>), grid, dim3(512), 0, s, dprobs, dl, rtol, w)
 #define QR_LAUNCH64(W_, C_, R_)                                                                        \
   if (nopiv_list)                                                                                      \
     hipLaunchKernelGGL((qrcp_reg_kernel<W_, C_, R_, true>), grid, dim3(W_ * 64), 0, s, dprobs, dl, rtol, w); \
