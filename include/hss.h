@@ -189,7 +189,13 @@ hss_status hss_matvec_batched(int nmat, const hss_handle* h, int nrhs, const dou
                               void* stream);
 
 /* ULV-like factorization of the HSS form (Alg. 3); root LU with partial
- * pivoting.  Host-synchronous. */
+ * pivoting.  The handle keeps the factors, and each node's reflectors also
+ * in compact WY form (a dense Y and the triangular T of each block of 64)
+ * for the solves: together a few n x leaf_size blocks of device memory.
+ * Host-synchronous.  A second call on a factored handle does nothing.
+ * Returns HSS_OK, HSS_ERR_ARG (NULL handle), HSS_ERR_STATE (not
+ * compressed), HSS_ERR_ALLOC, HSS_ERR_HIP or HSS_ERR_SINGULAR (a zero pivot
+ * in the root LU). */
 hss_status hss_factor(hss_handle h, void* stream);
 
 /* Solve A_HSS x = b after hss_factor (Alg. 4).  b, x: DEVICE n x nrhs
