@@ -146,7 +146,12 @@ hss_status apply_q_blocked(Handle& H, const std::vector<ReflDesc>& rd, hipStream
   for (const ReflDesc& d : rd)
     if (!d.transpose) return set_error(HSS_ERR_ARG, "apply_q_blocked: only the H_0 ... H_{r-1} v form");
   const size_t np = rd.size();
-  std::vector<long long> oy(np), ow1(np), ow2(np);
+  // W1 = Y_b^T v has at most 64 x nrhs entries but an inner dimension of up
+  // to m: above 2 KC it is split into KC-row parts, each its own product,
+  // whose results sum_partials adds in order (one workgroup per output tile
+  // took 100-175 us on the top levels of an N=32768 solve)
+  constexpr int KC = 256;
+  std::vector<long long> oy(np), ow1(np), ow2(np), opt(np);
   std::vector<int> nb(np), ob(np);
   long long tot = 0;
   int nbtot = 0, nbmax = 0, rmax = 0, mmax = 0;
@@ -158,6 +163,8 @@ hss_status apply_q_blocked(Handle& H, const std::vector<ReflDesc>& rd, hipStream
     tot += 64LL * d.nrhs;
     ow2[p] = tot;
     tot += 64LL * d.nrhs;
+    opt[p] = tot;
+    if (d.m > 2 * KC) tot += (long long)((d.m + KC - 1) / KC) * 64 * d.nrhs;
     nb[p] = (d.r + 63) / 64;
     ob[p] = nbtot;
     nbtot += nb[p];
@@ -208,6 +215,7 @@ hss_status apply_q_blocked(Handle& H, const std::vector<ReflDesc>& rd, hipStream
   }
   for (int step = 0; step < nbmax; ++step) {
     std::vector<GemmDesc> g1, g2, g3;
+    std::vector<SumDesc> sums;
     for (size_t p = 0; p < np; ++p) {
       if (step >= nb[p]) continue;
       const ReflDesc& d = rd[p];
@@ -217,18 +225,25 @@ hss_status apply_q_blocked(Handle& H, const std::vector<ReflDesc>& rd, hipStream
       double* vb = d.V + (long long)i0 * d.ldv;
       double* w1 = ws + ow1[p];
       double* w2 = ws + ow2[p];
-      GemmDesc g{};  // W1 = Y_b^T v
-      g.M = kb;
-      g.N = d.nrhs;
-      g.K = d.m - i0;
-      g.A = yb;
-      g.lda = d.r;
-      g.transA = 1;
-      g.B = seg(vb, d.ldv);
-      g.D = out(w1, d.nrhs);
-      g.alpha = 1.0;
-      g.beta = 0.0;
-      g1.push_back(g);
+      const int K = d.m - i0;
+      const int parts = K > 2 * KC ? (K + KC - 1) / KC : 1;
+      double* pt = ws + opt[p];
+      for (int q = 0; q < parts; ++q) {  // W1 = Y_b^T v, or its parts
+        const int k0 = q * KC;
+        GemmDesc g{};
+        g.M = kb;
+        g.N = d.nrhs;
+        g.K = parts > 1 ? std::min(KC, K - k0) : K;
+        g.A = yb + (long long)k0 * d.r;
+        g.lda = d.r;
+        g.transA = 1;
+        g.B = seg(vb + (long long)k0 * d.ldv, d.ldv);
+        g.D = out(parts > 1 ? pt + (long long)q * kb * d.nrhs : w1, d.nrhs);
+        g.alpha = 1.0;
+        g.beta = 0.0;
+        g1.push_back(g);
+      }
+      if (parts > 1) sums.push_back(SumDesc{pt, (long long)kb * d.nrhs, parts, kb, d.nrhs, w1, d.nrhs});
       GemmDesc t{};  // W2 = T_b W1
       t.M = kb;
       t.N = d.nrhs;
@@ -254,6 +269,7 @@ hss_status apply_q_blocked(Handle& H, const std::vector<ReflDesc>& rd, hipStream
       g3.push_back(u);
     }
     HIPCHK(launch_gemm_batched(g1.data(), (int)g1.size(), H.staging, s));
+    HIPCHK(launch_sum_partials(sums.data(), (int)sums.size(), H.staging, s));
     HIPCHK(launch_gemm_batched(g2.data(), (int)g2.size(), H.staging, s));
     HIPCHK(launch_gemm_batched(g3.data(), (int)g3.size(), H.staging, s));
   }

@@ -44,6 +44,14 @@ struct ReflYDesc {   // Y[q][i] = u_i[q] (m x r, ld r) from the rows of Z
   double* Y;
   int r, m;
 };
+struct SumDesc {     // out (rows x cols, ld ldo) = sum of parts partials (ld cols, stride apart)
+  const double* part;
+  long long stride;
+  int parts, rows, cols;
+  double* out;
+  long long ldo;
+};
+hipError_t launch_sum_partials(const SumDesc* d, int nd, Staging& st, hipStream_t s);
 struct LarftDesc {   // T (kb x kb, ld 64) of reflectors i0..i0+kb-1 from G = Y_b^T Y_b (ld 64)
   const double* G;
   const double* tau;  // tau of the block's first reflector

@@ -174,6 +174,20 @@ __global__ __launch_bounds__(NT) void refl_y_kernel(const ReflYDesc* __restrict_
   }
 }
 
+// out = the sum of `parts` partial products (rows x cols, ld cols, `stride`
+// apart), added in the order of the parts: the second stage of a product
+// whose long inner dimension was split over workgroups.  One thread per
+// output element; grid (element blocks, problems).
+__global__ __launch_bounds__(NT) void sum_partials_kernel(const SumDesc* __restrict__ d) {
+  const SumDesc g = d[blockIdx.y];
+  const int e = blockIdx.x * NT + threadIdx.x;
+  if (e >= g.rows * g.cols) return;
+  const int r = e / g.cols, c = e % g.cols;
+  double v = 0.0;
+  for (int q = 0; q < g.parts; ++q) v += g.part[q * g.stride + (long long)r * g.cols + c];
+  g.out[(long long)r * g.ldo + c] = v;
+}
+
 // Forward triangular factor of a block of kb reflectors, H_0 ... H_{kb-1} =
 // I - Y T Y^T: T[j][j] = tau_j, T[0:j, j] = -tau_j T[0:j, 0:j] G[0:j, j] with
 // G = Y^T Y.  One workgroup of 64 threads per block; thread l owns row l.
@@ -498,6 +512,16 @@ hipError_t launch_refl_y(const ReflYDesc* d, int nd, int rmax, int mmax, Staging
   if (!dd) return hipErrorOutOfMemory;
   const int tiles = ((mmax + 63) / 64) * ((rmax + 63) / 64);
   hipLaunchKernelGGL(refl_y_kernel, dim3(tiles, nd), dim3(NT), 0, s, dd);
+  return hipGetLastError();
+}
+
+hipError_t launch_sum_partials(const SumDesc* d, int nd, Staging& st, hipStream_t s) {
+  if (nd <= 0) return hipSuccess;
+  int emax = 1;
+  for (int i = 0; i < nd; ++i) emax = std::max(emax, d[i].rows * d[i].cols);
+  const SumDesc* dd = static_cast<const SumDesc*>(st.push(d, sizeof(SumDesc) * nd));
+  if (!dd) return hipErrorOutOfMemory;
+  hipLaunchKernelGGL(sum_partials_kernel, dim3((emax + NT - 1) / NT, nd), dim3(NT), 0, s, dd);
   return hipGetLastError();
 }
 
