@@ -76,6 +76,11 @@ struct TriJob {
 
 hss_status tri_solve_batch(const std::vector<TriJob>& jobs, bool lower, bool unit, Staging& st,
                            hipStream_t s) {
+  // right-looking: solve a diagonal block of 64, then update every row still
+  // to come with it (inner dimension <= 64, all those rows in one product).
+  // Taking the solved blocks into each new block instead (inner dimension
+  // growing to n, a 64 x nrhs output) left a few workgroups to run ever
+  // longer products: 10 to 50 us each in the root solve of an N=32768 matrix.
   int nmax = 0;
   for (const TriJob& j : jobs) nmax = std::max(nmax, j.n);
   const int nblk = (nmax + 63) / 64;
@@ -89,35 +94,6 @@ hss_status tri_solve_batch(const std::vector<TriJob>& jobs, bool lower, bool uni
       if (step >= nb_j || j.nrhs <= 0) continue;
       const int b = lower ? step : nb_j - 1 - step;
       const int b0 = b * 64, b1 = std::min(j.n, b0 + 64);
-      // update with the solved blocks
-      if (lower && b0 > 0) {
-        GemmDesc g{};
-        g.M = b1 - b0;
-        g.N = j.nrhs;
-        g.K = b0;
-        g.A = j.T + (long long)b0 * j.ldt;
-        g.lda = j.ldt;
-        g.B = seg(j.X, j.ldx);
-        g.C = seg(j.X + (long long)b0 * j.ldx, j.ldx);
-        g.D = out(j.X + (long long)b0 * j.ldx, j.ldx);
-        g.alpha = -1.0;
-        g.beta = 1.0;
-        gd.push_back(g);
-      }
-      if (!lower && b1 < j.n) {
-        GemmDesc g{};
-        g.M = b1 - b0;
-        g.N = j.nrhs;
-        g.K = j.n - b1;
-        g.A = j.T + (long long)b0 * j.ldt + b1;
-        g.lda = j.ldt;
-        g.B = seg(j.X + (long long)b1 * j.ldx, j.ldx);
-        g.C = seg(j.X + (long long)b0 * j.ldx, j.ldx);
-        g.D = out(j.X + (long long)b0 * j.ldx, j.ldx);
-        g.alpha = -1.0;
-        g.beta = 1.0;
-        gd.push_back(g);
-      }
       TriDesc t{};
       t.T = j.T + (long long)b0 * j.ldt + b0;
       t.ldt = j.ldt;
@@ -128,9 +104,25 @@ hss_status tri_solve_batch(const std::vector<TriJob>& jobs, bool lower, bool uni
       t.lower = lower ? 1 : 0;
       t.unit = unit ? 1 : 0;
       td.push_back(t);
+      // the rows still to come: below the block (lower) or above it (upper)
+      const int r0 = lower ? b1 : 0, r1 = lower ? j.n : b0;
+      if (r1 > r0) {
+        GemmDesc g{};
+        g.M = r1 - r0;
+        g.N = j.nrhs;
+        g.K = b1 - b0;
+        g.A = j.T + (long long)r0 * j.ldt + b0;
+        g.lda = j.ldt;
+        g.B = seg(j.X + (long long)b0 * j.ldx, j.ldx);
+        g.C = seg(j.X + (long long)r0 * j.ldx, j.ldx);
+        g.D = out(j.X + (long long)r0 * j.ldx, j.ldx);
+        g.alpha = -1.0;
+        g.beta = 1.0;
+        gd.push_back(g);
+      }
     }
-    HIPCHK(launch_gemm_batched(gd.data(), (int)gd.size(), st, s));
     HIPCHK(launch_tri_block(td.data(), (int)td.size(), st, s));
+    HIPCHK(launch_gemm_batched(gd.data(), (int)gd.size(), st, s));
   }
   return HSS_OK;
 }
