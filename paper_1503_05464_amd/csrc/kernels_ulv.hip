@@ -60,26 +60,28 @@ __global__ __launch_bounds__(NT) void vt_leaf_kernel(const VtLeafDesc* __restric
 // columns): lower: X = T^{-1} X with T lower triangular (unit diagonal if
 // unit); upper: likewise with T upper triangular.  One workgroup per problem
 // and block of NT right-hand-side columns (grid y); each thread owns one
-// column, all 64 rows of it in registers.  The LDS copy of T is padded to
-// 64 x 64 with the identity, so the padded rows solve to zero and the
+// column, all NB rows of it in registers.  The LDS copy of T is padded to
+// NB x NB with the identity, so the padded rows solve to zero and the
 // unrolled loops need no test against nb: with one, the compiler kept the
-// column in scratch memory.
+// column in scratch memory.  NB is 64, or 32 when every block of the launch
+// has at most 32 rows (the root LU's panels): half the steps and registers.
+template <int NB>
 __global__ __launch_bounds__(NT) void tri_block_kernel(const TriDesc* __restrict__ d) {
-  __shared__ double T[64][65];
+  __shared__ double T[NB][NB + 1];
   const TriDesc g = d[blockIdx.x];
   const int nb = g.nb;
   const int cbeg = blockIdx.y * NT;
   if (cbeg >= g.nrhs) return;
-  for (int e = threadIdx.x; e < 64 * 64; e += NT) {  // a unit diagonal is stored as 1: s / 1 = s exactly
-    const int r = e >> 6, c = e & 63;
+  for (int e = threadIdx.x; e < NB * NB; e += NT) {  // a unit diagonal is stored as 1: s / 1 = s exactly
+    const int r = e / NB, c = e % NB;
     T[r][c] = (r < nb && c < nb && !(g.unit && r == c)) ? g.T[(long long)r * g.ldt + c] : (r == c ? 1.0 : 0.0);
   }
   __syncthreads();
   const int col = cbeg + threadIdx.x;
   if (col >= g.nrhs) return;
-  double x[64];
+  double x[NB];
 #pragma unroll
-  for (int r = 0; r < 64; ++r) {  // rows past nb read row 0 and are zeroed
+  for (int r = 0; r < NB; ++r) {  // rows past nb read row 0 and are zeroed
     const double v = g.X[(long long)(r < nb ? r : 0) * g.ldx + col];
     x[r] = r < nb ? v : 0.0;
   }
@@ -87,21 +89,21 @@ __global__ __launch_bounds__(NT) void tri_block_kernel(const TriDesc* __restrict
   // independent of each other
   if (g.lower) {
 #pragma unroll
-    for (int c = 0; c < 64; ++c) {
+    for (int c = 0; c < NB; ++c) {
       x[c] = x[c] / T[c][c];
 #pragma unroll
-      for (int r = c + 1; r < 64; ++r) x[r] = fma(-T[r][c], x[c], x[r]);
+      for (int r = c + 1; r < NB; ++r) x[r] = fma(-T[r][c], x[c], x[r]);
     }
   } else {
 #pragma unroll
-    for (int c = 63; c >= 0; --c) {
+    for (int c = NB - 1; c >= 0; --c) {
       x[c] = x[c] / T[c][c];
 #pragma unroll
       for (int r = 0; r < c; ++r) x[r] = fma(-T[r][c], x[c], x[r]);
     }
   }
 #pragma unroll
-  for (int r = 0; r < 64; ++r)
+  for (int r = 0; r < NB; ++r)
     if (r < nb) g.X[(long long)r * g.ldx + col] = x[r];
 }
 
@@ -495,14 +497,19 @@ hipError_t launch_vt_leaf(const VtLeafDesc* d, int nd, int kmax, Staging& st, hi
 
 hipError_t launch_tri_block(const TriDesc* d, int nd, Staging& st, hipStream_t s) {
   if (nd <= 0) return hipSuccess;
-  int cmax = 1;
-  for (int i = 0; i < nd; ++i) cmax = d[i].nrhs > cmax ? d[i].nrhs : cmax;
+  int cmax = 1, nbmax = 1;
+  for (int i = 0; i < nd; ++i) {
+    cmax = d[i].nrhs > cmax ? d[i].nrhs : cmax;
+    nbmax = d[i].nb > nbmax ? d[i].nb : nbmax;
+  }
   const TriDesc* dd = static_cast<const TriDesc*>(st.push(d, sizeof(TriDesc) * nd));
   if (!dd) return hipErrorOutOfMemory;
   if (cmax <= kTriWaveMaxRhs)
     hipLaunchKernelGGL(tri_wave_kernel, dim3(nd, (cmax + 3) / 4), dim3(NT), 0, s, dd);
+  else if (nbmax <= 32)
+    hipLaunchKernelGGL(tri_block_kernel<32>, dim3(nd, (cmax + NT - 1) / NT), dim3(NT), 0, s, dd);
   else
-    hipLaunchKernelGGL(tri_block_kernel, dim3(nd, (cmax + NT - 1) / NT), dim3(NT), 0, s, dd);
+    hipLaunchKernelGGL(tri_block_kernel<64>, dim3(nd, (cmax + NT - 1) / NT), dim3(NT), 0, s, dd);
   return hipGetLastError();
 }
 
