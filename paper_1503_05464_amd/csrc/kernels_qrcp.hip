@@ -290,7 +290,7 @@ __global__ __launch_bounds__(RW * 64) void qrcp_reg_kernel(const DevProb* __rest
                                                           Work w) {
   __shared__ double xcol[NOPIV ? 2 : 1][RPL * 64];
   __shared__ double pn_s[2];
-  __shared__ double nrm_s[RW * CPW];
+  __shared__ double nrm_s[RW * CPW];  // squared norms: compared as they are, the winner's root taken
   __shared__ int step_s[RW * CPW];
   __shared__ double red_v[RW];
   __shared__ int red_i[RW];
@@ -315,7 +315,7 @@ __global__ __launch_bounds__(RW * 64) void qrcp_reg_kernel(const DevProb* __rest
     }
     if constexpr (!NOPIV) s = wave_sum(s);
     if (lane == 0 && j < m) {
-      if constexpr (!NOPIV) nrm_s[j] = sqrt(s);
+      if constexpr (!NOPIV) nrm_s[j] = s;
       step_s[j] = -1;
     }
   }
@@ -398,7 +398,7 @@ __global__ __launch_bounds__(RW * 64) void qrcp_reg_kernel(const DevProb* __rest
 #pragma unroll
     for (int q2 = 1; q2 < RW; ++q2) better(sb, sp, red_v[q2], red_i[q2]);
     const bool nopiv = P.nfac > 0;
-    const double best = nopiv ? nrm_s[i] : sb;
+    const double best = sqrt(nopiv ? nrm_s[i] : sb);
     const int p = nopiv ? i : sp;
     if (i == 0) nu0 = best;
     if (!nopiv && (best <= 0.0 || best <= rtol * nu0)) break;
@@ -456,7 +456,7 @@ __global__ __launch_bounds__(RW * 64) void qrcp_reg_kernel(const DevProb* __rest
         if (r > i && r < d) s = fma(v, v, s);
       }
       s = wave_sum(s);
-      if (lane == 0) nrm_s[j] = sqrt(s);
+      if (lane == 0) nrm_s[j] = s;
     }
     k = i + 1;
     __syncthreads();
@@ -552,9 +552,8 @@ __global__ __launch_bounds__(512) void qrcp_reg16_kernel(const DevProb* __restri
       const int j = 4 * ((g0 + gg) * RW + wave) + rq;
       if (j < m) {
         if constexpr (!NOPIV) {
-          const double nv = sqrt(s[gg]);
-          better(bv, bi, nv, j);
-          if (l16 == 0) nrm_s[j] = nv;
+          better(bv, bi, s[gg], j);  // squared norms: the winner's root is taken
+          if (l16 == 0) nrm_s[j] = s[gg];
         }
         if (l16 == 0) step_s[j] = -1;
       }
@@ -641,7 +640,7 @@ __global__ __launch_bounds__(512) void qrcp_reg16_kernel(const DevProb* __restri
     int sp = red_i[0];
 #pragma unroll
     for (int w2 = 1; w2 < RW; ++w2) better(sb, sp, red_v[w2], red_i[w2]);
-    const double best = nopiv ? nrm_s[i] : sb;
+    const double best = sqrt(nopiv ? nrm_s[i] : sb);
     const int p = nopiv ? i : sp;
     if (i == 0) nu0 = best;
     if (!nopiv && (best <= 0.0 || best <= rtol * nu0)) break;
@@ -709,9 +708,8 @@ __global__ __launch_bounds__(512) void qrcp_reg16_kernel(const DevProb* __restri
       for (int gg = 0; gg < SB; ++gg) {
         const int g = g0 + gg, j = 4 * (g * RW + wave) + rq;
         if (j < m && !((sel >> g) & 1u)) {
-          const double nv = sqrt(s2[gg]);
-          better(bv, bi, nv, j);
-          if (l16 == 0) nrm_s[j] = nv;
+          better(bv, bi, s2[gg], j);
+          if (l16 == 0) nrm_s[j] = s2[gg];
         }
       }
     }
