@@ -1051,7 +1051,7 @@ __global__ __launch_bounds__(PT) void qrcp_persist_kernel(const DevProb* __restr
       y[c][t] = v;
       s = fma(v, v, s);
     }
-    if (nopiv ? j == 0 : j < m) better(bv, bi, sqrt(wave_sum(s)), j);
+    if (nopiv ? j == 0 : j < m) better(bv, bi, wave_sum(s), j);  // squared norms throughout
     if (j < m && lane == 0) step[j] = -1;
     asm volatile("" ::: "memory");  // one column's loads in flight at a time
   }
@@ -1163,7 +1163,7 @@ __global__ __launch_bounds__(PT) void qrcp_persist_kernel(const DevProb* __restr
     int ix = gi_s[0];
 #pragma unroll
     for (int t = 1; t < PW; ++t) better(v, ix, gv_s[t], gi_s[t]);
-    best = v;
+    best = sqrt(v);  // records carry squared norms: the winner's root only
     p = ix;
     return s_ok != 0;
   };
@@ -1297,7 +1297,7 @@ __global__ __launch_bounds__(PT) void qrcp_persist_kernel(const DevProb* __restr
     bi = INT_MAX;
 #pragma unroll
     for (int c = 0; c < C; ++c)
-      if (nopiv ? jb + c == i + 1 : (!((sel >> c) & 1u) && jb + c < m)) better(bv, bi, sqrt(s2[c]), jb + c);
+      if (nopiv ? jb + c == i + 1 : (!((sel >> c) & 1u) && jb + c < m)) better(bv, bi, s2[c], jb + c);
     k = i + 1;
     if (i + 1 < dp.kmax) publish(i + 1);
   }
