@@ -398,7 +398,7 @@ __global__ __launch_bounds__(RW * 64) void qrcp_reg_kernel(const DevProb* __rest
 #pragma unroll
     for (int q2 = 1; q2 < RW; ++q2) better(sb, sp, red_v[q2], red_i[q2]);
     const bool nopiv = P.nfac > 0;
-    const double best = sqrt(nopiv ? nrm_s[i] : sb);
+    const double best = sqrt(fmax(nopiv ? nrm_s[i] : sb, 0.0));  // -1 (no candidate) stops as 0 would
     const int p = nopiv ? i : sp;
     if (i == 0) nu0 = best;
     if (!nopiv && (best <= 0.0 || best <= rtol * nu0)) break;
@@ -640,7 +640,7 @@ __global__ __launch_bounds__(512) void qrcp_reg16_kernel(const DevProb* __restri
     int sp = red_i[0];
 #pragma unroll
     for (int w2 = 1; w2 < RW; ++w2) better(sb, sp, red_v[w2], red_i[w2]);
-    const double best = sqrt(nopiv ? nrm_s[i] : sb);
+    const double best = sqrt(fmax(nopiv ? nrm_s[i] : sb, 0.0));  // -1 (no candidate) stops as 0 would
     const int p = nopiv ? i : sp;
     if (i == 0) nu0 = best;
     if (!nopiv && (best <= 0.0 || best <= rtol * nu0)) break;
@@ -1163,7 +1163,7 @@ __global__ __launch_bounds__(PT) void qrcp_persist_kernel(const DevProb* __restr
     int ix = gi_s[0];
 #pragma unroll
     for (int t = 1; t < PW; ++t) better(v, ix, gv_s[t], gi_s[t]);
-    best = sqrt(v);  // records carry squared norms: the winner's root only
+    best = sqrt(fmax(v, 0.0));  // squared norms in the records: the winner's root only
     p = ix;
     return s_ok != 0;
   };
