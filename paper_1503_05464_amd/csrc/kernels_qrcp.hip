@@ -1727,11 +1727,11 @@ static int small_resident(int c) {
         reinterpret_cast<const void*>(&qrcp_reg16_kernel<8, 4>),
         reinterpret_cast<const void*>(&qrcp_reg16_kernel<2, 8>),
         reinterpret_cast<const void*>(&qrcp_reg16_kernel<4, 8>),
-        reinterpret_cast<const void*>(&qrcp_reg_kernel<8, 32, 2>),
+        reinterpret_cast<const void*>(&qrcp_reg_kernel<16, 16, 2>),
         reinterpret_cast<const void*>(&qrcp_reg16_kernel<2, 12>),
         reinterpret_cast<const void*>(&qrcp_reg16_kernel<4, 12>),
-        reinterpret_cast<const void*>(&qrcp_reg_kernel<8, 32, 3>)};
-    const int waves[kSmallClasses] = {8, 8, 8, 8, 8, 8, 8, 8, 8, 8};
+        reinterpret_cast<const void*>(&qrcp_reg_kernel<16, 16, 3>)};
+    const int waves[kSmallClasses] = {8, 8, 8, 8, 8, 8, 16, 8, 8, 16};
     int dev = 0, cus = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
@@ -1865,7 +1865,8 @@ hipError_t launch_id_factor(IdProblem* probs, int nprob, double rtol, void* work
       // 16 lanes per column: (column groups, rows per lane) = 32 G columns,
       // 16 R rows; the two largest classes, whose 16-lane form would spill
       // registers inside the step loop, keep 64 lanes per column (W
-      // wavefronts, C columns per wavefront, R rows per lane)
+      // wavefronts, C columns per wavefront, R rows per lane), on 16
+      // wavefronts: each runs half as many columns' sum chains per step
       switch (c) {
         case 0: QR_LAUNCH(1, 4); break;
         case 1: QR_LAUNCH(2, 4); break;
@@ -1873,10 +1874,10 @@ hipError_t launch_id_factor(IdProblem* probs, int nprob, double rtol, void* work
         case 3: QR_LAUNCH(8, 4); break;
         case 4: QR_LAUNCH(2, 8); break;
         case 5: QR_LAUNCH(4, 8); break;
-        case 6: QR_LAUNCH64(8, 32, 2); break;
+        case 6: QR_LAUNCH64(16, 16, 2); break;
         case 7: QR_LAUNCH(2, 12); break;
         case 8: QR_LAUNCH(4, 12); break;
-        default: QR_LAUNCH64(8, 32, 3); break;
+        default: QR_LAUNCH64(16, 16, 3); break;
       }
 #undef QR_LAUNCH
 #undef QR_LAUNCH64
