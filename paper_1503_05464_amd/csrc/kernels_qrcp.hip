@@ -1363,8 +1363,12 @@ struct DiagDesc {
   long long wg0;
 };
 
+// NB: 64, or 32 / 16 when every block of the launch has at most that many
+// rows (low ranks): the padded steps add signed zeros only, so the result is
+// the same with fewer steps and registers.
+template <int NB>
 __global__ __launch_bounds__(NT) void trsm_diag_kernel(const DiagDesc* __restrict__ descs, int nd) {
-  __shared__ double Rt[64][65];
+  __shared__ double Rt[NB][NB + 1];
   int lo = 0, hi = nd - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
@@ -1373,10 +1377,10 @@ __global__ __launch_bounds__(NT) void trsm_diag_kernel(const DiagDesc* __restric
   }
   const DiagDesc g = descs[lo];
   const int nb = g.b1 - g.b0;
-  // padded to 64 x 64 with the identity: the padded entries solve to zero
+  // padded to NB x NB with the identity: the padded entries solve to zero
   // and the unrolled loops below need no test against nb
-  for (int e = threadIdx.x; e < 64 * 64; e += NT) {
-    const int bb = e >> 6, aa = e & 63;
+  for (int e = threadIdx.x; e < NB * NB; e += NT) {
+    const int bb = e / NB, aa = e % NB;
     Rt[bb][aa] = (bb < nb && aa <= bb)
                      ? g.W[(long long)g.perm[g.b0 + bb] * g.ldw + g.b0 + aa]
                      : (aa == bb ? 1.0 : 0.0);
@@ -1385,22 +1389,22 @@ __global__ __launch_bounds__(NT) void trsm_diag_kernel(const DiagDesc* __restric
   const int c = (int)(blockIdx.x - g.wg0) * NT + threadIdx.x;
   if (c >= g.nrest) return;
   double* x = g.E + (long long)c * g.k + g.b0;
-  double xv[64];
+  double xv[NB];
 #pragma unroll
-  for (int a = 0; a < 64; ++a) {  // entries past nb read entry 0 and are zeroed
+  for (int a = 0; a < NB; ++a) {  // entries past nb read entry 0 and are zeroed
     const double v = x[a < nb ? a : 0];
     xv[a] = a < nb ? v : 0.0;
   }
   // column by column, from the last: once x[b] is final, the updates of the
   // entries above it are independent of each other
 #pragma unroll
-  for (int b = 63; b >= 0; --b) {
+  for (int b = NB - 1; b >= 0; --b) {
     xv[b] = xv[b] / Rt[b][b];
 #pragma unroll
     for (int a = 0; a < b; ++a) xv[a] = fma(-xv[b], Rt[b][a], xv[a]);
   }
 #pragma unroll
-  for (int a = 0; a < 64; ++a)
+  for (int a = 0; a < NB; ++a)
     if (a < nb) x[a] = xv[a];
 }
 
@@ -2052,7 +2056,14 @@ hipError_t launch_id_finish(const IdProblem* probs, int nprob, const int* k_host
     if (e != hipSuccess) return e;
     const DiagDesc* ddev = static_cast<const DiagDesc*>(st.push(dd.data(), dd.size() * sizeof(DiagDesc)));
     if (!ddev) return hipErrorOutOfMemory;
-    hipLaunchKernelGGL(trsm_diag_kernel, dim3((unsigned)wg), dim3(NT), 0, s, ddev, (int)dd.size());
+    int nbmax = 1;
+    for (const DiagDesc& x : dd) nbmax = std::max(nbmax, x.b1 - x.b0);
+    if (nbmax <= 16)
+      hipLaunchKernelGGL(trsm_diag_kernel<16>, dim3((unsigned)wg), dim3(NT), 0, s, ddev, (int)dd.size());
+    else if (nbmax <= 32)
+      hipLaunchKernelGGL(trsm_diag_kernel<32>, dim3((unsigned)wg), dim3(NT), 0, s, ddev, (int)dd.size());
+    else
+      hipLaunchKernelGGL(trsm_diag_kernel<64>, dim3((unsigned)wg), dim3(NT), 0, s, ddev, (int)dd.size());
     e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
