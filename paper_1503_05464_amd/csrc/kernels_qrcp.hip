@@ -77,6 +77,8 @@ struct Work {
                             // workgroup and step, zeroed before each persistent launch
   long long rstride = 0;    // records per workgroup in a launch (its largest kmax): the
                             // records of workgroup g are rec[2 (g rstride + step) ...]
+  int rmask = 1;   // column slots per workgroup in a persistent launch, minus one (a power of two)
+  int xmask = 0;   // steps between full record exchanges, minus one: (rmask + 1) / 2 - 1
   int* err;        // 1: a wait for a candidate timed out (persistent path)
   int give_up = 0; // nonzero: every wait gives up at once (tests of the rerun)
   double* W;     // sum(m * d)
@@ -956,7 +958,7 @@ __global__ __launch_bounds__(ST) void id_step_kernel(const DevProb* __restrict__
 // wavefronts share each SIMD and every value lives in architectural
 // registers.  After each step the workgroup publishes its best remaining
 // column: norm and index go to a 16-byte record of its own for that step,
-// the values to a column slot of its own (double-buffered by step parity).
+// the values to a column slot of its own (a ring of 2, 4 or 8 slots by step).
 // Every workgroup of the problem waits for the G records of the step,
 // reduces the same candidates the same way, reads the winner's published
 // values as the reflector and updates its own columns.  Per step, global
@@ -1023,11 +1025,18 @@ __global__ __launch_bounds__(PT) void qrcp_persist_kernel(const DevProb* __restr
   const bool leader = ((int)blockIdx.x == dp.g0 && tid == 0);
   // no pivoting (Householder QR of the first nfac columns, the others only
   // transformed): step i's pivot is column i, the only candidate published.
-  // Every workgroup still publishes a record every step and waits for all
-  // of them: that exchange keeps the workgroups within one step of each
-  // other, which the double-buffered column slots need (an owner of
+  // Every workgroup still publishes a record every step.  With pivoting, or
+  // with two column slots per workgroup, every workgroup waits for all the
+  // records of every step: that exchange keeps the workgroups within one
+  // step of each other, which the double-buffered slots need (an owner of
   // consecutive columns would otherwise run ahead and overwrite a slot that
-  // a slower workgroup has yet to read).
+  // a slower workgroup has yet to read).  A launch of problems without
+  // pivoting may have R = 4 or 8 slots per workgroup (slot i mod R for step
+  // i); its workgroups then wait for all records only at steps that are
+  // multiples of R / 2, and at the other steps for the record of column i's
+  // owner alone.  A slot is written again R steps later, by a workgroup
+  // that has by then passed such a full exchange at a step between the
+  // two, so every workgroup has finished reading it.
   const bool nopiv = dp.p.nfac > 0;
   constexpr int CPG = PW * C;  // columns per workgroup
   const int jb = (blockIdx.x - dp.g0) * CPG + wave * C;
@@ -1085,7 +1094,7 @@ __global__ __launch_bounds__(PT) void qrcp_persist_kernel(const DevProb* __restr
     if (own) {
       // uniform bases and one 32-bit lane offset, formed here (not hoisted
       // out of the step loop as T live addresses)
-      const long long slot = (long long)(i & 1) * nslot + blockIdx.x;
+      const long long slot = (long long)(i & w.rmask) * nslot + blockIdx.x;
       char* blo = reinterpret_cast<char*>(w.cbuf + slot * 2 * ldcb);
       char* bhi = reinterpret_cast<char*>(w.cbuf + slot * 2 * ldcb + ldcb);
       unsigned vo = (unsigned)lane * 8u;
@@ -1126,7 +1135,13 @@ __global__ __launch_bounds__(PT) void qrcp_persist_kernel(const DevProb* __restr
       if (tid == 0) st_dev(w.err, 1);
       ok = false;
     }
-    for (int t = tid; t < dp.G && ok; t += PT) {
+    // without pivoting only the owner of column i has a candidate (every
+    // other record says none), so between full exchanges one thread waits
+    // for the owner's record alone; the reduction below gives the same pair
+    const bool full = !nopiv || (i & w.xmask) == 0;
+    const int t0 = full ? tid : (tid == 0 ? i / CPG : dp.G);
+    const int tstride = full ? PT : dp.G;
+    for (int t = t0; t < dp.G && ok; t += tstride) {
       int spins = 0;
       unsigned long long a, b;
       const unsigned long long* rt = recs + (long long)t * rs2;
@@ -1181,7 +1196,7 @@ __global__ __launch_bounds__(PT) void qrcp_persist_kernel(const DevProb* __restr
     if (!nopiv && (best <= 0.0 || best <= rtol * nu0)) break;
     if (!nopiv && dp.p.kfail >= 0 && i > dp.p.kfail && m > d) break;
     const int gp = p / CPG;  // the workgroup that published column p
-    const unsigned long long* xp = w.cbuf + ((long long)(i & 1) * nslot + dp.g0 + gp) * 2 * ldcb;
+    const unsigned long long* xp = w.cbuf + ((long long)(i & w.rmask) * nslot + dp.g0 + gp) * 2 * ldcb;
     // the winner's rows i..d-1 into LDS (zero elsewhere), loads in flight
     // together; a row whose words do not both carry this step's tag yet is
     // loaded again (bounded).  LDS receives the Householder vector
@@ -1645,16 +1660,31 @@ static hipError_t run_persistent(std::vector<DevProb>& h, const std::vector<int>
     int kb = 1;  // the launch's records: steps 0..kb-1 of nwg workgroups (kb apart), zeroed
     for (int q : batch) kb = std::max(kb, h[q].kmax);
     hipError_t e = hipMemsetAsync(w.rec, 0, (size_t)kb * nwg * 16, s);
-    // the launch's column slots (2 parities x nwg, two words per row): zero
-    // tags, so that nothing left by an earlier launch passes for this one's
-    if (e == hipSuccess) e = hipMemsetAsync(w.cbuf, 0, (size_t)2 * nwg * 2 * w.ldcb * 8, s);
+    // column slots per workgroup: 2, or for problems without pivoting as
+    // many as the workspace's 2 x nslots slots allow, up to 8
+    int rs = 2;
+    bool allnp = true;
+    for (int q : batch) allnp = allnp && h[q].p.nfac > 0;
+    if (const char* r2 = std::getenv("HSS_QRCP_RING2"))  // tests: the exchange at every step
+      if (r2[0] && r2[0] != '0') allnp = false;
+    while (allnp && rs < 8 && 2LL * rs * nwg <= 2 * w.nslots) rs *= 2;
+    // the launch's column slots (rs x nwg, two words per row): zero tags, so
+    // that nothing left by an earlier launch passes for this one's
+    if (e == hipSuccess) e = hipMemsetAsync(w.cbuf, 0, (size_t)rs * nwg * 2 * w.ldcb * 8, s);
     if (e == hipSuccess && done.empty()) e = hipMemsetAsync(w.err, 0, 4, s);
     if (e != hipSuccess) return e;
     Work wa = w;
     wa.rstride = kb;
+    wa.rmask = rs - 1;
+    wa.xmask = rs / 2 - 1;
     {
       const char* gu = std::getenv("HSS_QRCP_GIVE_UP");
       wa.give_up = (gu && gu[0] && gu[0] != '0') ? 1 : 0;
+    }
+    if (const char* vb = std::getenv("HSS_VERBOSE"); vb && vb[0] >= '2') {
+      std::fprintf(stderr, "[hss-id] persistent launch: %zu problems, %d workgroups, %d column slots each\n",
+                   batch.size(), nwg, rs);
+      std::fflush(stderr);
     }
     void* args[] = {(void*)&dprobs, (void*)&dwg, (void*)&rtol, (void*)&wa};
     e = hipLaunchKernel(pv.fn, dim3(nwg), dim3(PT), args, 0, s);

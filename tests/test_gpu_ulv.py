@@ -162,3 +162,36 @@ def test_nopiv_register_kernel_matches_pivoting_kernel(monkeypatch):
         P.hss_factor(h)
         xs.append(P.hss_solve(h, b))
     assert torch.equal(xs[0], xs[1])
+
+
+
+@pytest.mark.parametrize("n", [8192, 16384])
+def test_persistent_slot_ring_matches_exchange_every_step(n, monkeypatch, capfd):
+    """The ULV factor of a serving-mix matrix (3-D Gaussian kernel, BF16x3
+    sampling, leaves of 128, ranks up to 1024) runs its large QRs without
+    pivoting on the persistent kernel, with 4 or 8 column slots per
+    workgroup: the workgroups wait for every record only every 2 or 4 steps
+    and for the column owner's record in between.  Every other record says
+    "no candidate", so the factor must equal, bit for bit, the one whose
+    launches exchange all records at every step."""
+    pts = W.cube_points(n, 7)
+    A = W.device_kernel_matrix("gauss", pts[W.kd_order(pts, 128)], torch.float32, torch.device("cuda:0"))
+    b = torch.from_numpy(W.normal_rhs(n, 3, 5)).cuda()
+    monkeypatch.setenv("HSS_VERBOSE", "2")
+    xs, slots = [], []
+    for flag in ("1", "0"):
+        monkeypatch.setenv("HSS_QRCP_RING2", flag)
+        print(f"persistent ring: n={n}, HSS_QRCP_RING2={flag}", flush=True)
+        h = P.hss_compress(A, rtol=1e-6, d0=64, dd=32, d_max=1024, leaf_size=128, sample_prec="bf16x3",
+                           p_margin=32)
+        capfd.readouterr()
+        P.hss_factor(h)
+        err = capfd.readouterr().err
+        assert "persistent wait gave up" not in err
+        slots.append([int(l.split(" workgroups, ")[1].split(" ")[0]) for l in err.splitlines()
+                      if "persistent launch:" in l])
+        xs.append(P.hss_solve(h, b))
+    print(f"column slots per launch: {slots}", flush=True)
+    assert slots[0] and set(slots[0]) == {2}
+    assert slots[1] and max(slots[1]) >= 4
+    assert torch.equal(xs[0], xs[1])
